@@ -1,0 +1,168 @@
+/*
+ * vor.h -- C ABI of the MI355X projector-algorithm Voronoi/Delaunay library (libvor.so).
+ *
+ * The library computes, for n distinct integer point sites strictly inside an axis-aligned box
+ * X, every Voronoi cell of the diagram restricted to X (Section 2, definition of the Voronoi
+ * diagram; Section 3, Method 3.1; Section 4, Algorithm 1 with the endpoint method of Section 5
+ * and Appendix 1), stored as in Section 6, and the Delaunay graph read off the neighbour lists
+ * (Section 7).  Each cell is computed independently of the others (Theorem 9.1(d)).
+ *
+ * No C++ exception or torch type crosses this boundary.  Every function returns an int status
+ * (VOR_OK or a negative VOR_E_* code) unless noted.  Threading: vor_submit / vor_poll are
+ * thread-safe; vor_compute and vor_compute_batch serialise per context.
+ *
+ * Coordinates: int32, |coordinate| <= 2^30, box extent x1-x0 and y1-y0 at most 2^24.
+ * Sites must lie strictly inside X (x0 < x < x1, y0 < y < y1) and be pairwise distinct
+ * (problem statement in Section 2; a duplicate is an error, never silently dropped, since
+ * dropping it would renumber the sites).
+ */
+#ifndef VOR_H
+#define VOR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------------------------- */
+#define VOR_OK 0
+#define VOR_PENDING 1          /* vor_poll: ticket not finished yet                           */
+#define VOR_E_INVAL (-1)       /* null pointer, n == 0, empty or inverted box, bad argument   */
+#define VOR_E_DOMAIN (-2)      /* a site not strictly inside X, |coord| > 2^30, extent > 2^24  */
+#define VOR_E_DUPLICATE (-3)   /* two equal sites                                             */
+#define VOR_E_NOMEM (-4)       /* device memory or the HBM budget cannot hold the job         */
+#define VOR_E_DEVICE (-5)      /* a HIP runtime error                                         */
+#define VOR_E_TICKET (-6)      /* unknown or already consumed ticket                          */
+#define VOR_E_CAPACITY (-7)    /* a cell deeper than the exact pass supports (> 4096 lines)   */
+
+/* ---- side codes used in neighbour lists (Section 6: boundary lines get unique indices) ---- */
+#define VOR_SIDE_BOTTOM (-1)   /* y = y0 */
+#define VOR_SIDE_RIGHT (-2)    /* x = x1 */
+#define VOR_SIDE_TOP (-3)      /* y = y1 */
+#define VOR_SIDE_LEFT (-4)     /* x = x0 */
+
+/* ---- flags ------------------------------------------------------------------------------ */
+#define VOR_SET_DEVICE 0x1u       /* vor_set.x / .y are device pointers (HBM-resident input)  */
+#define VOR_RESULT_DEVICE 0x2u    /* opts: result arrays stay in device memory (owned by the
+                                     context, valid until the next call or vor_result_free)  */
+#define VOR_NO_VERTICES 0x4u      /* opts: do not write vertex rationals (vtx == NULL)         */
+#define VOR_CHECK_SYMMETRY 0x8u   /* opts: count asymmetric neighbour pairs into stats          */
+
+typedef struct vor_ctx vor_ctx;   /* opaque: device memory pools, streams, request loop */
+
+typedef struct {
+    int32_t x0, y0, x1, y1;       /* X = [x0, x1] x [y0, y1] */
+} vor_box;
+
+/* One point set in structure-of-arrays form.  Borrowed for the duration of vor_compute*,
+ * copied by vor_submit. */
+typedef struct {
+    uint32_t n;
+    const int32_t *x;
+    const int32_t *y;
+    vor_box box;
+    uint32_t flags;               /* VOR_SET_DEVICE */
+} vor_set;
+
+typedef enum {
+    VOR_EXACT_ONLY = 0,           /* every predicate in exact integer arithmetic            */
+    VOR_FP32_FILTERED = 1         /* FP32 filter with a stated error bound, exact fallback    */
+} vor_precision;
+
+typedef struct {
+    int device;                   /* HIP device ordinal                                       */
+    uint64_t hbm_budget_bytes;    /* admission budget of the request loop (0 = 3/4 of HBM)    */
+    int32_t precision;            /* vor_precision                                            */
+    uint32_t flags;               /* VOR_RESULT_DEVICE | VOR_NO_VERTICES | VOR_CHECK_SYMMETRY  */
+} vor_opts;
+
+/* Vertex in pair form: the point (X/d, Y/d), X and Y two's-complement 128-bit integers split
+ * into 64-bit halves, d > 0.  Not reduced by the gcd: X, Y, d are Cramer's rule applied to the
+ * two lines N.x <= c of the vertex in absolute coordinates (site line N = 2(p_j - p_k),
+ * c = |p_j|^2 - |p_k|^2; sides use their unit outward normal). */
+typedef struct {
+    uint64_t x_lo;
+    int64_t x_hi;
+    uint64_t y_lo;
+    int64_t y_hi;
+    int64_t d;
+} vor_rat;
+
+/* Work counters of one call (Theorem 9.1(b): rays, nodes of the algorithm tree and distance
+ * comparisons per cell). */
+typedef struct {
+    uint64_t rays;            /* rays shot (Lemma on shot rays: sum <= 11 n for a rectangle)  */
+    uint64_t nodes;           /* subedges classified (Lemma on tree nodes: <= 2 e_k per cell)  */
+    uint64_t evals;           /* candidate evaluations ("distance comparisons")              */
+    uint64_t exact_decisions; /* predicates the FP32 filter left to exact arithmetic          */
+    uint64_t deferred_cells;  /* cells moved from the filtered pass to the exact pass         */
+    uint64_t asym_pairs;      /* with VOR_CHECK_SYMMETRY: neighbour pairs seen one way only   */
+    uint64_t shells;          /* bucket shells scanned                                        */
+    uint64_t edges;           /* sum of e_k                                                   */
+} vor_stats;
+
+/* Result of one point set.  Host memory owned by the library (device memory with
+ * VOR_RESULT_DEVICE) until vor_result_free. */
+typedef struct {
+    uint32_t n;
+    const uint32_t *cell_off;  /* [n+1] CSR offsets into nbr / vtx                            */
+    const int32_t *nbr;        /* [cell_off[n]] per cell, CCW, lines that carry an edge of
+                                  positive length: site index 0..n-1 or a VOR_SIDE_* code;
+                                  rotated so the entry smallest as uint32 comes first         */
+    const vor_rat *vtx;        /* [cell_off[n]] vtx[i] = line(nbr[i]) ∩ line(nbr[i+1 cyclic]);
+                                  NULL with VOR_NO_VERTICES                                   */
+    uint64_t m;                /* Delaunay edges                                              */
+    const uint32_t *del;       /* [2m] pairs (i, j), i < j, lexicographically sorted          */
+    vor_stats stats;
+    float device_ms;           /* device time of the pipeline (HIP events)                     */
+    int32_t status;            /* VOR_OK, or the error of this set inside a batch             */
+} vor_result;
+
+/* Create a context on opts->device (NULL opts: device 0, FP32 filtered, host results). */
+int vor_create(const vor_opts *opts, vor_ctx **out);
+
+/* Destroy a context: pending tickets are cancelled, their results freed. */
+int vor_destroy(vor_ctx *ctx);
+
+/* Blocking: one point set -> *out (free with vor_result_free). */
+int vor_compute(vor_ctx *ctx, const vor_set *set, vor_result **out);
+
+/* Blocking: k independent point sets in one persistent launch per pipeline stage, the whole
+ * pipeline captured once as a HIP graph and replayed.  outs[i] receives set i's result (its
+ * status field carries a per-set error). */
+int vor_compute_batch(vor_ctx *ctx, const vor_set *sets, uint32_t k, vor_result **outs);
+
+/* Request loop: copy the set into library memory and enqueue it; returns immediately. */
+int vor_submit(vor_ctx *ctx, const vor_set *set, uint64_t *ticket);
+
+/* VOR_OK (and *out, ownership passes to the caller), VOR_PENDING, or the request's error. */
+int vor_poll(vor_ctx *ctx, uint64_t ticket, vor_result **out);
+
+/* Per-request latency stamps (seconds, monotonic clock): submit, admit, done. */
+int vor_ticket_times(vor_ctx *ctx, uint64_t ticket, double *t_submit, double *t_admit,
+                     double *t_done);
+
+void vor_result_free(vor_result *r);
+
+/* Static string for a status code (never NULL). */
+const char *vor_strerror(int status);
+
+/* Tuning knobs (chosen by the autotuner).  sites_per_bucket: target mean bucket occupancy
+ * of the uniform grid (Method 11.5); block: threads per workgroup of the cell kernel
+ * (64, 128 or 256). */
+typedef struct {
+    float sites_per_bucket;
+    int32_t block;
+} vor_tuning;
+
+int vor_set_tuning(vor_ctx *ctx, const vor_tuning *t);
+int vor_get_tuning(vor_ctx *ctx, vor_tuning *t);
+
+/* Version string of the library build (never NULL). */
+const char *vor_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VOR_H */

@@ -1,0 +1,310 @@
+"""ctypes binding of include/vor.h.  Argument marshalling only: every step of the path runs in
+the HIP library."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(HERE, "libvor.so")
+
+VOR_OK, VOR_PENDING = 0, 1
+VOR_E_INVAL, VOR_E_DOMAIN, VOR_E_DUPLICATE, VOR_E_NOMEM = -1, -2, -3, -4
+VOR_E_DEVICE, VOR_E_TICKET, VOR_E_CAPACITY = -5, -6, -7
+VOR_SET_DEVICE, VOR_RESULT_DEVICE, VOR_NO_VERTICES, VOR_CHECK_SYMMETRY = 0x1, 0x2, 0x4, 0x8
+VOR_EXACT_ONLY, VOR_FP32_FILTERED = 0, 1
+
+
+class vor_box(C.Structure):
+    _fields_ = [("x0", C.c_int32), ("y0", C.c_int32), ("x1", C.c_int32), ("y1", C.c_int32)]
+
+
+class vor_set(C.Structure):
+    _fields_ = [("n", C.c_uint32), ("x", C.c_void_p), ("y", C.c_void_p), ("box", vor_box),
+                ("flags", C.c_uint32)]
+
+
+class vor_opts(C.Structure):
+    _fields_ = [("device", C.c_int), ("hbm_budget_bytes", C.c_uint64), ("precision", C.c_int32),
+                ("flags", C.c_uint32)]
+
+
+class vor_rat(C.Structure):
+    _fields_ = [("x_lo", C.c_uint64), ("x_hi", C.c_int64), ("y_lo", C.c_uint64),
+                ("y_hi", C.c_int64), ("d", C.c_int64)]
+
+
+class vor_stats(C.Structure):
+    _fields_ = [(k, C.c_uint64) for k in ("rays", "nodes", "evals", "exact_decisions",
+                                           "deferred_cells", "asym_pairs", "shells", "edges")]
+
+
+class vor_result(C.Structure):
+    _fields_ = [("n", C.c_uint32), ("cell_off", C.c_void_p), ("nbr", C.c_void_p),
+                ("vtx", C.c_void_p), ("m", C.c_uint64), ("del_", C.c_void_p),
+                ("stats", vor_stats), ("device_ms", C.c_float), ("status", C.c_int32)]
+
+
+class vor_tuning(C.Structure):
+    _fields_ = [("sites_per_bucket", C.c_float), ("block", C.c_int32)]
+
+
+_lib = None
+
+
+def lib_path() -> str:
+    return _LIB_PATH
+
+
+def lib():
+    """Load libvor.so; raise if it is missing (no fallback path exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise ImportError(f"{_LIB_PATH} is not built: run __graft_entry__.build()")
+        L = C.CDLL(_LIB_PATH)
+        P = C.POINTER
+        L.vor_create.argtypes = [P(vor_opts), P(C.c_void_p)]
+        L.vor_destroy.argtypes = [C.c_void_p]
+        L.vor_compute.argtypes = [C.c_void_p, P(vor_set), P(P(vor_result))]
+        L.vor_compute_batch.argtypes = [C.c_void_p, P(vor_set), C.c_uint32, P(P(vor_result))]
+        L.vor_submit.argtypes = [C.c_void_p, P(vor_set), P(C.c_uint64)]
+        L.vor_poll.argtypes = [C.c_void_p, C.c_uint64, P(P(vor_result))]
+        L.vor_ticket_times.argtypes = [C.c_void_p, C.c_uint64, P(C.c_double), P(C.c_double),
+                                       P(C.c_double)]
+        L.vor_result_free.argtypes = [P(vor_result)]
+        L.vor_result_free.restype = None
+        L.vor_strerror.argtypes = [C.c_int]
+        L.vor_strerror.restype = C.c_char_p
+        L.vor_set_tuning.argtypes = [C.c_void_p, P(vor_tuning)]
+        L.vor_get_tuning.argtypes = [C.c_void_p, P(vor_tuning)]
+        L.vor_version.argtypes = []
+        L.vor_version.restype = C.c_char_p
+        for f in ("vor_create", "vor_destroy", "vor_compute", "vor_compute_batch", "vor_submit",
+                  "vor_poll", "vor_ticket_times", "vor_set_tuning", "vor_get_tuning"):
+            getattr(L, f).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+class VorError(RuntimeError):
+    def __init__(self, status: int, where: str = ""):
+        self.status = status
+        super().__init__(f"{where}: {vor_strerror(status)} ({status})")
+
+
+def vor_strerror(status: int) -> str:
+    return lib().vor_strerror(int(status)).decode()
+
+
+def vor_version() -> str:
+    return lib().vor_version().decode()
+
+
+def _check(rc: int, where: str) -> int:
+    if rc < 0:
+        raise VorError(rc, where)
+    return rc
+
+
+def vor_create(device: int = 0, precision: int = VOR_FP32_FILTERED, flags: int = 0,
+               hbm_budget_bytes: int = 0):
+    o = vor_opts(device, hbm_budget_bytes, precision, flags)
+    h = C.c_void_p()
+    _check(lib().vor_create(C.byref(o), C.byref(h)), "vor_create")
+    return h
+
+
+def vor_destroy(ctx) -> None:
+    _check(lib().vor_destroy(ctx), "vor_destroy")
+
+
+def _make_set(x, y, box, device_ptrs=False):
+    """x, y: int32 numpy arrays (host) or (ptr, ptr) device addresses with device_ptrs=True."""
+    if device_ptrs:
+        xp, yp, n = x[0], y[0], x[1]
+        return vor_set(n, xp, yp, vor_box(*box), VOR_SET_DEVICE), None
+    x = np.ascontiguousarray(x, dtype=np.int32)
+    y = np.ascontiguousarray(y, dtype=np.int32)
+    keep = (x, y)
+    return vor_set(x.shape[0], x.ctypes.data, y.ctypes.data, vor_box(*[int(v) for v in box]),
+                   0), keep
+
+
+@dataclass
+class Stats:
+    rays: int
+    nodes: int
+    evals: int
+    exact_decisions: int
+    deferred_cells: int
+    asym_pairs: int
+    shells: int
+    edges: int
+
+
+@dataclass
+class Result:
+    n: int
+    cell_off: np.ndarray        # uint32 [n+1]
+    nbr: np.ndarray             # int32
+    vtx: np.ndarray | None      # structured (x_lo, x_hi, y_lo, y_hi, d)
+    dele: np.ndarray            # uint32 [m, 2]
+    stats: Stats
+    device_ms: float
+    status: int
+
+    def lines(self, k: int) -> list:
+        return self.nbr[self.cell_off[k]:self.cell_off[k + 1]].tolist()
+
+    def vertices_int(self):
+        """Pair-form vertices as Python ints (X, Y, D) per entry."""
+        v = self.vtx
+        X = [int(h) * (1 << 64) + int(l) for l, h in zip(v["x_lo"], v["x_hi"])]
+        Y = [int(h) * (1 << 64) + int(l) for l, h in zip(v["y_lo"], v["y_hi"])]
+        return X, Y, [int(d) for d in v["d"]]
+
+
+_RAT = np.dtype([("x_lo", "<u8"), ("x_hi", "<i8"), ("y_lo", "<u8"), ("y_hi", "<i8"), ("d", "<i8")])
+
+
+def _to_result(rp) -> Result:
+    r = rp.contents
+    n = int(r.n)
+    st = Stats(*[int(getattr(r.stats, f)) for f, _ in vor_stats._fields_])
+    if r.status != VOR_OK or not r.cell_off:
+        return Result(n, np.zeros(0, np.uint32), np.zeros(0, np.int32), None,
+                      np.zeros((0, 2), np.uint32), st, float(r.device_ms), int(r.status))
+    off = np.ctypeslib.as_array(C.cast(r.cell_off, C.POINTER(C.c_uint32)), (n + 1,)).copy()
+    E = int(off[-1])
+    nbr = (np.ctypeslib.as_array(C.cast(r.nbr, C.POINTER(C.c_int32)), (E,)).copy()
+           if E else np.zeros(0, np.int32))
+    vtx = None
+    if r.vtx and E:
+        buf = (C.c_char * (E * _RAT.itemsize)).from_address(r.vtx)
+        vtx = np.frombuffer(bytes(buf), dtype=_RAT).copy()
+    m = int(r.m)
+    dele = (np.ctypeslib.as_array(C.cast(r.del_, C.POINTER(C.c_uint32)), (2 * m,)).copy()
+            .reshape(m, 2) if m else np.zeros((0, 2), np.uint32))
+    return Result(n, off, nbr, vtx, dele, st, float(r.device_ms), int(r.status))
+
+
+def vor_result_free(rp) -> None:
+    lib().vor_result_free(rp)
+
+
+def vor_compute(ctx, x, y, box, device_ptrs=False, keep_raw=False):
+    s, keep = _make_set(x, y, box, device_ptrs)
+    rp = C.POINTER(vor_result)()
+    _check(lib().vor_compute(ctx, C.byref(s), C.byref(rp)), "vor_compute")
+    if keep_raw:
+        return rp
+    try:
+        return _to_result(rp)
+    finally:
+        lib().vor_result_free(rp)
+
+
+def vor_compute_batch(ctx, sets):
+    """sets: list of (x, y, box).  Returns (status, [Result])."""
+    k = len(sets)
+    arr = (vor_set * k)()
+    keep = []
+    for i, (x, y, box) in enumerate(sets):
+        s, kp = _make_set(x, y, box)
+        arr[i] = s
+        keep.append(kp)
+    outs = (C.POINTER(vor_result) * k)()
+    rc = lib().vor_compute_batch(ctx, arr, k, outs)
+    if rc < 0 and not any(bool(o) for o in outs):
+        raise VorError(rc, "vor_compute_batch")
+    res = []
+    for o in outs:
+        if o:
+            res.append(_to_result(o))
+            lib().vor_result_free(o)
+        else:
+            res.append(None)
+    return rc, res
+
+
+def vor_submit(ctx, x, y, box) -> int:
+    s, keep = _make_set(x, y, box)
+    t = C.c_uint64()
+    _check(lib().vor_submit(ctx, C.byref(s), C.byref(t)), "vor_submit")
+    return int(t.value)
+
+
+def vor_poll(ctx, ticket: int):
+    """Returns (status, Result | None); status VOR_PENDING while running."""
+    rp = C.POINTER(vor_result)()
+    rc = lib().vor_poll(ctx, C.c_uint64(ticket), C.byref(rp))
+    if rc == VOR_OK:
+        try:
+            return rc, _to_result(rp)
+        finally:
+            lib().vor_result_free(rp)
+    return rc, None
+
+
+def vor_ticket_times(ctx, ticket: int):
+    a, b, c = C.c_double(), C.c_double(), C.c_double()
+    _check(lib().vor_ticket_times(ctx, C.c_uint64(ticket), C.byref(a), C.byref(b), C.byref(c)),
+           "vor_ticket_times")
+    return a.value, b.value, c.value
+
+
+def vor_set_tuning(ctx, sites_per_bucket: float, block: int) -> None:
+    t = vor_tuning(sites_per_bucket, block)
+    _check(lib().vor_set_tuning(ctx, C.byref(t)), "vor_set_tuning")
+
+
+def vor_get_tuning(ctx):
+    t = vor_tuning()
+    _check(lib().vor_get_tuning(ctx, C.byref(t)), "vor_get_tuning")
+    return float(t.sites_per_bucket), int(t.block)
+
+
+class Context:
+    """Owning wrapper: ``with Context() as ctx: ctx.compute(x, y, box)``."""
+
+    def __init__(self, device=0, precision=VOR_FP32_FILTERED, flags=0, hbm_budget_bytes=0):
+        self.h = vor_create(device, precision, flags, hbm_budget_bytes)
+
+    def compute(self, x, y, box, **kw):
+        return vor_compute(self.h, x, y, box, **kw)
+
+    def compute_batch(self, sets):
+        return vor_compute_batch(self.h, sets)
+
+    def submit(self, x, y, box):
+        return vor_submit(self.h, x, y, box)
+
+    def poll(self, ticket):
+        return vor_poll(self.h, ticket)
+
+    def times(self, ticket):
+        return vor_ticket_times(self.h, ticket)
+
+    def tune(self, sites_per_bucket, block):
+        vor_set_tuning(self.h, sites_per_bucket, block)
+
+    def close(self):
+        if self.h:
+            vor_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

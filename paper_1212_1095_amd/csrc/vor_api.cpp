@@ -1,0 +1,819 @@
+// vor_api.cpp -- host runtime behind include/vor.h: contexts, device workspaces, the
+// graph-captured pipeline, batched sets and the continuous-batching request loop.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstdlib>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "vor.h"
+#include "vor_device.hpp"
+#include "vor_internal.h"
+
+using namespace vor;
+
+namespace {
+
+double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t cap = 0;
+    hipError_t ensure(size_t bytes) {
+        if (bytes <= cap && p) return hipSuccess;
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        cap = 0;
+        size_t want = bytes < 256 ? 256 : bytes;
+        want += want / 8;   // headroom so slightly larger calls reuse the buffer
+        hipError_t e = hipMalloc(&p, want);
+        if (e == hipSuccess) cap = want;
+        return e;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        cap = 0;
+    }
+    template <class T> T *as() const { return (T *)p; }
+};
+
+struct HostBuf {   // pinned staging
+    void *p = nullptr;
+    size_t cap = 0;
+    hipError_t ensure(size_t bytes) {
+        if (bytes <= cap && p) return hipSuccess;
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        cap = 0;
+        size_t want = bytes < 256 ? 256 : bytes + bytes / 8;
+        hipError_t e = hipHostMalloc(&p, want, hipHostMallocDefault);
+        if (e == hipSuccess) cap = want;
+        return e;
+    }
+    void release() {
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        cap = 0;
+    }
+};
+
+enum BufId {
+    B_SETS, B_SETOFF, B_INX, B_INY, B_XYID, B_KEY, B_BCNT, B_BSTART, B_SXY, B_SID, B_OCNT,
+    B_OLINES, B_OVF, B_POOL, B_QUEUE, B_QUEUE2, B_WBUF, B_WBUF2, B_CELLOFF, B_NBR, B_VTX,
+    B_DCNT, B_DELOFF, B_DEL, B_SCANTMP, B_SMALL, B_STATS, B_COUNT
+};
+
+struct Workspace {
+    DevBuf b[B_COUNT];
+    HostBuf h_in, h_small;
+    hipStream_t stream = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+    PipeArgs gkey{};
+    bool have_graph = false;
+
+    hipError_t init() {
+        hipError_t e = hipStreamCreateWithFlags(&stream, hipStreamNonBlocking);
+        if (e != hipSuccess) return e;
+        if ((e = hipEventCreate(&ev0)) != hipSuccess) return e;
+        return hipEventCreate(&ev1);
+    }
+    void drop_graph() {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (graph) (void)hipGraphDestroy(graph);
+        gexec = nullptr;
+        graph = nullptr;
+        have_graph = false;
+    }
+    void destroy() {
+        if (stream) (void)hipStreamSynchronize(stream);
+        drop_graph();
+        for (auto &x : b) x.release();
+        h_in.release();
+        h_small.release();
+        if (ev0) (void)hipEventDestroy(ev0);
+        if (ev1) (void)hipEventDestroy(ev1);
+        if (stream) (void)hipStreamDestroy(stream);
+        stream = nullptr;
+    }
+};
+
+struct HostSet {   // validated description of one input set
+    uint32_t n;
+    const int32_t *x, *y;
+    vor_box box;
+    bool device;
+};
+
+int check_set(const vor_set *s) {
+    if (!s || s->n == 0 || !s->x || !s->y) return VOR_E_INVAL;
+    const vor_box &b = s->box;
+    if (!(b.x0 < b.x1 && b.y0 < b.y1)) return VOR_E_INVAL;
+    const long long lim = 1LL << 30;
+    if (b.x0 < -lim || b.y0 < -lim || b.x1 > lim || b.y1 > lim) return VOR_E_DOMAIN;
+    if ((long long)b.x1 - b.x0 > (1LL << 24) || (long long)b.y1 - b.y0 > (1LL << 24))
+        return VOR_E_DOMAIN;
+    if (s->n > (1u << 27)) return VOR_E_INVAL;
+    return VOR_OK;
+}
+
+// Uniform grid of Method 11.5 with about `rho` sites per square bucket.
+void choose_grid(const vor_box &b, uint32_t n, float rho, SetDesc &d) {
+    const double W = (double)b.x1 - b.x0, H = (double)b.y1 - b.y0;
+    double s = std::sqrt(W * H * (double)rho / (double)n);
+    long long si = (long long)std::ceil(s);
+    if (si < 1) si = 1;
+    long long gx = (long long)std::ceil(W / (double)si), gy = (long long)std::ceil(H / (double)si);
+    // keep the grid at most ~4 buckets per site
+    while (gx * gy > 4LL * n + 16) {
+        si *= 2;
+        gx = (long long)std::ceil(W / (double)si);
+        gy = (long long)std::ceil(H / (double)si);
+    }
+    d.s = (int32_t)si;
+    d.gx = (int32_t)std::max(1LL, gx);
+    d.gy = (int32_t)std::max(1LL, gy);
+}
+
+int map_status(int st) {
+    if (st & ST_DUP) return VOR_E_DUPLICATE;
+    if (st & ST_DOMAIN) return VOR_E_DOMAIN;
+    if (st & ST_CAPACITY) return VOR_E_CAPACITY;
+    if (st & ST_INTERNAL) return VOR_E_DEVICE;
+    return VOR_OK;
+}
+
+struct ResultBox {   // vor_result plus the storage it points to
+    vor_result r;
+    std::vector<uint32_t> off;
+    std::vector<int32_t> nbr;
+    std::vector<vor_rat> vtx;
+    std::vector<uint32_t> del;
+};
+
+vor_result *new_result(ResultBox *&box) {
+    box = new (std::nothrow) ResultBox();
+    if (!box) return nullptr;
+    std::memset(&box->r, 0, sizeof(box->r));
+    return &box->r;
+}
+
+// vor_result is the first member of ResultBox: vor_result_free converts the pointer back.
+
+}  // namespace
+
+struct Request {
+    uint64_t ticket;
+    std::vector<int32_t> x, y;
+    vor_box box;
+    double t_submit = 0, t_admit = 0, t_done = 0;
+    int status = VOR_PENDING;
+    vor_result *result = nullptr;
+    size_t footprint = 0;
+};
+
+struct vor_ctx {
+    int device = 0;
+    vor_opts opts{};
+    vor_tuning tune{1.0f, 256};
+    Workspace ws;            // vor_compute / vor_compute_batch
+    std::mutex mu;           // serialises vor_compute*
+    bool use_graph = true;
+    // request loop
+    Workspace rws[2];
+    std::mutex qmu;
+    std::condition_variable qcv;
+    std::deque<std::shared_ptr<Request>> pending;
+    std::map<uint64_t, std::shared_ptr<Request>> all;
+    uint64_t next_ticket = 1;
+    bool stop = false;
+    bool loop_started = false;
+    std::thread loop;
+    uint64_t budget = 0;
+};
+
+namespace {
+
+size_t footprint_bytes(uint64_t total, uint64_t gtot, bool vertices) {
+    const uint64_t E = 10 * total + 16;
+    size_t b = 0;
+    b += total * (4 + 4 + 8 + 4 + 8 + 4 + 4 + 4 + 4 + 4 + 4 + 4);   // inputs, grid, queues, counts
+    b += total * 4ull * KOUT;                                       // filtered-pass lines
+    b += E * 4 * 2;                                                 // pool + nbr
+    if (vertices) b += E * sizeof(vor_rat);
+    b += (3 * total + 8) * 8;                                       // delaunay
+    b += gtot * 8;
+    return b;
+}
+
+// Prepare descriptors, size the workspace and launch the pipeline on ws.stream.  Inputs are
+// either device pointers (single set, VOR_SET_DEVICE) or gathered into pinned staging and
+// copied.  Returns a VOR status; on success the launch is in flight.
+int launch(vor_ctx *ctx, Workspace &ws, const std::vector<HostSet> &sets, bool vertices,
+           bool exact_only, bool symmetry, bool use_graph, PipeArgs &a,
+           std::vector<SetDesc> &descs, std::vector<int> &set_off) {
+    const int K = (int)sets.size();
+    descs.resize(K);
+    set_off.assign(K + 1, 0);
+    long long total = 0, gtot = 0;
+    for (int i = 0; i < K; ++i) {
+        const HostSet &s = sets[i];
+        SetDesc &d = descs[i];
+        d.W = s.box.x1 - s.box.x0;
+        d.H = s.box.y1 - s.box.y0;
+        d.x0 = s.box.x0;
+        d.y0 = s.box.y0;
+        d.n = (int32_t)s.n;
+        d.site_off = (int32_t)total;
+        choose_grid(s.box, s.n, ctx->tune.sites_per_bucket, d);
+        d.bucket_off = (int32_t)gtot;
+        set_off[i] = (int)total;
+        total += s.n;
+        gtot += (long long)d.gx * d.gy;
+    }
+    set_off[K] = (int)total;
+    if (total >= (1LL << 30) || gtot >= (1LL << 30)) return VOR_E_NOMEM;
+    const long long T = total;
+    const long long E = 10 * T + 16;
+    const long long D = 3 * T + 8;
+    const int exact_blocks = (int)std::min<long long>(1024, std::max<long long>(1, (T + 63) / 64));
+    const long long stmp = scan_tmp_ints(std::max(T, gtot)) + 8;
+    struct Need { int id; size_t bytes; } need[] = {
+        {B_SETS, sizeof(SetDesc) * K}, {B_SETOFF, 4ull * (K + 1)}, {B_INX, 4ull * T},
+        {B_INY, 4ull * T}, {B_XYID, 8ull * T}, {B_KEY, 4ull * T}, {B_BCNT, 4ull * gtot},
+        {B_BSTART, 4ull * (gtot + 1)}, {B_SXY, 8ull * T}, {B_SID, 4ull * T},
+        {B_OCNT, 4ull * T}, {B_OLINES, 4ull * KOUT * T}, {B_OVF, 4ull * T}, {B_POOL, 4ull * E},
+        {B_QUEUE, 4ull * T}, {B_QUEUE2, 4ull * T},
+        {B_WBUF, 4ull * 2 * DCAP1 * 64 * exact_blocks}, {B_WBUF2, 4ull * 2 * DCAP2 * 64 * DEEP_BLOCKS},
+        {B_CELLOFF, 4ull * (T + 1)}, {B_NBR, 4ull * E},
+        {B_VTX, vertices ? sizeof(vor_rat) * E : 16}, {B_DCNT, 4ull * T},
+        {B_DELOFF, 4ull * (T + 1)}, {B_DEL, 8ull * D}, {B_SCANTMP, 4ull * stmp},
+        {B_SMALL, 4ull * SMALL_INTS}, {B_STATS, 8ull * SL_COUNT}};
+    bool grew = false;
+    for (auto &q : need) {
+        const size_t before = ws.b[q.id].cap;
+        const void *pb = ws.b[q.id].p;
+        if (ws.b[q.id].ensure(q.bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return VOR_E_NOMEM;
+        }
+        grew |= (ws.b[q.id].cap != before) || (ws.b[q.id].p != pb);
+    }
+    if (grew) ws.drop_graph();
+    // inputs
+    const bool dev_in = (K == 1 && sets[0].device);
+    const int *in_x, *in_y;
+    hipError_t e;
+    if (dev_in) {
+        in_x = sets[0].x;
+        in_y = sets[0].y;
+    } else {
+        if (ws.h_in.ensure(8ull * T) != hipSuccess) return VOR_E_NOMEM;
+        int32_t *hx = (int32_t *)ws.h_in.p, *hy = hx + T;
+        for (int i = 0; i < K; ++i) {
+            std::memcpy(hx + set_off[i], sets[i].x, 4ull * sets[i].n);
+            std::memcpy(hy + set_off[i], sets[i].y, 4ull * sets[i].n);
+        }
+        e = hipMemcpyAsync(ws.b[B_INX].p, hx, 4ull * T, hipMemcpyHostToDevice, ws.stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(ws.b[B_INY].p, hy, 4ull * T, hipMemcpyHostToDevice, ws.stream);
+        if (e != hipSuccess) return VOR_E_DEVICE;
+        in_x = ws.b[B_INX].as<int>();
+        in_y = ws.b[B_INY].as<int>();
+    }
+    e = hipMemcpyAsync(ws.b[B_SETS].p, descs.data(), sizeof(SetDesc) * K, hipMemcpyHostToDevice,
+                       ws.stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(ws.b[B_SETOFF].p, set_off.data(), 4ull * (K + 1),
+                           hipMemcpyHostToDevice, ws.stream);
+    if (e != hipSuccess) return VOR_E_DEVICE;
+
+    std::memset(&a, 0, sizeof(a));
+    a.sets = ws.b[B_SETS].as<SetDesc>();
+    a.nsets = K;
+    a.set_off = ws.b[B_SETOFF].as<int>();
+    a.total = (int)T;
+    a.gtot = gtot;
+    a.in_x = in_x;
+    a.in_y = in_y;
+    a.xyid = ws.b[B_XYID].as<int2>();
+    a.key = ws.b[B_KEY].as<int>();
+    a.bcnt = ws.b[B_BCNT].as<int>();
+    a.bstart = ws.b[B_BSTART].as<int>();
+    a.sxy = ws.b[B_SXY].as<float2>();
+    a.sid = ws.b[B_SID].as<int>();
+    a.ocnt = ws.b[B_OCNT].as<int>();
+    a.olines = ws.b[B_OLINES].as<int>();
+    a.ovf = ws.b[B_OVF].as<int>();
+    a.pool = ws.b[B_POOL].as<int>();
+    a.poolcap = E;
+    a.queue = ws.b[B_QUEUE].as<int>();
+    a.queue2 = ws.b[B_QUEUE2].as<int>();
+    a.wbuf = ws.b[B_WBUF].as<int>();
+    a.wbuf2 = ws.b[B_WBUF2].as<int>();
+    a.exact_blocks = exact_blocks;
+    a.cell_off = ws.b[B_CELLOFF].as<int>();
+    a.nbr = ws.b[B_NBR].as<int>();
+    a.nbr_cap = E;
+    a.vtx = ws.b[B_VTX].p;
+    a.dcnt = ws.b[B_DCNT].as<int>();
+    a.del_off = ws.b[B_DELOFF].as<int>();
+    a.del = ws.b[B_DEL].as<unsigned>();
+    a.del_cap = D;
+    a.scan_tmp = ws.b[B_SCANTMP].as<int>();
+    a.small = ws.b[B_SMALL].as<int>();
+    a.stats = ws.b[B_STATS].as<unsigned long long>();
+    a.block = ctx->tune.block;
+    a.exact_only = exact_only;
+    a.with_vertices = vertices;
+    a.check_symmetry = symmetry;
+
+    if ((e = hipEventRecord(ws.ev0, ws.stream)) != hipSuccess) return VOR_E_DEVICE;
+    if (use_graph) {
+        if (!ws.have_graph || std::memcmp(&ws.gkey, &a, sizeof(a)) != 0) {
+            ws.drop_graph();
+            e = hipStreamBeginCapture(ws.stream, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) return VOR_E_DEVICE;
+            launch_pipeline(a, ws.stream);
+            e = hipStreamEndCapture(ws.stream, &ws.graph);
+            if (e != hipSuccess) return VOR_E_DEVICE;
+            e = hipGraphInstantiate(&ws.gexec, ws.graph, nullptr, nullptr, 0);
+            if (e != hipSuccess) return VOR_E_DEVICE;
+            ws.gkey = a;
+            ws.have_graph = true;
+        }
+        if ((e = hipGraphLaunch(ws.gexec, ws.stream)) != hipSuccess) return VOR_E_DEVICE;
+    } else {
+        launch_pipeline(a, ws.stream);
+        if ((e = hipGetLastError()) != hipSuccess) return VOR_E_DEVICE;
+    }
+    if ((e = hipEventRecord(ws.ev1, ws.stream)) != hipSuccess) return VOR_E_DEVICE;
+    // small summary: status words, stats, totals
+    if (ws.h_small.ensure(4 * SMALL_INTS + 8 * SL_COUNT + 16) != hipSuccess) return VOR_E_NOMEM;
+    char *hs = (char *)ws.h_small.p;
+    e = hipMemcpyAsync(hs, a.small, 4 * SMALL_INTS, hipMemcpyDeviceToHost, ws.stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(hs + 4 * SMALL_INTS, a.stats, 8 * SL_COUNT, hipMemcpyDeviceToHost,
+                           ws.stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(hs + 4 * SMALL_INTS + 8 * SL_COUNT, a.cell_off + T, 4,
+                           hipMemcpyDeviceToHost, ws.stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(hs + 4 * SMALL_INTS + 8 * SL_COUNT + 4, a.del_off + T, 4,
+                           hipMemcpyDeviceToHost, ws.stream);
+    return e == hipSuccess ? VOR_OK : VOR_E_DEVICE;
+}
+
+struct Summary {
+    int status;
+    unsigned long long stats[SL_COUNT];
+    long long edges, dels;
+    float ms;
+};
+
+Summary read_summary(Workspace &ws) {
+    Summary s;
+    const char *hs = (const char *)ws.h_small.p;
+    const int *sm = (const int *)hs;
+    s.status = sm[0];
+    std::memcpy(s.stats, hs + 4 * SMALL_INTS, 8 * SL_COUNT);
+    s.edges = *(const int *)(hs + 4 * SMALL_INTS + 8 * SL_COUNT);
+    s.dels = *(const int *)(hs + 4 * SMALL_INTS + 8 * SL_COUNT + 4);
+    s.ms = 0.0f;
+    (void)hipEventElapsedTime(&s.ms, ws.ev0, ws.ev1);
+    return s;
+}
+
+void fill_stats(vor_stats &st, const Summary &s) {
+    st.rays = s.stats[SL_RAYS];
+    st.nodes = s.stats[SL_NODES];
+    st.evals = s.stats[SL_EVALS];
+    st.exact_decisions = s.stats[SL_EXACT];
+    st.deferred_cells = s.stats[SL_DEFERRED];
+    st.asym_pairs = s.stats[SL_ASYM];
+    st.shells = s.stats[SL_SHELLS];
+    st.edges = s.stats[SL_EDGES];
+}
+
+// Copy the results of every set back to host ResultBoxes (after the stream is idle).
+int collect_host(Workspace &ws, const PipeArgs &a, const std::vector<SetDesc> &descs,
+                 const Summary &sm, bool vertices, std::vector<vor_result *> &outs) {
+    const long long T = a.total;
+    std::vector<int> off(T + 1), doff(T + 1);
+    std::vector<int> nbr(sm.edges);
+    std::vector<vor_rat> vtx(vertices ? sm.edges : 0);
+    std::vector<uint32_t> del(2 * sm.dels);
+    hipError_t e = hipMemcpy(off.data(), a.cell_off, 4ull * (T + 1), hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(doff.data(), a.del_off, 4ull * (T + 1), hipMemcpyDeviceToHost);
+    if (e == hipSuccess && sm.edges)
+        e = hipMemcpy(nbr.data(), a.nbr, 4ull * sm.edges, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && vertices && sm.edges)
+        e = hipMemcpy(vtx.data(), a.vtx, sizeof(vor_rat) * sm.edges, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && sm.dels)
+        e = hipMemcpy(del.data(), a.del, 8ull * sm.dels, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return VOR_E_DEVICE;
+    const int K = (int)descs.size();
+    outs.assign(K, nullptr);
+    for (int i = 0; i < K; ++i) {
+        ResultBox *box;
+        vor_result *r = new_result(box);
+        if (!r) return VOR_E_NOMEM;
+        const int so = descs[i].site_off, n = descs[i].n;
+        const int e0 = off[so], e1 = off[so + n];
+        box->off.resize(n + 1);
+        for (int t = 0; t <= n; ++t) box->off[t] = (uint32_t)(off[so + t] - e0);
+        box->nbr.assign(nbr.begin() + e0, nbr.begin() + e1);
+        if (vertices) box->vtx.assign(vtx.begin() + e0, vtx.begin() + e1);
+        const int d0 = doff[so], d1 = doff[so + n];
+        box->del.assign(del.begin() + 2ll * d0, del.begin() + 2ll * d1);
+        r->n = (uint32_t)n;
+        r->cell_off = box->off.data();
+        r->nbr = box->nbr.data();
+        r->vtx = vertices ? box->vtx.data() : nullptr;
+        r->m = (uint64_t)(d1 - d0);
+        r->del = box->del.data();
+        fill_stats(r->stats, sm);
+        r->device_ms = sm.ms;
+        r->status = VOR_OK;
+        outs[i] = r;
+    }
+    return VOR_OK;
+}
+
+int run_sync(vor_ctx *ctx, Workspace &ws, const std::vector<HostSet> &sets,
+             std::vector<vor_result *> &outs, bool device_result) {
+    const bool vertices = !(ctx->opts.flags & VOR_NO_VERTICES);
+    const bool exact_only = ctx->opts.precision == VOR_EXACT_ONLY;
+    const bool sym = (ctx->opts.flags & VOR_CHECK_SYMMETRY) != 0;
+    PipeArgs a;
+    std::vector<SetDesc> descs;
+    std::vector<int> set_off;
+    int rc = launch(ctx, ws, sets, vertices, exact_only, sym, ctx->use_graph, a, descs, set_off);
+    if (rc != VOR_OK) {
+        (void)hipStreamSynchronize(ws.stream);
+        return rc;
+    }
+    if (hipStreamSynchronize(ws.stream) != hipSuccess) return VOR_E_DEVICE;
+    Summary sm = read_summary(ws);
+    rc = map_status(sm.status);
+    if (rc != VOR_OK) return rc;
+    if (device_result) {
+        ResultBox *box;
+        vor_result *r = new_result(box);
+        if (!r) return VOR_E_NOMEM;
+        r->n = sets[0].n;
+        r->cell_off = (const uint32_t *)a.cell_off;
+        r->nbr = a.nbr;
+        r->vtx = vertices ? (const vor_rat *)a.vtx : nullptr;
+        r->m = (uint64_t)sm.dels;
+        r->del = a.del;
+        fill_stats(r->stats, sm);
+        r->device_ms = sm.ms;
+        r->status = VOR_OK;
+        outs.assign(1, r);
+        return VOR_OK;
+    }
+    return collect_host(ws, a, descs, sm, vertices, outs);
+}
+
+// ------------------------------------------------------------------------------ request loop
+void request_loop(vor_ctx *ctx) {
+    (void)hipSetDevice(ctx->device);
+    struct InFlight {
+        std::vector<std::shared_ptr<Request>> reqs;
+        PipeArgs a;
+        std::vector<SetDesc> descs;
+        std::vector<int> set_off;
+        bool busy = false;
+    } fl[2];
+    const bool vertices = !(ctx->opts.flags & VOR_NO_VERTICES);
+    const bool exact_only = ctx->opts.precision == VOR_EXACT_ONLY;
+    for (;;) {
+        bool did = false;
+        // completions
+        for (int w = 0; w < 2; ++w) {
+            if (!fl[w].busy) continue;
+            const hipError_t q = hipStreamQuery(ctx->rws[w].stream);
+            if (q == hipErrorNotReady) continue;
+            did = true;
+            fl[w].busy = false;
+            std::vector<vor_result *> outs;
+            int rc = q == hipSuccess ? VOR_OK : VOR_E_DEVICE;
+            Summary sm{};
+            if (rc == VOR_OK) {
+                sm = read_summary(ctx->rws[w]);
+                rc = map_status(sm.status);
+            }
+            if (rc == VOR_OK)
+                rc = collect_host(ctx->rws[w], fl[w].a, fl[w].descs, sm, vertices, outs);
+            if (rc != VOR_OK && rc != VOR_E_DEVICE && fl[w].reqs.size() > 1) {
+                // an input error of one request: re-run each alone so the others succeed
+                std::lock_guard<std::mutex> lk(ctx->qmu);
+                for (auto it = fl[w].reqs.rbegin(); it != fl[w].reqs.rend(); ++it) {
+                    (*it)->footprint |= (size_t)1 << 62;   // marks "run alone"
+                    ctx->pending.push_front(*it);
+                }
+                continue;
+            }
+            const double t = now_s();
+            std::lock_guard<std::mutex> lk(ctx->qmu);
+            for (size_t i = 0; i < fl[w].reqs.size(); ++i) {
+                Request &r = *fl[w].reqs[i];
+                r.t_done = t;
+                if (rc == VOR_OK) {
+                    r.result = outs[i];
+                    r.status = VOR_OK;
+                } else {
+                    r.status = rc;
+                }
+            }
+        }
+        // admissions
+        for (int w = 0; w < 2; ++w) {
+            if (fl[w].busy) continue;
+            std::vector<std::shared_ptr<Request>> take;
+            {
+                std::lock_guard<std::mutex> lk(ctx->qmu);
+                if (ctx->stop) break;
+                size_t used = 0;
+                const size_t cap = ctx->budget / 2;
+                while (!ctx->pending.empty()) {
+                    auto &r = ctx->pending.front();
+                    const bool alone = (r->footprint >> 62) & 1;
+                    const size_t fp = r->footprint & (((size_t)1 << 62) - 1);
+                    if (!take.empty() && (alone || used + fp > cap)) break;
+                    if (take.empty() && fp > ctx->budget) {
+                        r->status = VOR_E_NOMEM;
+                        r->t_done = now_s();
+                        ctx->pending.pop_front();
+                        continue;
+                    }
+                    take.push_back(r);
+                    used += fp;
+                    ctx->pending.pop_front();
+                    if (alone) break;
+                }
+            }
+            if (take.empty()) continue;
+            did = true;
+            std::vector<HostSet> sets;
+            const double t = now_s();
+            for (auto &r : take) {
+                r->t_admit = t;
+                sets.push_back(HostSet{(uint32_t)r->x.size(), r->x.data(), r->y.data(), r->box, false});
+            }
+            fl[w].reqs = take;
+            int rc = launch(ctx, ctx->rws[w], sets, vertices, exact_only, false, ctx->use_graph,
+                            fl[w].a, fl[w].descs, fl[w].set_off);
+            if (rc != VOR_OK) {
+                (void)hipStreamSynchronize(ctx->rws[w].stream);
+                std::lock_guard<std::mutex> lk(ctx->qmu);
+                for (auto &r : take) {
+                    r->status = rc;
+                    r->t_done = now_s();
+                }
+                continue;
+            }
+            fl[w].busy = true;
+        }
+        {
+            std::unique_lock<std::mutex> lk(ctx->qmu);
+            if (ctx->stop && !fl[0].busy && !fl[1].busy) break;
+            if (!did) {
+                if (fl[0].busy || fl[1].busy)
+                    ctx->qcv.wait_for(lk, std::chrono::microseconds(100));
+                else
+                    ctx->qcv.wait_for(lk, std::chrono::milliseconds(20),
+                                      [&] { return ctx->stop || !ctx->pending.empty(); });
+            }
+        }
+    }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------------ C ABI
+extern "C" {
+
+const char *vor_version(void) { return "vor-mi355x 0.1 (gfx950)"; }
+
+const char *vor_strerror(int s) {
+    switch (s) {
+    case VOR_OK: return "ok";
+    case VOR_PENDING: return "pending";
+    case VOR_E_INVAL: return "invalid argument";
+    case VOR_E_DOMAIN: return "site not strictly inside the box, or box out of range";
+    case VOR_E_DUPLICATE: return "duplicate sites";
+    case VOR_E_NOMEM: return "out of device memory / HBM budget";
+    case VOR_E_DEVICE: return "HIP device error";
+    case VOR_E_TICKET: return "unknown or consumed ticket";
+    case VOR_E_CAPACITY: return "cell deeper than the supported capacity";
+    default: return "unknown status";
+    }
+}
+
+int vor_create(const vor_opts *opts, vor_ctx **out) {
+    if (!out) return VOR_E_INVAL;
+    *out = nullptr;
+    vor_ctx *c = new (std::nothrow) vor_ctx();
+    if (!c) return VOR_E_NOMEM;
+    if (opts) c->opts = *opts;
+    else c->opts.precision = VOR_FP32_FILTERED;
+    c->device = c->opts.device;
+    if (c->opts.precision != VOR_EXACT_ONLY && c->opts.precision != VOR_FP32_FILTERED) {
+        delete c;
+        return VOR_E_INVAL;
+    }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || c->device < 0 || c->device >= ndev) {
+        (void)hipGetLastError();
+        delete c;
+        return VOR_E_DEVICE;
+    }
+    if (hipSetDevice(c->device) != hipSuccess || c->ws.init() != hipSuccess) {
+        delete c;
+        return VOR_E_DEVICE;
+    }
+    const char *g = std::getenv("VOR_NO_GRAPH");
+    c->use_graph = !(g && g[0] == '1');
+    size_t fr = 0, tot = 0;
+    (void)hipMemGetInfo(&fr, &tot);
+    c->budget = c->opts.hbm_budget_bytes ? c->opts.hbm_budget_bytes : (uint64_t)(tot / 4 * 3);
+    *out = c;
+    return VOR_OK;
+}
+
+int vor_destroy(vor_ctx *ctx) {
+    if (!ctx) return VOR_E_INVAL;
+    {
+        std::lock_guard<std::mutex> lk(ctx->qmu);
+        ctx->stop = true;
+        ctx->pending.clear();
+    }
+    ctx->qcv.notify_all();
+    if (ctx->loop.joinable()) ctx->loop.join();
+    (void)hipSetDevice(ctx->device);
+    for (auto &kv : ctx->all)
+        if (kv.second->result) vor_result_free(kv.second->result);
+    ctx->all.clear();
+    ctx->ws.destroy();
+    if (ctx->loop_started)
+        for (auto &w : ctx->rws) w.destroy();
+    delete ctx;
+    return VOR_OK;
+}
+
+int vor_set_tuning(vor_ctx *ctx, const vor_tuning *t) {
+    if (!ctx || !t) return VOR_E_INVAL;
+    if (!(t->sites_per_bucket >= 0.0625f && t->sites_per_bucket <= 64.0f)) return VOR_E_INVAL;
+    if (t->block != 64 && t->block != 128 && t->block != 256) return VOR_E_INVAL;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->tune = *t;
+    return VOR_OK;
+}
+
+int vor_get_tuning(vor_ctx *ctx, vor_tuning *t) {
+    if (!ctx || !t) return VOR_E_INVAL;
+    *t = ctx->tune;
+    return VOR_OK;
+}
+
+int vor_compute(vor_ctx *ctx, const vor_set *set, vor_result **out) {
+    if (!ctx || !out) return VOR_E_INVAL;
+    *out = nullptr;
+    int rc = check_set(set);
+    if (rc != VOR_OK) return rc;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (hipSetDevice(ctx->device) != hipSuccess) return VOR_E_DEVICE;
+    std::vector<HostSet> sets{HostSet{set->n, set->x, set->y, set->box,
+                                      (set->flags & VOR_SET_DEVICE) != 0}};
+    std::vector<vor_result *> outs;
+    rc = run_sync(ctx, ctx->ws, sets, outs, (ctx->opts.flags & VOR_RESULT_DEVICE) != 0);
+    if (rc == VOR_OK) *out = outs[0];
+    return rc;
+}
+
+int vor_compute_batch(vor_ctx *ctx, const vor_set *sets, uint32_t k, vor_result **outs) {
+    if (!ctx || !sets || !outs || k == 0) return VOR_E_INVAL;
+    for (uint32_t i = 0; i < k; ++i) outs[i] = nullptr;
+    std::vector<HostSet> hs;
+    long long total = 0;
+    for (uint32_t i = 0; i < k; ++i) {
+        int rc = check_set(&sets[i]);
+        if (rc != VOR_OK) return rc;
+        if (sets[i].flags & VOR_SET_DEVICE) return VOR_E_INVAL;   // batches take host inputs
+        hs.push_back(HostSet{sets[i].n, sets[i].x, sets[i].y, sets[i].box, false});
+        total += sets[i].n;
+    }
+    if (total >= (1LL << 30)) return VOR_E_NOMEM;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (hipSetDevice(ctx->device) != hipSuccess) return VOR_E_DEVICE;
+    std::vector<vor_result *> res;
+    int rc = run_sync(ctx, ctx->ws, hs, res, false);
+    if (rc != VOR_OK) {
+        // an input error inside the batch: find the offending sets, run the rest
+        if (rc == VOR_E_DEVICE || rc == VOR_E_NOMEM) return rc;
+        int first_err = rc;
+        for (uint32_t i = 0; i < k; ++i) {
+            std::vector<HostSet> one{hs[i]};
+            std::vector<vor_result *> r1;
+            int r = run_sync(ctx, ctx->ws, one, r1, false);
+            if (r == VOR_OK) {
+                outs[i] = r1[0];
+            } else {
+                ResultBox *box;
+                vor_result *er = new_result(box);
+                if (er) er->status = r;
+                outs[i] = er;
+                if (r == VOR_E_DEVICE) return r;
+            }
+        }
+        return first_err;
+    }
+    for (uint32_t i = 0; i < k; ++i) outs[i] = res[i];
+    return VOR_OK;
+}
+
+int vor_submit(vor_ctx *ctx, const vor_set *set, uint64_t *ticket) {
+    if (!ctx || !ticket) return VOR_E_INVAL;
+    int rc = check_set(set);
+    if (rc != VOR_OK) return rc;
+    if (set->flags & VOR_SET_DEVICE) return VOR_E_INVAL;
+    auto r = std::make_shared<Request>();
+    r->x.assign(set->x, set->x + set->n);
+    r->y.assign(set->y, set->y + set->n);
+    r->box = set->box;
+    r->t_submit = now_s();
+    SetDesc d{};
+    choose_grid(set->box, set->n, ctx->tune.sites_per_bucket, d);
+    r->footprint = footprint_bytes(set->n, (uint64_t)d.gx * d.gy,
+                                   !(ctx->opts.flags & VOR_NO_VERTICES));
+    {
+        std::lock_guard<std::mutex> lk(ctx->qmu);
+        if (ctx->stop) return VOR_E_INVAL;
+        if (!ctx->loop_started) {
+            for (auto &w : ctx->rws)
+                if (w.init() != hipSuccess) return VOR_E_DEVICE;
+            ctx->loop_started = true;
+            ctx->loop = std::thread(request_loop, ctx);
+        }
+        r->ticket = ctx->next_ticket++;
+        *ticket = r->ticket;
+        ctx->all[r->ticket] = r;
+        ctx->pending.push_back(r);
+    }
+    ctx->qcv.notify_all();
+    return VOR_OK;
+}
+
+int vor_poll(vor_ctx *ctx, uint64_t ticket, vor_result **out) {
+    if (!ctx || !out) return VOR_E_INVAL;
+    *out = nullptr;
+    std::lock_guard<std::mutex> lk(ctx->qmu);
+    auto it = ctx->all.find(ticket);
+    if (it == ctx->all.end()) return VOR_E_TICKET;
+    Request &r = *it->second;
+    if (r.status == VOR_PENDING) return VOR_PENDING;
+    int st = r.status;
+    if (st == VOR_OK) {
+        *out = r.result;
+        r.result = nullptr;
+    }
+    // keep the latency stamps readable, but the result is consumed
+    r.status = st == VOR_OK ? VOR_E_TICKET : st;
+    if (st != VOR_OK) ctx->all.erase(it);
+    return st;
+}
+
+int vor_ticket_times(vor_ctx *ctx, uint64_t ticket, double *ts, double *ta, double *td) {
+    if (!ctx) return VOR_E_INVAL;
+    std::lock_guard<std::mutex> lk(ctx->qmu);
+    auto it = ctx->all.find(ticket);
+    if (it == ctx->all.end()) return VOR_E_TICKET;
+    if (ts) *ts = it->second->t_submit;
+    if (ta) *ta = it->second->t_admit;
+    if (td) *td = it->second->t_done;
+    return VOR_OK;
+}
+
+void vor_result_free(vor_result *r) {
+    if (!r) return;
+    delete reinterpret_cast<ResultBox *>(r);
+}
+
+}  // extern "C"

@@ -1,0 +1,257 @@
+// vor_device.hpp -- device-side building blocks of the projector algorithm on gfx950.
+//
+// Coordinates.  Every cell is computed in the frame of its own site p, doubled:
+// w = 2 (x - p).  In that frame the bisector of p and a site a is the line delta.w <= q with
+// delta = a - p and q = |delta|^2 (the closed half-plane of the cell, Section 2), and a side of
+// the box X is N.w <= 2 dist(p, side) with N the unit outward normal.  Every line is thus
+// (N, c) with integer N, |N| < 2^24, and 0 < c < 2^49.
+//
+// Ray endpoint (eq. Tdef of Theorem 2.2).  A ray from p in direction d leaves the cell at
+// T = min over lines with N.d > 0 of c / (N.d): the point p + t d stays in the half-plane of a
+// line exactly while t N.d <= c.  The minimising line is the line the endpoint lies on
+// (Method 5.1 reaches the same point: its temporary endpoints decrease monotonically, Lemma
+// on z closer than y, and stop at the first line crossed).
+//
+// Candidates (Method 11.5 buckets, Method 11.6 with Remark 11.7(ii) shell order, Lemma on
+// sites in the large square): buckets are scanned in Chebyshev shells around p's bucket.  Once
+// the square S[y, |y - p|] around an upper bound y of the endpoint lies inside the scanned
+// block, no unscanned site can be closer to y than p, so the scanned minimum is the endpoint
+// and every line through it has been seen (the squares of points of [p, y] nest, Lemma
+// B(y,y') / S(y,y')).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace vor {
+
+typedef __int128 i128;
+typedef unsigned __int128 u128;
+
+constexpr int KOUT = 24;     // lines per cell kept by the filtered pass (more: deferred)
+constexpr int SCAP = 24;     // LDS stack entries per thread in the filtered pass
+constexpr int DCAP1 = 128;   // stack / output entries per worker in the exact pass
+constexpr int DCAP2 = 65536; // same for the few workers of the deep-cell pass
+constexpr int NODE_LIMIT_FACTOR = 4;
+
+// status bits (device status word)
+enum : int { ST_DOMAIN = 1, ST_DUP = 2, ST_CAPACITY = 4, ST_INTERNAL = 8 };
+
+// stats slots
+enum : int {
+    SL_RAYS = 0, SL_NODES, SL_EVALS, SL_EXACT, SL_DEFERRED, SL_ASYM, SL_SHELLS, SL_EDGES,
+    SL_COUNT
+};
+
+struct SetDesc {
+    int32_t W, H;        // box extent: relative box [0, W] x [0, H]
+    int32_t x0, y0;      // absolute origin of the box
+    int32_t n;           // number of sites
+    int32_t site_off;    // first global index of the set (input, by-id and sorted arrays)
+    int32_t gx, gy;      // bucket grid
+    int32_t s;           // bucket side
+    int32_t bucket_off;  // first global bucket of the set
+};
+
+// ------------------------------------------------------------------------------ FP32 filter
+// u = 2^-24.  With d rounded componentwise to FP32 (relative error <= 1.01u) and the products
+// and sums rounded to nearest, |den_hat - den| <= 3.03 u S_hat; the upper / lower bounds
+// den_hat +- 5u S_hat (one more rounding) bracket the exact scaled N.d.  q_hat has relative
+// error <= 2.0001u, v_rcp_f32 is taken as <= 2 ulp (the ISA states 1 ulp), so
+//   t >= key_lo (1 - 7.01u)   and   t <= key_hi / (1 - 7.01u).
+// Certification multiplies by (1 +- 2^-19) = (1 +- 32u), which covers both factors and the
+// rounding of the product itself.
+constexpr float GAMMA = 5.0f * 5.9604644775390625e-8f;
+constexpr float CERT_UP = 1.0f + 1.9073486328125e-6f;   // 1 + 2^-19
+constexpr float CERT_DN = 1.0f - 1.9073486328125e-6f;   // 1 - 2^-19
+constexpr float FINF = __builtin_huge_valf();
+
+struct Best {
+    float k1, k2;   // smallest and second smallest lower bound
+    int w;          // sorted position (>= 0) or side code (-1..-4) of the smallest
+};
+
+__device__ __forceinline__ void consider(float key, int tag, Best &b) {
+    const bool better = key < b.k1;
+    b.k2 = fminf(b.k2, fmaxf(b.k1, key));
+    b.w = better ? tag : b.w;
+    b.k1 = fminf(b.k1, key);
+}
+
+#pragma clang fp contract(off)
+// Lower bound key of t = c / (N.d) for a line (nx, ny, c) (floats, exact), or +inf when N.d
+// is certainly <= 0.
+__device__ __forceinline__ float key_lo_line(float c, float nx, float ny, float dx, float dy) {
+    const float mx = nx * dx, my = ny * dy;
+    const float den = mx + my;
+    const float S = fabsf(mx) + fabsf(my);
+    const float up = fmaf(GAMMA, S, den);
+    const float key = c * __builtin_amdgcn_rcpf(up);
+    return up > 0.0f ? key : FINF;
+}
+// Upper bound key (+inf unless N.d is certainly > 0).
+__device__ __forceinline__ float key_hi_line(float c, float nx, float ny, float dx, float dy) {
+    const float mx = nx * dx, my = ny * dy;
+    const float den = mx + my;
+    const float S = fabsf(mx) + fabsf(my);
+    const float lo = fmaf(-GAMMA, S, den);
+    const float key = c * __builtin_amdgcn_rcpf(lo);
+    return lo > 0.0f ? key : FINF;
+}
+// Site candidate: delta = a - p exact in FP32 (|delta| < 2^24), q = |delta|^2 rounded.
+__device__ __forceinline__ float site_q(float ex, float ey) { return fmaf(ex, ex, ey * ey); }
+#pragma clang fp contract(fast)
+
+// ------------------------------------------------------------------------------ exact helpers
+__device__ __forceinline__ double u128_to_double(u128 m) {
+    return (double)(uint64_t)(m >> 64) * 18446744073709551616.0 + (double)(uint64_t)m;
+}
+__device__ __forceinline__ double i128_to_double(i128 v) {
+    const bool neg = v < 0;
+    const double r = u128_to_double(neg ? (u128)(-v) : (u128)v);
+    return neg ? -r : r;
+}
+
+// 64 x 128 -> 192-bit unsigned product, limbs little-endian.
+__device__ __forceinline__ void mul_u64_u128(uint64_t a, u128 b, uint64_t r[3]) {
+    const u128 lo = (u128)a * (uint64_t)b;
+    const u128 hi = (u128)a * (uint64_t)(b >> 64);
+    const u128 mid = (lo >> 64) + (u128)(uint64_t)hi;
+    r[0] = (uint64_t)lo;
+    r[1] = (uint64_t)mid;
+    r[2] = (uint64_t)(mid >> 64) + (uint64_t)(hi >> 64);
+}
+__device__ __forceinline__ int cmp192(const uint64_t a[3], const uint64_t b[3]) {
+    if (a[2] != b[2]) return a[2] < b[2] ? -1 : 1;
+    if (a[1] != b[1]) return a[1] < b[1] ? -1 : 1;
+    if (a[0] != b[0]) return a[0] < b[0] ? -1 : 1;
+    return 0;
+}
+// sign(t_i - t_j) for t = c / den with c > 0, den > 0:  sign(c_i den_j - c_j den_i).
+__device__ __forceinline__ int cmp_t(uint64_t ci, u128 di, uint64_t cj, u128 dj) {
+    uint64_t a[3], b[3];
+    mul_u64_u128(ci, dj, a);
+    mul_u64_u128(cj, di, b);
+    return cmp192(a, b);
+}
+
+// ------------------------------------------------------------------------------ lines
+struct Line {
+    int id;         // sorted position (>= 0) or side code (-1 .. -4)
+    int nx, ny;     // normal (doubled frame)
+    int64_t c;      // right-hand side, > 0
+};
+
+struct Cell {       // per-cell constants
+    int gx, gy, s, boff;  // the set's bucket grid
+    float pxf, pyf; // p, relative to the box origin (exact floats)
+    int px, py;
+    int bx, by;     // p's bucket
+    int W, H;       // box extent (relative box [0, W] x [0, H])
+};
+
+// Box side code -> line (N.w <= 2 dist).  k = -code - 1: 0 bottom, 1 right, 2 top, 3 left.
+// Written with arithmetic selects so that no lookup table is materialised.
+__device__ __forceinline__ Line side_line(const Cell &C, int code) {
+    const int k = -code - 1;
+    const bool vert = (k & 1) == 0;            // bottom / top: normal along y
+    const bool far = ((k + 1) >> 1) & 1;       // right / top: outward normal positive
+    const int v = vert ? C.py : C.px;
+    const int ext = vert ? C.H : C.W;
+    const int sgn = far ? 1 : -1;
+    Line L;
+    L.id = code;
+    L.nx = vert ? 0 : sgn;
+    L.ny = vert ? sgn : 0;
+    L.c = 2 * (int64_t)(far ? ext - v : v);
+    return L;
+}
+__device__ __forceinline__ Line site_line(const Cell &C, const float2 *sxy, int pos) {
+    const float2 a = sxy[pos];
+    Line L;
+    L.id = pos;
+    L.nx = (int)a.x - C.px;
+    L.ny = (int)a.y - C.py;
+    L.c = (int64_t)L.nx * L.nx + (int64_t)L.ny * L.ny;
+    return L;
+}
+__device__ __forceinline__ Line make_line(const Cell &C, const float2 *sxy, int id) {
+    return id >= 0 ? site_line(C, sxy, id) : side_line(C, id);
+}
+
+// Direction d (exact, 128-bit components) and its FP32 image d_s = d 2^-sigma rounded, with
+// max |component| of d_s in [1, 2).
+struct Dir {
+    i128 x, y;
+    float fx, fy;
+    int sigma;
+};
+__device__ __forceinline__ Dir make_dir(i128 x, i128 y) {
+    Dir d;
+    d.x = x;
+    d.y = y;
+    const double ax = i128_to_double(x), ay = i128_to_double(y);
+    const double m = fmax(fabs(ax), fabs(ay));
+    int e;
+    (void)frexp(m, &e);          // m = f 2^e, f in [0.5, 1)
+    d.sigma = e - 1;             // m 2^-sigma in [1, 2)
+    d.fx = (float)ldexp(ax, -d.sigma);
+    d.fy = (float)ldexp(ay, -d.sigma);
+    return d;
+}
+
+// ------------------------------------------------------------------------------ shells
+// Calls f(lo, hi) for every sorted-position range of shell k around bucket (bx, by).
+template <class F>
+__device__ __forceinline__ void for_shell(const Cell &S, const int *__restrict__ bstart, int bx,
+                                          int by, int k, F &&f) {
+    const int base = S.boff;
+    if (k == 0) {
+        const int b = base + by * S.gx + bx;
+        f(bstart[b], bstart[b + 1]);
+        return;
+    }
+    const int xa = max(bx - k, 0), xb = min(bx + k, S.gx - 1);
+    if (by - k >= 0) {
+        const int r = base + (by - k) * S.gx;
+        f(bstart[r + xa], bstart[r + xb + 1]);
+    }
+    if (by + k < S.gy) {
+        const int r = base + (by + k) * S.gx;
+        f(bstart[r + xa], bstart[r + xb + 1]);
+    }
+    const int ya = max(by - k + 1, 0), yb = min(by + k - 1, S.gy - 1);
+    if (bx - k >= 0)
+        for (int y = ya; y <= yb; ++y) {
+            const int b = base + y * S.gx + bx - k;
+            f(bstart[b], bstart[b + 1]);
+        }
+    if (bx + k < S.gx)
+        for (int y = ya; y <= yb; ++y) {
+            const int b = base + y * S.gx + bx + k;
+            f(bstart[b], bstart[b + 1]);
+        }
+}
+
+// True when every site closer than p to the point y = p + (T/2) d_s (doubled-frame ray
+// parameter T, an upper bound of the endpoint) lies in the block of shells 0..k: the square
+// S[y, |y - p|] (Lemma on sites in the large square; eq. S_I gives the same bucket test)
+// fits inside the block, a block side on the grid edge counting as unbounded.
+__device__ __forceinline__ bool block_certifies(const Cell &C, int k, float T, float dx,
+                                                float dy) {
+    const Cell &S = C;
+    const bool el = C.bx - k <= 0, er = C.bx + k >= S.gx - 1;
+    const bool eb = C.by - k <= 0, et = C.by + k >= S.gy - 1;
+    if (el && er && eb && et) return true;
+    const float Tu = T * CERT_UP;
+    const float hx = 0.5f * Tu * dx, hy = 0.5f * Tu * dy;
+    const float yx = C.pxf + hx, yy = C.pyf + hy;
+    const float r = sqrtf(hx * hx + hy * hy);
+    const float M = (r + fabsf(yx) + fabsf(yy)) * 1.0e-5f + 1.0e-3f;
+    const bool l = el || (yx - r - M >= (float)(C.bx - k) * (float)S.s);
+    const bool rr = er || (yx + r + M < (float)(C.bx + k + 1) * (float)S.s);
+    const bool b = eb || (yy - r - M >= (float)(C.by - k) * (float)S.s);
+    const bool t = et || (yy + r + M < (float)(C.by + k + 1) * (float)S.s);
+    return l && rr && b && t;
+}
+
+}  // namespace vor

@@ -1,0 +1,55 @@
+// vor_internal.h -- interface between the host runtime (vor_api.cpp) and the device pipeline.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace vor {
+
+struct SetDesc;
+constexpr int SMALL_INTS = 16;   // status, qcount, qcount2, poolcnt, spare
+constexpr int DEEP_BLOCKS = 1;   // workers of the deep-cell pass = 64 * DEEP_BLOCKS
+
+// Device pointers and sizes of one pipeline launch.
+struct PipeArgs {
+    const SetDesc *sets;
+    int nsets;
+    const int *set_off;     // [nsets + 1] first global site of each set
+    int total;              // sites in all sets
+    long long gtot;         // buckets in all sets
+    const int *in_x, *in_y; // absolute input coordinates [total]
+    int2 *xyid;             // relative coordinates by site [total]
+    int *key;               // bucket of each site [total]
+    int *bcnt;              // [gtot]
+    int *bstart;            // [gtot + 1]
+    float2 *sxy;            // sorted coordinates [total]
+    int *sid;               // local id of each sorted site [total]
+    int *ocnt, *olines, *ovf;
+    int *pool;
+    long long poolcap;
+    int *queue, *queue2;
+    int *wbuf, *wbuf2;
+    int exact_blocks;
+    int *cell_off;          // [total + 1]
+    int *nbr;
+    long long nbr_cap;
+    void *vtx;              // vor_rat [nbr_cap]
+    int *dcnt, *del_off;    // [total], [total + 1]
+    unsigned *del;          // [2 * del_cap]
+    long long del_cap;
+    int *scan_tmp;
+    int *small;             // SMALL_INTS
+    unsigned long long *stats;
+    int block;
+    bool exact_only, with_vertices, check_symmetry;
+
+    int *status() const { return small; }
+    int *status_rw() const { return small; }
+    int *qcount() const { return small + 1; }
+    int *qcount2() const { return small + 2; }
+    int *poolcnt() const { return small + 3; }
+};
+
+void launch_pipeline(const PipeArgs &a, hipStream_t st);
+long long scan_tmp_ints(long long n);
+
+}  // namespace vor

@@ -1,0 +1,54 @@
+"""The C-ABI library loads and exports every function include/vor.h declares (CPU only: no
+compute calls without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "vor.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:int|void|const char \*)\s*(vor_\w+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("vor_create", "vor_destroy", "vor_compute", "vor_compute_batch", "vor_submit",
+                 "vor_poll", "vor_result_free", "vor_strerror"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_1212_1095_amd as vor
+    lib = ctypes.CDLL(vor.lib_path())
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_strerror_and_version_without_gpu():
+    import paper_1212_1095_amd as vor
+    assert vor.vor_strerror(vor.VOR_E_DUPLICATE) == "duplicate sites"
+    assert vor.vor_strerror(12345) == "unknown status"
+    assert "gfx950" in vor.vor_version()
+
+
+def test_create_fails_loudly_without_gpu():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("GPU present")
+    import paper_1212_1095_amd as vor
+    with pytest.raises(vor.VorError):
+        vor.Context()
+
+
+def test_no_fallback_when_library_missing(tmp_path, monkeypatch):
+    import paper_1212_1095_amd._binding as b
+    monkeypatch.setattr(b, "_LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(b, "_lib", None)
+    with pytest.raises(ImportError):
+        b.lib()

@@ -1,0 +1,162 @@
+"""Parity of the HIP path with the oracle (element by element), through the C ABI."""
+import numpy as np
+import pytest
+
+import sitegen
+from oracle import cdiagram, paper_forms
+from tests.gpu_util import assert_matches_oracle, say, symmetric
+
+pytestmark = pytest.mark.gpu
+
+MODES = ["filtered", "exact"]
+
+
+@pytest.fixture(scope="module")
+def vor():
+    import paper_1212_1095_amd as v
+    return v
+
+
+@pytest.fixture(scope="module", params=MODES)
+def ctx(request, vor):
+    prec = vor.VOR_FP32_FILTERED if request.param == "filtered" else vor.VOR_EXACT_ONLY
+    c = vor.Context(device=0, precision=prec)
+    c.mode = request.param
+    yield c
+    c.close()
+
+
+def run(ctx, ps, name):
+    say(f"[{ctx.mode}] {name}: n={ps.n} box={ps.box}")
+    return ctx.compute(ps.x, ps.y, ps.box)
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_tiny_tie_heavy_sets(ctx, seed):
+    n = 1 + seed % 8
+    ps = sitegen.small_integer_set(n, 3 + seed % 6, seed=5000 + seed)
+    r = run(ctx, ps, f"tiny seed={seed}")
+    assert_matches_oracle(r, ps)
+
+
+def test_single_site(ctx):
+    ps = sitegen.PointSet(np.array([3], np.int32), np.array([5], np.int32), (0, 0, 10, 10))
+    r = run(ctx, ps, "single site")
+    assert r.lines(0) == [-4, -1, -2, -3]
+    assert_matches_oracle(r, ps)
+
+
+def test_two_sites(ctx):
+    ps = sitegen.PointSet(np.array([2, 8], np.int32), np.array([5, 5], np.int32), (0, 0, 10, 10))
+    assert_matches_oracle(run(ctx, ps, "two sites"), ps)
+
+
+def test_collinear_row(ctx):
+    xs = np.array([3, 7, 15, 16, 30, 31, 33], np.int32)
+    ps = sitegen.PointSet(xs, np.full(xs.shape, 20, np.int32), (0, 0, 40, 40))
+    assert_matches_oracle(run(ctx, ps, "collinear row"), ps)
+
+
+def test_collinear_column_and_diagonal(ctx):
+    ys = np.array([1, 5, 6, 20, 38], np.int32)
+    ps = sitegen.PointSet(np.full(ys.shape, 11, np.int32), ys, (0, 0, 40, 40))
+    assert_matches_oracle(run(ctx, ps, "collinear column"), ps)
+    d = np.array([2, 5, 9, 14, 30], np.int32)
+    ps = sitegen.PointSet(d, d, (0, 0, 40, 40))
+    assert_matches_oracle(run(ctx, ps, "diagonal"), ps)
+
+
+def test_twelve_cocircular(ctx):
+    offs = [(3, 4), (4, 3), (5, 0), (4, -3), (3, -4), (0, -5), (-3, -4), (-4, -3), (-5, 0),
+            (-4, 3), (-3, 4), (0, 5)]
+    x = np.array([50 + a for a, _ in offs], np.int32)
+    y = np.array([50 + b for _, b in offs], np.int32)
+    ps = sitegen.PointSet(x, y, (0, 0, 100, 100))
+    r = run(ctx, ps, "12 cocircular")
+    assert_matches_oracle(r, ps)
+    assert r.dele.shape[0] == 12
+
+
+@pytest.mark.parametrize("k", [1, 2, 7, 16])
+def test_perfect_lattice(ctx, k):
+    h = 64
+    ii, jj = np.meshgrid(np.arange(k), np.arange(k), indexing="xy")
+    x = (h // 2 + h * ii.ravel()).astype(np.int32)
+    y = (h // 2 + h * jj.ravel()).astype(np.int32)
+    ps = sitegen.PointSet(x, y, (0, 0, k * h, k * h))
+    r = run(ctx, ps, f"lattice {k}x{k}")
+    assert_matches_oracle(r, ps)
+    assert r.dele.shape[0] == 2 * k * (k - 1)
+
+
+def test_config1_uniform_1000(ctx):
+    """n = 1000 uniform in [1, 2^16)^2, X = [0, 2^16]^2, seed 1."""
+    ps = sitegen.uniform(1000, 1 << 16, seed=1)
+    r = run(ctx, ps, "config1")
+    assert_matches_oracle(r, ps)
+
+
+@pytest.mark.parametrize("gen,n", [("uniform", 20000), ("clustered", 20000),
+                                   ("lattice", 20000)])
+def test_moderate_full(ctx, gen, n):
+    if gen == "uniform":
+        ps = sitegen.uniform(n, 1 << 20, seed=41)
+    elif gen == "clustered":
+        ps = sitegen.clustered(n, 1 << 24, seed=42)
+    else:
+        ps = sitegen.lattice(n, 1 << 24, seed=43)
+    r = run(ctx, ps, f"{gen} {n}")
+    assert_matches_oracle(r, ps)
+
+
+def test_small_box_dense(ctx):
+    """Many sites in a small box: most coordinates collide with cocircular quadruples."""
+    ps = sitegen.small_integer_set(600, 40, seed=77)
+    r = run(ctx, ps, "dense small box")
+    assert_matches_oracle(r, ps)
+
+
+def test_negative_box_origin(ctx):
+    ps = sitegen.uniform(3000, 1 << 18, seed=9)
+    x = ps.x - (1 << 17) - 12345
+    y = ps.y - 77777
+    box = (-(1 << 17) - 12345, -77777, (1 << 18) - (1 << 17) - 12345, (1 << 18) - 77777)
+    ps2 = sitegen.PointSet(x.astype(np.int32), y.astype(np.int32), box)
+    assert_matches_oracle(run(ctx, ps2, "negative origin"), ps2)
+
+
+def test_paper_counter_bounds(ctx):
+    """Lemma on shot rays: sum rho_k <= (|X_e| + 7) n = 11 n; nodes <= 2 e_k per cell summed;
+    sum e_k <= 10 n (rectangle X)."""
+    ps = sitegen.uniform(50000, 1 << 24, seed=2)
+    r = run(ctx, ps, "counters")
+    E = int(r.cell_off[-1])
+    assert E <= 10 * ps.n
+    assert r.stats.edges == E
+    assert r.stats.rays <= 11 * ps.n
+    assert r.stats.nodes <= 2 * E
+    say(f"  rays/cell={r.stats.rays / ps.n:.3f} nodes/cell={r.stats.nodes / ps.n:.3f} "
+        f"evals/cell={r.stats.evals / ps.n:.1f} exact={r.stats.exact_decisions} "
+        f"deferred={r.stats.deferred_cells}")
+
+
+def test_errors(vor):
+    with vor.Context() as c:
+        box = (0, 0, 100, 100)
+        for x, y, code in [([5, 5], [6, 6], vor.VOR_E_DUPLICATE),
+                           ([0, 5], [6, 7], vor.VOR_E_DOMAIN),
+                           ([100, 5], [6, 7], vor.VOR_E_DOMAIN),
+                           ([5, 50], [6, 100], vor.VOR_E_DOMAIN)]:
+            say(f"error case {x} {y}")
+            with pytest.raises(vor.VorError) as e:
+                c.compute(np.array(x, np.int32), np.array(y, np.int32), box)
+            assert e.value.status == code
+        with pytest.raises(vor.VorError) as e:
+            c.compute(np.array([], np.int32), np.array([], np.int32), box)
+        assert e.value.status == vor.VOR_E_INVAL
+        with pytest.raises(vor.VorError) as e:
+            c.compute(np.array([1], np.int32), np.array([1], np.int32), (0, 0, 1 << 25, 10))
+        assert e.value.status == vor.VOR_E_DOMAIN
+        # the context still works after errors
+        ps = sitegen.uniform(100, 1 << 10, seed=3)
+        assert_matches_oracle(c.compute(ps.x, ps.y, ps.box), ps)
