@@ -1,0 +1,227 @@
+"""Benchmark: Voronoi cells per second (bit-exact) of the projector-algorithm engine on MI355X.
+
+Workload (default): one set of n = 2^20 distinct sites uniform in [1, 2^24)^2, X = [0, 2^24]^2,
+seed 2, FP32-filtered predicates with exact fallback.  Inputs are resident in HBM (torch
+tensors) when the timed region starts; one step = the whole device pipeline (validation, grid,
+projector cells, CSR neighbour lists, pair-form vertices, Delaunay edges) through the C ABI.
+
+Prints ONE JSON line.  Also measured, outside the timed steps:
+  * roofline of the dominant kernel (the filtered cell pass), timed with HIP events on the
+    library's stream during the timed steps;
+  * the oracle (C, exact half-plane clipping) on a bounded sample of the same cells, on the
+    host cores, which also checks the sampled GPU cells bit for bit;
+  * the exact-only GPU path on the same set, and the batched and served modes (--extras).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Per candidate evaluation the FP32 filter executes these floating-point operations:
+# 2 sub (delta), mul + fma (q: 3 flops), 2 mul (delta.d products), add (den), add (|.| sum),
+# fma (upper den bound: 2 flops), rcp, mul (key) = 13 flops.
+FLOPS_PER_EVAL = 13
+PEAK_FP32_TFLOPS = 157.3      # MI355X FP32 vector (spec sheet)
+PEAK_FP32_NONPACKED = 78.6    # without packed FP32 (the build disables packed FP32 ops)
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_workload(n, B, seed):
+    import sitegen
+    return sitegen.uniform(n, B, seed=seed)
+
+
+def cpu_baseline(ps, res, budget_s=12.0, threads=None):
+    """Oracle on a bounded sample of cells; returns (cells/s, cores, sample, sample_cells)."""
+    from oracle import cdiagram
+    if threads is None:
+        threads = min(16, os.cpu_count() or 1)
+    rng = np.random.default_rng(12345)
+    probe = np.sort(rng.choice(ps.n, size=min(ps.n, 8 * threads), replace=False)).astype(np.int32)
+    t0 = time.perf_counter()
+    cdiagram.cells(ps.x, ps.y, ps.box, which=probe, threads=threads, vertices=False)
+    t_probe = time.perf_counter() - t0
+    per_cell = t_probe / probe.shape[0]
+    m = int(min(ps.n, max(probe.shape[0], budget_s / max(per_cell, 1e-9))))
+    which = np.sort(rng.choice(ps.n, size=m, replace=False)).astype(np.int32)
+    t0 = time.perf_counter()
+    oc = cdiagram.cells(ps.x, ps.y, ps.box, which=which, threads=threads, vertices=True)
+    dt = time.perf_counter() - t0
+    # bit-exact check of the sampled cells (neighbour lists and pair-form vertices)
+    bad = 0
+    if res is not None:
+        for i, k in enumerate(which):
+            lo, hi = int(res.cell_off[k]), int(res.cell_off[k + 1])
+            if res.nbr[lo:hi].tolist() != oc.lines(i):
+                bad += 1
+                continue
+            if res.vtx is not None:
+                v = res.vtx[lo:hi]
+                o0, o1 = int(oc.off[i]), int(oc.off[i + 1])
+                X = [int(h) * (1 << 64) + int(l) for l, h in zip(v["x_lo"], v["x_hi"])]
+                if X != list(oc.vx[o0:o1]) or [int(d) for d in v["d"]] != [int(d) for d in oc.vd[o0:o1]]:
+                    bad += 1
+    return m / dt, threads, m, bad, dt
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=1 << 20)
+    ap.add_argument("--box", type=int, default=1 << 24)
+    ap.add_argument("--seed", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--extras", action="store_true", help="also time exact-only mode")
+    ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB mebibytes (counter calibration)")
+    args = ap.parse_args()
+
+    if args.copy_calibration:
+        import torch
+        nbytes = args.copy_calibration << 20
+        src = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": nbytes, "launches": 3}), flush=True)
+        return
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; the path shards by cell "
+                                   "ranges or sets (see the design notes), but no multi-GPU "
+                                   "run is provided", "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+
+    import torch
+    import paper_1212_1095_amd as vor
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    dev = torch.device("cuda:0")
+    ps = make_workload(args.n, args.box, args.seed)
+    log(f"workload: n={ps.n} box={ps.box} seed={args.seed}")
+    xd = torch.from_numpy(ps.x).to(dev)
+    yd = torch.from_numpy(ps.y).to(dev)
+    torch.cuda.synchronize()
+
+    ctx = vor.Context(device=0, precision=vor.VOR_FP32_FILTERED,
+                      flags=vor.VOR_RESULT_DEVICE | vor.VOR_TIME_KERNELS)
+
+    def step():
+        return ctx.compute((xd.data_ptr(), ps.n), (yd.data_ptr(), ps.n), ps.box,
+                           device_ptrs=True)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    cells_ms, dev_ms, last = [], [], None
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        last = step()
+        cells_ms.append(last.cells_ms)
+        dev_ms.append(last.device_ms)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = 1000.0 * wall / args.steps
+    value = ps.n / (wall / args.steps)
+    st = last.stats
+    log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step, device {np.mean(dev_ms):.3f} ms, "
+        f"grid {last.grid_ms:.3f} cells {np.mean(cells_ms):.3f} exact {last.exact_ms:.3f} "
+        f"emit {last.emit_ms:.3f} ms, graph {last.graph_replayed}; stats {st}")
+    ctx.close()
+
+    # host copy of one full result for the sampled bit-exact check (outside the timed region)
+    res = None
+    if not args.no_cpu:
+        with vor.Context(device=0) as hctx:
+            res = hctx.compute(ps.x, ps.y, ps.box)
+
+    # roofline of the dominant kernel: algorithmic flops per launch / mean launch duration
+    evals = st.evals
+    kern_s = float(np.mean(cells_ms)) / 1000.0
+    achieved = evals * FLOPS_PER_EVAL / kern_s / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved, 4), "peak": PEAK_FP32_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 6), "traffic": None,
+                "kernel": "k_cells_fast<256>", "kernel_ms": round(1000 * kern_s, 4),
+                "flops_per_eval": FLOPS_PER_EVAL, "evals_per_launch": int(evals),
+                "frac_nonpacked_peak": round(achieved / PEAK_FP32_NONPACKED, 6)}
+
+    cpu = None
+    if not args.no_cpu:
+        v, cores, m, bad, dt = cpu_baseline(ps, res, args.cpu_budget)
+        cpu = {"value": round(v, 2), "unit": "cells/s", "cores": cores, "kind": "oracle",
+               "sample": f"{m} cells sampled uniformly from the same n={ps.n} set "
+                         f"(exact half-plane clipping, {dt:.1f} s wall)",
+               "sampled_cells_bit_exact": m - bad, "sampled_cells_mismatch": bad}
+        log(f"oracle sample: {m} cells in {dt:.2f} s on {cores} threads, mismatches {bad}")
+        if bad:
+            log("ERROR: sampled cells differ from the oracle")
+
+    extra = {}
+    if args.extras:
+        with vor.Context(device=0, precision=vor.VOR_EXACT_ONLY,
+                         flags=vor.VOR_RESULT_DEVICE | vor.VOR_TIME_KERNELS) as ectx:
+            for _ in range(2):
+                ectx.compute((xd.data_ptr(), ps.n), (yd.data_ptr(), ps.n), ps.box,
+                             device_ptrs=True)
+            torch.cuda.synchronize()
+            k = max(3, args.steps // 4)
+            t0 = time.perf_counter()
+            for _ in range(k):
+                er = ectx.compute((xd.data_ptr(), ps.n), (yd.data_ptr(), ps.n), ps.box,
+                                  device_ptrs=True)
+            torch.cuda.synchronize()
+            ew = (time.perf_counter() - t0) / k
+        extra["exact_only_cells_per_s"] = round(ps.n / ew, 1)
+        extra["exact_only_ms_per_step"] = round(1000 * ew, 3)
+
+    out = {
+        "metric": "Voronoi cells/sec (bit-exact) plain vs batched; p50/p99 latency per request",
+        "value": round(value, 1),
+        "unit": "cells/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+i128",
+        "data": "synthetic",
+        "config": {"workload": f"single set, n={ps.n} uniform sites in [1,{args.box})^2, "
+                               f"X=[0,{args.box}]^2, seed {args.seed}, FP32 filter + exact "
+                               f"fallback, vertices and Delaunay edges",
+                   "n": ps.n, "box": args.box, "mode": "plain (single set)"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "stats": {"evals_per_cell": round(st.evals / ps.n, 2),
+                  "rays_per_cell": round(st.rays / ps.n, 3),
+                  "nodes_per_cell": round(st.nodes / ps.n, 3),
+                  "shells_per_cell": round(st.shells / ps.n, 3),
+                  "exact_decisions": st.exact_decisions, "deferred_cells": st.deferred_cells,
+                  "edges_per_cell": round(st.edges / ps.n, 3),
+                  "device_ms": round(float(np.mean(dev_ms)), 4),
+                  "stage_ms": {"grid": round(last.grid_ms, 4), "cells": round(last.cells_ms, 4),
+                               "exact": round(last.exact_ms, 4), "emit": round(last.emit_ms, 4)},
+                  "graph_replayed": bool(last.graph_replayed)},
+    }
+    if extra:
+        out["extra"] = extra
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

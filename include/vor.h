@@ -34,7 +34,7 @@ extern "C" {
 #define VOR_E_NOMEM (-4)       /* device memory or the HBM budget cannot hold the job         */
 #define VOR_E_DEVICE (-5)      /* a HIP runtime error                                         */
 #define VOR_E_TICKET (-6)      /* unknown or already consumed ticket                          */
-#define VOR_E_CAPACITY (-7)    /* a cell deeper than the exact pass supports (> 4096 lines)   */
+#define VOR_E_CAPACITY (-7)    /* a cell with more lines than the deep pass holds (65536)    */
 
 /* ---- side codes used in neighbour lists (Section 6: boundary lines get unique indices) ---- */
 #define VOR_SIDE_BOTTOM (-1)   /* y = y0 */
@@ -48,6 +48,7 @@ extern "C" {
                                      context, valid until the next call or vor_result_free)  */
 #define VOR_NO_VERTICES 0x4u      /* opts: do not write vertex rationals (vtx == NULL)         */
 #define VOR_CHECK_SYMMETRY 0x8u   /* opts: count asymmetric neighbour pairs into stats          */
+#define VOR_TIME_KERNELS 0x10u    /* opts: HIP events between the pipeline stages (*_ms fields) */
 
 typedef struct vor_ctx vor_ctx;   /* opaque: device memory pools, streams, request loop */
 
@@ -100,6 +101,7 @@ typedef struct {
     uint64_t asym_pairs;      /* with VOR_CHECK_SYMMETRY: neighbour pairs seen one way only   */
     uint64_t shells;          /* bucket shells scanned                                        */
     uint64_t edges;           /* sum of e_k                                                   */
+    uint64_t vertex_tests;    /* rays towards a candidate vertex that confirmed it            */
 } vor_stats;
 
 /* Result of one point set.  Host memory owned by the library (device memory with
@@ -116,6 +118,11 @@ typedef struct {
     const uint32_t *del;       /* [2m] pairs (i, j), i < j, lexicographically sorted          */
     vor_stats stats;
     float device_ms;           /* device time of the pipeline (HIP events)                     */
+    float cells_ms;            /* with VOR_TIME_KERNELS: filtered cell pass                    */
+    float exact_ms;            /* with VOR_TIME_KERNELS: exact / deep cell passes              */
+    float grid_ms;             /* with VOR_TIME_KERNELS: validation and grid build             */
+    float emit_ms;             /* with VOR_TIME_KERNELS: CSR, vertices, Delaunay edges         */
+    int32_t graph_replayed;    /* 1 when the pipeline ran as replayed HIP graph(s)            */
     int32_t status;            /* VOR_OK, or the error of this set inside a batch             */
 } vor_result;
 

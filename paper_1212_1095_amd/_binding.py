@@ -15,6 +15,7 @@ VOR_OK, VOR_PENDING = 0, 1
 VOR_E_INVAL, VOR_E_DOMAIN, VOR_E_DUPLICATE, VOR_E_NOMEM = -1, -2, -3, -4
 VOR_E_DEVICE, VOR_E_TICKET, VOR_E_CAPACITY = -5, -6, -7
 VOR_SET_DEVICE, VOR_RESULT_DEVICE, VOR_NO_VERTICES, VOR_CHECK_SYMMETRY = 0x1, 0x2, 0x4, 0x8
+VOR_TIME_KERNELS = 0x10
 VOR_EXACT_ONLY, VOR_FP32_FILTERED = 0, 1
 
 
@@ -39,13 +40,16 @@ class vor_rat(C.Structure):
 
 class vor_stats(C.Structure):
     _fields_ = [(k, C.c_uint64) for k in ("rays", "nodes", "evals", "exact_decisions",
-                                           "deferred_cells", "asym_pairs", "shells", "edges")]
+                                           "deferred_cells", "asym_pairs", "shells", "edges",
+                                           "vertex_tests")]
 
 
 class vor_result(C.Structure):
     _fields_ = [("n", C.c_uint32), ("cell_off", C.c_void_p), ("nbr", C.c_void_p),
                 ("vtx", C.c_void_p), ("m", C.c_uint64), ("del_", C.c_void_p),
-                ("stats", vor_stats), ("device_ms", C.c_float), ("status", C.c_int32)]
+                ("stats", vor_stats), ("device_ms", C.c_float), ("cells_ms", C.c_float),
+                ("exact_ms", C.c_float), ("grid_ms", C.c_float), ("emit_ms", C.c_float),
+                ("graph_replayed", C.c_int32), ("status", C.c_int32)]
 
 
 class vor_tuning(C.Structure):
@@ -144,6 +148,7 @@ class Stats:
     asym_pairs: int
     shells: int
     edges: int
+    vertex_tests: int
 
 
 @dataclass
@@ -156,6 +161,11 @@ class Result:
     stats: Stats
     device_ms: float
     status: int
+    cells_ms: float = 0.0
+    exact_ms: float = 0.0
+    grid_ms: float = 0.0
+    emit_ms: float = 0.0
+    graph_replayed: int = 0
 
     def lines(self, k: int) -> list:
         return self.nbr[self.cell_off[k]:self.cell_off[k + 1]].tolist()
@@ -171,13 +181,24 @@ class Result:
 _RAT = np.dtype([("x_lo", "<u8"), ("x_hi", "<i8"), ("y_lo", "<u8"), ("y_hi", "<i8"), ("d", "<i8")])
 
 
-def _to_result(rp) -> Result:
+def _to_result(rp, device: bool = False) -> Result:
     r = rp.contents
     n = int(r.n)
     st = Stats(*[int(getattr(r.stats, f)) for f, _ in vor_stats._fields_])
+    if device:
+        # arrays live in device memory: hand back their addresses, never dereference them here
+        res = Result(n, np.zeros(0, np.uint32), np.zeros(0, np.int32), None,
+                     np.zeros((0, 2), np.uint32), st, float(r.device_ms), int(r.status),
+                     float(r.cells_ms), float(r.exact_ms), float(r.grid_ms),
+                     float(r.emit_ms), int(r.graph_replayed))
+        res.device_ptrs = {"cell_off": r.cell_off, "nbr": r.nbr, "vtx": r.vtx, "del": r.del_,
+                           "m": int(r.m)}
+        return res
     if r.status != VOR_OK or not r.cell_off:
         return Result(n, np.zeros(0, np.uint32), np.zeros(0, np.int32), None,
-                      np.zeros((0, 2), np.uint32), st, float(r.device_ms), int(r.status))
+                      np.zeros((0, 2), np.uint32), st, float(r.device_ms), int(r.status),
+                      float(r.cells_ms), float(r.exact_ms), float(r.grid_ms), float(r.emit_ms),
+                      int(r.graph_replayed))
     off = np.ctypeslib.as_array(C.cast(r.cell_off, C.POINTER(C.c_uint32)), (n + 1,)).copy()
     E = int(off[-1])
     nbr = (np.ctypeslib.as_array(C.cast(r.nbr, C.POINTER(C.c_int32)), (E,)).copy()
@@ -189,21 +210,25 @@ def _to_result(rp) -> Result:
     m = int(r.m)
     dele = (np.ctypeslib.as_array(C.cast(r.del_, C.POINTER(C.c_uint32)), (2 * m,)).copy()
             .reshape(m, 2) if m else np.zeros((0, 2), np.uint32))
-    return Result(n, off, nbr, vtx, dele, st, float(r.device_ms), int(r.status))
+    return Result(n, off, nbr, vtx, dele, st, float(r.device_ms), int(r.status),
+                  float(r.cells_ms), float(r.exact_ms), float(r.grid_ms), float(r.emit_ms),
+                  int(r.graph_replayed))
 
 
 def vor_result_free(rp) -> None:
     lib().vor_result_free(rp)
 
 
-def vor_compute(ctx, x, y, box, device_ptrs=False, keep_raw=False):
+def vor_compute(ctx, x, y, box, device_ptrs=False, keep_raw=False, device_result=False):
+    """x, y: int32 host arrays, or (device address, n) pairs with device_ptrs=True.
+    device_result must match the context's VOR_RESULT_DEVICE flag."""
     s, keep = _make_set(x, y, box, device_ptrs)
     rp = C.POINTER(vor_result)()
     _check(lib().vor_compute(ctx, C.byref(s), C.byref(rp)), "vor_compute")
     if keep_raw:
         return rp
     try:
-        return _to_result(rp)
+        return _to_result(rp, device_result)
     finally:
         lib().vor_result_free(rp)
 
@@ -272,9 +297,12 @@ class Context:
     """Owning wrapper: ``with Context() as ctx: ctx.compute(x, y, box)``."""
 
     def __init__(self, device=0, precision=VOR_FP32_FILTERED, flags=0, hbm_budget_bytes=0):
+        self.h = None
+        self.flags = flags
         self.h = vor_create(device, precision, flags, hbm_budget_bytes)
 
     def compute(self, x, y, box, **kw):
+        kw.setdefault("device_result", bool(self.flags & VOR_RESULT_DEVICE))
         return vor_compute(self.h, x, y, box, **kw)
 
     def compute_batch(self, sets):

@@ -82,22 +82,30 @@ struct Workspace {
     HostBuf h_in, h_small;
     hipStream_t stream = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    hipGraphExec_t gexec = nullptr;
-    hipGraph_t graph = nullptr;
+    hipEvent_t ek[NSTAGES + 1] = {};
+    hipGraphExec_t gexec[NSTAGES] = {};
+    hipGraph_t graph[NSTAGES] = {};
     PipeArgs gkey{};
     bool have_graph = false;
+    bool graph_broken = false;
+    bool last_timed = false;
+    bool used_graph = false;
 
     hipError_t init() {
         hipError_t e = hipStreamCreateWithFlags(&stream, hipStreamNonBlocking);
         if (e != hipSuccess) return e;
         if ((e = hipEventCreate(&ev0)) != hipSuccess) return e;
+        for (auto &x : ek)
+            if ((e = hipEventCreate(&x)) != hipSuccess) return e;
         return hipEventCreate(&ev1);
     }
     void drop_graph() {
-        if (gexec) (void)hipGraphExecDestroy(gexec);
-        if (graph) (void)hipGraphDestroy(graph);
-        gexec = nullptr;
-        graph = nullptr;
+        for (int s = 0; s < NSTAGES; ++s) {
+            if (gexec[s]) (void)hipGraphExecDestroy(gexec[s]);
+            if (graph[s]) (void)hipGraphDestroy(graph[s]);
+            gexec[s] = nullptr;
+            graph[s] = nullptr;
+        }
         have_graph = false;
     }
     void destroy() {
@@ -108,6 +116,8 @@ struct Workspace {
         h_small.release();
         if (ev0) (void)hipEventDestroy(ev0);
         if (ev1) (void)hipEventDestroy(ev1);
+        for (auto &x : ek)
+            if (x) (void)hipEventDestroy(x);
         if (stream) (void)hipStreamDestroy(stream);
         stream = nullptr;
     }
@@ -342,26 +352,59 @@ int launch(vor_ctx *ctx, Workspace &ws, const std::vector<HostSet> &sets, bool v
     a.exact_only = exact_only;
     a.with_vertices = vertices;
     a.check_symmetry = symmetry;
+    a.time_stages = (ctx->opts.flags & VOR_TIME_KERNELS) != 0;
 
+    ws.last_timed = a.time_stages;
     if ((e = hipEventRecord(ws.ev0, ws.stream)) != hipSuccess) return VOR_E_DEVICE;
-    if (use_graph) {
+    // one graph for the whole pipeline, or one per stage with events between the stages
+    const int ngraphs = a.time_stages ? NSTAGES : 1;
+    bool launched = false;
+    if (use_graph && !ws.graph_broken) {
         if (!ws.have_graph || std::memcmp(&ws.gkey, &a, sizeof(a)) != 0) {
             ws.drop_graph();
-            e = hipStreamBeginCapture(ws.stream, hipStreamCaptureModeThreadLocal);
-            if (e != hipSuccess) return VOR_E_DEVICE;
-            launch_pipeline(a, ws.stream);
-            e = hipStreamEndCapture(ws.stream, &ws.graph);
-            if (e != hipSuccess) return VOR_E_DEVICE;
-            e = hipGraphInstantiate(&ws.gexec, ws.graph, nullptr, nullptr, 0);
-            if (e != hipSuccess) return VOR_E_DEVICE;
-            ws.gkey = a;
-            ws.have_graph = true;
+            bool ok = true;
+            for (int g = 0; g < ngraphs && ok; ++g) {
+                ok = hipStreamBeginCapture(ws.stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+                if (!ok) break;
+                if (ngraphs == 1) launch_pipeline(a, ws.stream);
+                else launch_stage(a, ws.stream, g);
+                ok = hipStreamEndCapture(ws.stream, &ws.graph[g]) == hipSuccess;
+                if (ok)
+                    ok = hipGraphInstantiate(&ws.gexec[g], ws.graph[g], nullptr, nullptr, 0) ==
+                         hipSuccess;
+            }
+            if (ok) {
+                ws.gkey = a;
+                ws.have_graph = true;
+            } else {
+                // capture not available for this sequence: launch the kernels directly from now on
+                (void)hipGetLastError();
+                ws.drop_graph();
+                ws.graph_broken = true;
+            }
         }
-        if ((e = hipGraphLaunch(ws.gexec, ws.stream)) != hipSuccess) return VOR_E_DEVICE;
-    } else {
-        launch_pipeline(a, ws.stream);
+        if (ws.have_graph) {
+            for (int g = 0; g < ngraphs; ++g) {
+                if (a.time_stages && (e = hipEventRecord(ws.ek[g], ws.stream)) != hipSuccess)
+                    return VOR_E_DEVICE;
+                if ((e = hipGraphLaunch(ws.gexec[g], ws.stream)) != hipSuccess) return VOR_E_DEVICE;
+            }
+            if (a.time_stages && (e = hipEventRecord(ws.ek[NSTAGES], ws.stream)) != hipSuccess)
+                return VOR_E_DEVICE;
+            launched = true;
+        }
+    }
+    if (!launched) {
+        for (int g = 0; g < NSTAGES; ++g) {
+            if (a.time_stages && (e = hipEventRecord(ws.ek[g], ws.stream)) != hipSuccess)
+                return VOR_E_DEVICE;
+            launch_stage(a, ws.stream, g);
+        }
+        if (a.time_stages && (e = hipEventRecord(ws.ek[NSTAGES], ws.stream)) != hipSuccess)
+            return VOR_E_DEVICE;
         if ((e = hipGetLastError()) != hipSuccess) return VOR_E_DEVICE;
     }
+    ws.used_graph = launched;
     if ((e = hipEventRecord(ws.ev1, ws.stream)) != hipSuccess) return VOR_E_DEVICE;
     // small summary: status words, stats, totals
     if (ws.h_small.ensure(4 * SMALL_INTS + 8 * SL_COUNT + 16) != hipSuccess) return VOR_E_NOMEM;
@@ -383,7 +426,8 @@ struct Summary {
     int status;
     unsigned long long stats[SL_COUNT];
     long long edges, dels;
-    float ms;
+    float ms, cells_ms, exact_ms, stage_ms[NSTAGES];
+    bool graph;
 };
 
 Summary read_summary(Workspace &ws) {
@@ -394,8 +438,17 @@ Summary read_summary(Workspace &ws) {
     std::memcpy(s.stats, hs + 4 * SMALL_INTS, 8 * SL_COUNT);
     s.edges = *(const int *)(hs + 4 * SMALL_INTS + 8 * SL_COUNT);
     s.dels = *(const int *)(hs + 4 * SMALL_INTS + 8 * SL_COUNT + 4);
-    s.ms = 0.0f;
+    s.ms = s.cells_ms = s.exact_ms = 0.0f;
+    for (auto &x : s.stage_ms) x = 0.0f;
     (void)hipEventElapsedTime(&s.ms, ws.ev0, ws.ev1);
+    if (ws.last_timed) {
+        for (int g = 0; g < NSTAGES; ++g)
+            if (hipEventElapsedTime(&s.stage_ms[g], ws.ek[g], ws.ek[g + 1]) != hipSuccess)
+                s.stage_ms[g] = -1.0f;
+        s.cells_ms = s.stage_ms[1];
+        s.exact_ms = s.stage_ms[2];
+    }
+    s.graph = ws.used_graph;
     return s;
 }
 
@@ -408,6 +461,7 @@ void fill_stats(vor_stats &st, const Summary &s) {
     st.asym_pairs = s.stats[SL_ASYM];
     st.shells = s.stats[SL_SHELLS];
     st.edges = s.stats[SL_EDGES];
+    st.vertex_tests = s.stats[SL_VTESTS];
 }
 
 // Copy the results of every set back to host ResultBoxes (after the stream is idle).
@@ -449,6 +503,11 @@ int collect_host(Workspace &ws, const PipeArgs &a, const std::vector<SetDesc> &d
         r->del = box->del.data();
         fill_stats(r->stats, sm);
         r->device_ms = sm.ms;
+        r->cells_ms = sm.cells_ms;
+        r->exact_ms = sm.exact_ms;
+        r->grid_ms = sm.stage_ms[0];
+        r->emit_ms = sm.stage_ms[3];
+        r->graph_replayed = sm.graph ? 1 : 0;
         r->status = VOR_OK;
         outs[i] = r;
     }
@@ -484,6 +543,11 @@ int run_sync(vor_ctx *ctx, Workspace &ws, const std::vector<HostSet> &sets,
         r->del = a.del;
         fill_stats(r->stats, sm);
         r->device_ms = sm.ms;
+        r->cells_ms = sm.cells_ms;
+        r->exact_ms = sm.exact_ms;
+        r->grid_ms = sm.stage_ms[0];
+        r->emit_ms = sm.stage_ms[3];
+        r->graph_replayed = sm.graph ? 1 : 0;
         r->status = VOR_OK;
         outs.assign(1, r);
         return VOR_OK;

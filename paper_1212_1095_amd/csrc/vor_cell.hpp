@@ -29,7 +29,7 @@
 namespace vor {
 
 struct Counters {
-    uint32_t rays, nodes, evals, exact, shells;
+    uint32_t rays, nodes, evals, exact, shells, vtests;
 };
 
 struct ScanOut {
@@ -64,23 +64,38 @@ __device__ __forceinline__ ScanOut scan_f32(const Cell &C, const float2 *__restr
         const Line L = side_line(C, code);
         consider(key_lo_line((float)L.c, (float)L.nx, (float)L.ny, dx, dy), code, b);
     }
+    // One flat loop per lane over the candidates of shells 0, 1, 2, ...: a lane pays only for
+    // its own candidates, not for the longest bucket range among the lanes of its wave.
     float U = FINF, Uw = FINF;
-    int k = 0;
-    for (;; ++k) {
-        for_shell(C, bstart, C.bx, C.by, k, [&](int lo, int hi) {
-            K.evals += (uint32_t)(hi - lo);
-            for (int pos = lo; pos < hi; ++pos) {
-                const float2 a = sxy[pos];
-                const float ex = a.x - C.pxf, ey = a.y - C.pyf;
-                float key = key_lo_line(site_q(ex, ey), ex, ey, dx, dy);
-                if (EXCL) key = (pos == ex1 || pos == ex2) ? FINF : key;
-                consider(key, pos, b);
+    int k = 0, seg = 0, nseg = 1, pos, end;
+    seg_range(C, bstart, 0, 0, pos, end);
+    for (;;) {
+        if (pos < end) {
+            const float2 a = sxy[pos];
+            const float ex = a.x - C.pxf, ey = a.y - C.pyf;
+            float key = key_lo_line(site_q(ex, ey), ex, ey, dx, dy);
+            if (EXCL) key = (pos == ex1 || pos == ex2) ? FINF : key;
+            consider(key, pos, b);
+            ++pos;
+            ++K.evals;
+        }
+        bool stop = false;
+        while (pos >= end) {
+            if (++seg >= nseg) {   // shell k complete: does the block certify the endpoint?
+                K.shells++;
+                Uw = upper_of(C, sxy, b.w, dx, dy);
+                U = fminf(U, Uw);
+                if (block_certifies(C, k, fminf(U, tcap), dx, dy)) {
+                    stop = true;
+                    break;
+                }
+                ++k;
+                seg = 0;
+                nseg = 4 * k;
             }
-        });
-        K.shells++;
-        Uw = upper_of(C, sxy, b.w, dx, dy);
-        U = fminf(U, Uw);
-        if (block_certifies(C, k, fminf(U, tcap), dx, dy)) break;
+            seg_range(C, bstart, k, seg, pos, end);
+        }
+        if (stop) break;
     }
     return ScanOut{b, Uw, U, k};
 }
@@ -199,7 +214,6 @@ template <int MODE>
 __device__ __forceinline__ int ray(const Cell &C, const float2 *__restrict__ sxy,
                                    const int *__restrict__ bstart, const Dir &d, int64_t Den,
                                    int ex1, int ex2, Line &out, Counters &K) {
-    K.rays++;
     const bool vmode = Den > 0;
     float tu_hi = FINF, tu_lo = FINF;
     if (vmode) {
@@ -223,7 +237,8 @@ __device__ __forceinline__ int ray(const Cell &C, const float2 *__restrict__ sxy
         K.exact++;
         exact_scan<true>(C, sxy, bstart, d, s.kmax, vmode ? tu_hi : s.U, tu_hi, ex1, ex2, xb, K);
     }
-    if (!xb.have) return -1;
+    // no line other than the two through u is crossed: u is the endpoint (a vertex)
+    if (!xb.have) return vmode ? 1 : -1;
     // u is outside the cell iff some line is crossed before it: c_b / den_b < 1 / Den
     if (!vmode || (u128)xb.c * (u128)Den < xb.den) {
         out.id = xb.id;
@@ -281,6 +296,9 @@ __device__ __forceinline__ int run_cell(const Cell &C, const float2 *__restrict_
             const int r = ray<MODE>(C, sxy, bstart, d, Den, ex1, ex2, L3, K);
             if (r < 0) return -1;
             leaf = (r == 1);
+            // a shot ray (Lemma on shot rays) yields a corner; a ray that confirms a vertex
+            // is the in-cell test of the vertex
+            if (leaf) K.vtests++; else K.rays++;
         }
         if (phase < 3) {
             if (phase == 0) {

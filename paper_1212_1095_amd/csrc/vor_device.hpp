@@ -39,7 +39,7 @@ enum : int { ST_DOMAIN = 1, ST_DUP = 2, ST_CAPACITY = 4, ST_INTERNAL = 8 };
 // stats slots
 enum : int {
     SL_RAYS = 0, SL_NODES, SL_EVALS, SL_EXACT, SL_DEFERRED, SL_ASYM, SL_SHELLS, SL_EDGES,
-    SL_COUNT
+    SL_VTESTS, SL_COUNT
 };
 
 struct SetDesc {
@@ -230,6 +230,35 @@ __device__ __forceinline__ void for_shell(const Cell &S, const int *__restrict__
             const int b = base + y * S.gx + bx + k;
             f(bstart[b], bstart[b + 1]);
         }
+}
+
+// Segment `seg` of shell k as a sorted-position range [lo, hi): shell 0 is p's bucket; shell
+// k >= 1 has 4k segments: the bottom and top rows (2k+1 buckets, contiguous in row-major
+// bucket order), then the 2k-1 buckets of the left column and of the right column.  Parts
+// outside the grid are empty.
+__device__ __forceinline__ void seg_range(const Cell &C, const int *__restrict__ bstart, int k,
+                                          int seg, int &lo, int &hi) {
+    int row, xa, xb;
+    if (k == 0) {
+        row = C.by;
+        xa = xb = C.bx;
+    } else if (seg < 2) {
+        row = seg == 0 ? C.by - k : C.by + k;
+        xa = max(C.bx - k, 0);
+        xb = min(C.bx + k, C.gx - 1);
+    } else {
+        const int t = seg - 2;                 // 0 .. 4k-3
+        const bool right = t >= 2 * k - 1;
+        row = C.by - k + 1 + (right ? t - (2 * k - 1) : t);
+        xa = xb = right ? C.bx + k : C.bx - k;
+    }
+    if (row < 0 || row >= C.gy || xa < 0 || xb >= C.gx || xa > xb) {
+        lo = hi = 0;
+        return;
+    }
+    const int r = C.boff + row * C.gx;
+    lo = bstart[r + xa];
+    hi = bstart[r + xb + 1];
 }
 
 // True when every site closer than p to the point y = p + (T/2) d_s (doubled-frame ray

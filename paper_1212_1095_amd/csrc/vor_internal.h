@@ -41,6 +41,7 @@ struct PipeArgs {
     unsigned long long *stats;
     int block;
     bool exact_only, with_vertices, check_symmetry;
+    bool time_stages;           // HIP events between the stages (one graph per stage)
 
     int *status() const { return small; }
     int *status_rw() const { return small; }
@@ -49,6 +50,9 @@ struct PipeArgs {
     int *poolcnt() const { return small + 3; }
 };
 
+// stages: 0 grid build, 1 filtered cell pass, 2 exact / deep passes, 3 CSR and Delaunay
+constexpr int NSTAGES = 4;
+void launch_stage(const PipeArgs &a, hipStream_t st, int stage);
 void launch_pipeline(const PipeArgs &a, hipStream_t st);
 long long scan_tmp_ints(long long n);
 

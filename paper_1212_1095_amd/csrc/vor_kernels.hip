@@ -121,6 +121,7 @@ __device__ __forceinline__ void reduce_stats(const Counters &K, uint32_t edges, 
     atomicAdd(&sh[SL_SHELLS], (unsigned long long)K.shells);
     atomicAdd(&sh[SL_EDGES], (unsigned long long)edges);
     atomicAdd(&sh[SL_DEFERRED], (unsigned long long)deferred);
+    atomicAdd(&sh[SL_VTESTS], (unsigned long long)K.vtests);
     __syncthreads();
     if (threadIdx.x < SL_COUNT && sh[threadIdx.x]) atomicAdd(&stats[threadIdx.x], sh[threadIdx.x]);
 }
@@ -139,7 +140,7 @@ __global__ __launch_bounds__(BLOCK) void k_cells_fast(
     if (threadIdx.x < SL_COUNT) sh[threadIdx.x] = 0;
     __syncthreads();
     const int pos = xcd_block(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
-    Counters K{0, 0, 0, 0, 0};
+    Counters K{0, 0, 0, 0, 0, 0};
     uint32_t edges = 0, deferred = 0;
     if (pos < total) {
         const SetDesc S = sets[find_set(set_off, nsets, pos)];
@@ -187,7 +188,7 @@ __global__ __launch_bounds__(64) void k_cells_exact(
     const int nw = gridDim.x * blockDim.x;
     const int nq = *qcount;
     int *area = wbuf + (size_t)w * 2 * dcap;
-    Counters K{0, 0, 0, 0, 0};
+    Counters K{0, 0, 0, 0, 0, 0};
     uint32_t edges = 0;
     for (int qi = w; qi < nq; qi += nw) {
         const int pos = queue[qi];
@@ -453,8 +454,9 @@ void launch_scan(const int *in, long long n, int *out, int *tmp, const int *stat
 
 long long scan_tmp_ints(long long n) { return (long long)nblk(n, SCAN_TILE) + 1; }
 
-void launch_pipeline(const PipeArgs &a, hipStream_t st) {
+void launch_stage(const PipeArgs &a, hipStream_t st, int stage) {
     const int T = a.total;
+    if (stage == 0) {
     // 1. clear counters (no memset nodes: the sequence is captured as a graph)
     {
         const long long n = a.gtot;
@@ -469,6 +471,7 @@ void launch_pipeline(const PipeArgs &a, hipStream_t st) {
                                              a.bcnt, a.sxy, a.sid);
     k_dups<<<nblk(T, 256), 256, 0, st>>>(a.sets, a.nsets, a.set_off, T, a.sxy, a.bstart,
                                           a.status());
+    } else if (stage == 1) {
     // 3. cells
     if (a.exact_only) {
         k_queue_all<<<nblk(T, 256), 256, 0, st>>>(T, a.queue, a.qcount(), a.status());
@@ -488,6 +491,7 @@ void launch_pipeline(const PipeArgs &a, hipStream_t st) {
                                                  a.bstart, T, a.ocnt, a.olines, a.ovf, a.queue,
                                                  a.qcount(), a.stats, a.status());
     }
+    } else if (stage == 2) {
     if (a.exact_only)
         k_cells_exact<2><<<a.exact_blocks, 64, 0, st>>>(
             a.sets, a.nsets, a.set_off, a.sxy, a.sid, a.bstart, a.ocnt, a.olines, a.ovf, a.pool,
@@ -509,6 +513,7 @@ void launch_pipeline(const PipeArgs &a, hipStream_t st) {
             a.sets, a.nsets, a.set_off, a.sxy, a.sid, a.bstart, a.ocnt, a.olines, a.ovf, a.pool,
             a.poolcnt(), a.poolcap, a.queue2, a.qcount2(), nullptr, nullptr, a.wbuf2, DCAP2,
             a.stats, a.status_rw());
+    } else {
     // 4. CSR
     launch_scan(a.ocnt, T, a.cell_off, a.scan_tmp, a.status(), 1, st);
     k_fill<<<nblk(T, 256), 256, 0, st>>>(a.sets, a.nsets, a.set_off, T, a.ocnt, a.olines, a.ovf,
@@ -521,6 +526,11 @@ void launch_pipeline(const PipeArgs &a, hipStream_t st) {
     if (a.check_symmetry)
         k_symmetry<<<nblk(T, 256), 256, 0, st>>>(a.sets, a.nsets, a.set_off, T, a.cell_off, a.nbr,
                                                   a.stats, a.status());
+    }
+}
+
+void launch_pipeline(const PipeArgs &a, hipStream_t st) {
+    for (int s = 0; s < NSTAGES; ++s) launch_stage(a, st, s);
 }
 
 }  // namespace vor

@@ -133,8 +133,12 @@ def test_paper_counter_bounds(ctx):
     E = int(r.cell_off[-1])
     assert E <= 10 * ps.n
     assert r.stats.edges == E
-    assert r.stats.rays <= 11 * ps.n
-    assert r.stats.nodes <= 2 * E
+    # counters include the abandoned filtered attempt of each deferred cell
+    slack = 64 * r.stats.deferred_cells
+    assert r.stats.rays <= 11 * ps.n + slack
+    assert r.stats.nodes <= 2 * E + slack
+    # the projector confirms each vertex of a cell once: one test per stored vertex
+    assert r.stats.vertex_tests <= E + slack
     say(f"  rays/cell={r.stats.rays / ps.n:.3f} nodes/cell={r.stats.nodes / ps.n:.3f} "
         f"evals/cell={r.stats.evals / ps.n:.1f} exact={r.stats.exact_decisions} "
         f"deferred={r.stats.deferred_cells}")
