@@ -157,10 +157,12 @@ const char *vor_strerror(int status);
 
 /* Tuning knobs (chosen by the autotuner).  sites_per_bucket: target mean bucket occupancy
  * of the uniform grid (Method 11.5); block: threads per workgroup of the cell kernel
- * (64, 128 or 256). */
+ * (64, 128 or 256); block_halfwidth: h, the cell's (2h+1)^2 bucket block scanned before
+ * further shells (1..16, 0 = round(2 / sqrt(sites_per_bucket))). */
 typedef struct {
     float sites_per_bucket;
     int32_t block;
+    int32_t block_halfwidth;
 } vor_tuning;
 
 int vor_set_tuning(vor_ctx *ctx, const vor_tuning *t);

@@ -53,7 +53,8 @@ class vor_result(C.Structure):
 
 
 class vor_tuning(C.Structure):
-    _fields_ = [("sites_per_bucket", C.c_float), ("block", C.c_int32)]
+    _fields_ = [("sites_per_bucket", C.c_float), ("block", C.c_int32),
+                ("block_halfwidth", C.c_int32)]
 
 
 _lib = None
@@ -282,15 +283,15 @@ def vor_ticket_times(ctx, ticket: int):
     return a.value, b.value, c.value
 
 
-def vor_set_tuning(ctx, sites_per_bucket: float, block: int) -> None:
-    t = vor_tuning(sites_per_bucket, block)
+def vor_set_tuning(ctx, sites_per_bucket: float, block: int, block_halfwidth: int = 0) -> None:
+    t = vor_tuning(sites_per_bucket, block, block_halfwidth)
     _check(lib().vor_set_tuning(ctx, C.byref(t)), "vor_set_tuning")
 
 
 def vor_get_tuning(ctx):
     t = vor_tuning()
     _check(lib().vor_get_tuning(ctx, C.byref(t)), "vor_get_tuning")
-    return float(t.sites_per_bucket), int(t.block)
+    return float(t.sites_per_bucket), int(t.block), int(t.block_halfwidth)
 
 
 class Context:
@@ -317,8 +318,8 @@ class Context:
     def times(self, ticket):
         return vor_ticket_times(self.h, ticket)
 
-    def tune(self, sites_per_bucket, block):
-        vor_set_tuning(self.h, sites_per_bucket, block)
+    def tune(self, sites_per_bucket, block, block_halfwidth=0):
+        vor_set_tuning(self.h, sites_per_bucket, block, block_halfwidth)
 
     def close(self):
         if self.h:

@@ -1,0 +1,103 @@
+"""Autotuner: picks the grid density, block half-width and workgroup size of the cell kernel
+for a workload shape by timing the C-ABI pipeline on the device (results are exact whatever
+the parameters; only the speed changes).
+
+    python -m paper_1212_1095_amd.autotune --n 1048576 --box 16777216 [--out tuning.json]
+
+The table maps "log2(n)" (rounded) and a distribution tag to the best (sites_per_bucket,
+block, block_halfwidth).  ``best_params`` looks a shape up (nearest log2 n).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+TABLE = os.path.join(HERE, "tuning.json")
+
+DEFAULT_GRID = [(0.5, 1), (0.7, 1), (1.0, 1), (1.5, 1), (2.0, 1), (0.35, 2), (0.5, 2), (1.0, 2)]
+DEFAULT_BLOCKS = (256,)
+
+
+def time_config(ctx, xd, yd, n, box, rho, h, block, reps=5, warmup=2):
+    import torch
+    ctx.tune(rho, block, h)
+    for _ in range(warmup):
+        ctx.compute((xd.data_ptr(), n), (yd.data_ptr(), n), box, device_ptrs=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        r = ctx.compute((xd.data_ptr(), n), (yd.data_ptr(), n), box, device_ptrs=True)
+    torch.cuda.synchronize()
+    return 1000.0 * (time.perf_counter() - t0) / reps, r
+
+
+def sweep(x, y, box, grid=DEFAULT_GRID, blocks=DEFAULT_BLOCKS, reps=5, log=print):
+    import numpy as np
+    import torch
+    from ._binding import Context, VOR_RESULT_DEVICE, VOR_TIME_KERNELS
+    n = int(np.asarray(x).shape[0])
+    xd = torch.from_numpy(np.ascontiguousarray(x, dtype=np.int32)).cuda()
+    yd = torch.from_numpy(np.ascontiguousarray(y, dtype=np.int32)).cuda()
+    rows = []
+    with Context(flags=VOR_RESULT_DEVICE | VOR_TIME_KERNELS) as ctx:
+        for rho, h in grid:
+            for block in blocks:
+                ms, r = time_config(ctx, xd, yd, n, box, rho, h, block, reps)
+                row = {"sites_per_bucket": rho, "block_halfwidth": h, "block": block, "ms": ms,
+                       "cells_ms": r.cells_ms, "exact_ms": r.exact_ms,
+                       "evals_per_cell": r.stats.evals / n, "shells_per_cell": r.stats.shells / n}
+                rows.append(row)
+                log(json.dumps(row))
+    rows.sort(key=lambda r: r["ms"])
+    return rows
+
+
+def load_table(path=TABLE) -> dict:
+    if os.path.exists(path):
+        with open(path) as f:
+            return json.load(f)
+    return {}
+
+
+def best_params(n: int, dist: str = "uniform", path=TABLE):
+    """(sites_per_bucket, block, block_halfwidth) for the nearest tuned log2(n), or None."""
+    t = load_table(path).get(dist, {})
+    if not t:
+        return None
+    key = min(t.keys(), key=lambda k: abs(int(k) - round(math.log2(max(n, 1)))))
+    e = t[key]
+    return e["sites_per_bucket"], e["block"], e["block_halfwidth"]
+
+
+def main():
+    sys.path.insert(0, os.path.dirname(HERE))
+    import sitegen
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--n", type=int, default=1 << 20)
+    ap.add_argument("--box", type=int, default=1 << 24)
+    ap.add_argument("--dist", default="uniform", choices=["uniform", "clustered", "lattice"])
+    ap.add_argument("--seed", type=int, default=2)
+    ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--out", default=None, help="merge the best entry into this table")
+    a = ap.parse_args()
+    gen = {"uniform": sitegen.uniform, "clustered": sitegen.clustered,
+           "lattice": sitegen.lattice}[a.dist]
+    ps = gen(a.n, a.box, seed=a.seed)
+    rows = sweep(ps.x, ps.y, ps.box, reps=a.reps, log=lambda s: print(s, flush=True))
+    best = rows[0]
+    print(json.dumps({"best": best}), flush=True)
+    if a.out:
+        t = load_table(a.out)
+        t.setdefault(a.dist, {})[str(round(math.log2(a.n)))] = {
+            k: best[k] for k in ("sites_per_bucket", "block", "block_halfwidth", "ms")}
+        with open(a.out, "w") as f:
+            json.dump(t, f, indent=1, sort_keys=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -143,7 +143,7 @@ int check_set(const vor_set *s) {
 }
 
 // Uniform grid of Method 11.5 with about `rho` sites per square bucket.
-void choose_grid(const vor_box &b, uint32_t n, float rho, SetDesc &d) {
+void choose_grid(const vor_box &b, uint32_t n, float rho, int hw, SetDesc &d) {
     const double W = (double)b.x1 - b.x0, H = (double)b.y1 - b.y0;
     double s = std::sqrt(W * H * (double)rho / (double)n);
     long long si = (long long)std::ceil(s);
@@ -158,6 +158,9 @@ void choose_grid(const vor_box &b, uint32_t n, float rho, SetDesc &d) {
     d.s = (int32_t)si;
     d.gx = (int32_t)std::max(1LL, gx);
     d.gy = (int32_t)std::max(1LL, gy);
+    // block of shells 0..h scanned first: about two site spacings in each direction
+    const double h = hw > 0 ? (double)hw : std::round(2.0 / std::sqrt((double)rho));
+    d.h = (int32_t)std::max(1.0, std::min(h, 16.0));
 }
 
 int map_status(int st) {
@@ -200,7 +203,7 @@ struct Request {
 struct vor_ctx {
     int device = 0;
     vor_opts opts{};
-    vor_tuning tune{1.0f, 256};
+    vor_tuning tune{1.0f, 256, 0};
     Workspace ws;            // vor_compute / vor_compute_batch
     std::mutex mu;           // serialises vor_compute*
     bool use_graph = true;
@@ -250,7 +253,7 @@ int launch(vor_ctx *ctx, Workspace &ws, const std::vector<HostSet> &sets, bool v
         d.y0 = s.box.y0;
         d.n = (int32_t)s.n;
         d.site_off = (int32_t)total;
-        choose_grid(s.box, s.n, ctx->tune.sites_per_bucket, d);
+        choose_grid(s.box, s.n, ctx->tune.sites_per_bucket, ctx->tune.block_halfwidth, d);
         d.bucket_off = (int32_t)gtot;
         set_off[i] = (int)total;
         total += s.n;
@@ -746,6 +749,7 @@ int vor_set_tuning(vor_ctx *ctx, const vor_tuning *t) {
     if (!ctx || !t) return VOR_E_INVAL;
     if (!(t->sites_per_bucket >= 0.0625f && t->sites_per_bucket <= 64.0f)) return VOR_E_INVAL;
     if (t->block != 64 && t->block != 128 && t->block != 256) return VOR_E_INVAL;
+    if (t->block_halfwidth < 0 || t->block_halfwidth > 16) return VOR_E_INVAL;
     std::lock_guard<std::mutex> lk(ctx->mu);
     ctx->tune = *t;
     return VOR_OK;
@@ -824,7 +828,7 @@ int vor_submit(vor_ctx *ctx, const vor_set *set, uint64_t *ticket) {
     r->box = set->box;
     r->t_submit = now_s();
     SetDesc d{};
-    choose_grid(set->box, set->n, ctx->tune.sites_per_bucket, d);
+    choose_grid(set->box, set->n, ctx->tune.sites_per_bucket, ctx->tune.block_halfwidth, d);
     r->footprint = footprint_bytes(set->n, (uint64_t)d.gx * d.gy,
                                    !(ctx->opts.flags & VOR_NO_VERTICES));
     {

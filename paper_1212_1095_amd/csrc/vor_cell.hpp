@@ -36,7 +36,7 @@ struct ScanOut {
     Best b;
     float Uw;   // upper bound key of the final winner
     float U;    // smallest upper bound seen
-    int kmax;   // last shell scanned
+    Rect A;     // the scanned rectangle (it contains S_I of the endpoint)
 };
 
 // Upper bound key of candidate w (sorted position or side code).
@@ -55,8 +55,8 @@ __device__ __forceinline__ float upper_of(const Cell &C, const float2 *__restric
 // (or the point at tcap, whichever is nearer).  Candidates ex1 / ex2 are skipped when EXCL.
 template <bool EXCL>
 __device__ __forceinline__ ScanOut scan_f32(const Cell &C, const float2 *__restrict__ sxy,
-                            const int *__restrict__ bstart, float dx, float dy, int ex1, int ex2,
-                            float tcap, Counters &K) {
+                                            const int *__restrict__ bstart, float dx, float dy,
+                                            int ex1, int ex2, float tcap, Counters &K) {
     Best b{FINF, FINF, 0};
 #pragma unroll
     for (int code = -1; code >= -4; --code) {
@@ -64,40 +64,41 @@ __device__ __forceinline__ ScanOut scan_f32(const Cell &C, const float2 *__restr
         const Line L = side_line(C, code);
         consider(key_lo_line((float)L.c, (float)L.nx, (float)L.ny, dx, dy), code, b);
     }
-    // One flat loop per lane over the candidates of shells 0, 1, 2, ...: a lane pays only for
-    // its own candidates, not for the longest bucket range among the lanes of its wave.
-    float U = FINF, Uw = FINF;
-    int k = 0, seg = 0, nseg = 1, pos, end;
-    seg_range(C, bstart, 0, 0, pos, end);
+    // Method 11.6, one flat loop per lane (a lane pays only for its own candidates): the
+    // cell's block of shells 0..h is a warm start that bounds the endpoint by y; then the
+    // scanned rectangle grows towards the integer rectangle S_I[y, |y - p|] until it contains
+    // it.  The rectangles of later, nearer bounds nest inside the earlier ones, so the final
+    // scanned rectangle certifies the endpoint.
+    RowWalk wk;
+    wk.start(block_rect(C), Rect{1, 0, 1, 0});
+    float U = FINF;
     for (;;) {
-        if (pos < end) {
+        if (wk.pos < wk.end) {
+            const int pos = wk.pos++;
             const float2 a = sxy[pos];
             const float ex = a.x - C.pxf, ey = a.y - C.pyf;
             float key = key_lo_line(site_q(ex, ey), ex, ey, dx, dy);
             if (EXCL) key = (pos == ex1 || pos == ex2) ? FINF : key;
             consider(key, pos, b);
-            ++pos;
             ++K.evals;
+            continue;
         }
-        bool stop = false;
-        while (pos >= end) {
-            if (++seg >= nseg) {   // shell k complete: does the block certify the endpoint?
-                K.shells++;
-                Uw = upper_of(C, sxy, b.w, dx, dy);
-                U = fminf(U, Uw);
-                if (block_certifies(C, k, fminf(U, tcap), dx, dy)) {
-                    stop = true;
-                    break;
-                }
-                ++k;
-                seg = 0;
-                nseg = 4 * k;
-            }
-            seg_range(C, bstart, k, seg, pos, end);
-        }
-        if (stop) break;
+        if (wk.next(C, bstart)) continue;
+        // rectangle wk.O scanned: the rectangle needed by the current bound
+        K.shells++;
+        U = fminf(U, upper_of(C, sxy, b.w, dx, dy));
+        const Rect R = need_rect(C, fminf(U, tcap), dx, dy);
+        if (rect_inside(R, wk.O)) break;
+        wk.start(grow_rect(wk.O, R), wk.O);
     }
-    return ScanOut{b, Uw, U, k};
+    const float Uw = upper_of(C, sxy, b.w, dx, dy);
+    U = fminf(U, Uw);
+    ScanOut o;
+    o.b = b;
+    o.Uw = Uw;
+    o.U = U;
+    o.A = wk.O;
+    return o;
 }
 
 // ------------------------------------------------------------------------------ exact argmin
@@ -137,12 +138,13 @@ __device__ __forceinline__ float x_upper(const XBest &b, const Dir &d) {
     return (float)ldexp(t, d.sigma) * CERT_UP;
 }
 
-// Exact argmin over the shells 0..kmax (kmax >= 0), or shell by shell until the exact winner
-// certifies (kmax < 0).  With FILTER only candidates whose FP32 lower bound is <= Tlim count.
+// Exact argmin over the rectangle an FP32 scan certified (prev), or over a block grown
+// towards the certified rectangle of the exact winner (prev == null: exact-only precision).  With FILTER only candidates whose FP32 lower bound is <= Tlim count.
 template <bool FILTER>
 __device__ __forceinline__ void exact_scan(const Cell &C, const float2 *__restrict__ sxy,
-                           const int *__restrict__ bstart, const Dir &d, int kmax, float Tlim,
-                           float tcap, int ex1, int ex2, XBest &b, Counters &K) {
+                                           const int *__restrict__ bstart, const Dir &d,
+                                           const ScanOut *prev, float Tlim, float tcap, int ex1,
+                                           int ex2, XBest &b, Counters &K) {
     b.have = false;
     const float lim = Tlim * CERT_UP;
     for (int code = -1; code >= -4; --code) {
@@ -153,26 +155,28 @@ __device__ __forceinline__ void exact_scan(const Cell &C, const float2 *__restri
             continue;
         x_consider(b, code, L.nx, L.ny, L.c, d);
     }
-    for (int k = 0;; ++k) {
-        for_shell(C, bstart, C.bx, C.by, k, [&](int lo, int hi) {
-            if (!FILTER) K.evals += (uint32_t)(hi - lo);
-            for (int pos = lo; pos < hi; ++pos) {
-                if (pos == ex1 || pos == ex2) continue;
-                const float2 a = sxy[pos];
-                const float ex = a.x - C.pxf, ey = a.y - C.pyf;
-                if (FILTER && !(key_lo_line(site_q(ex, ey), ex, ey, d.fx, d.fy) * CERT_DN <= lim))
-                    continue;
-                const int nx = (int)a.x - C.px, ny = (int)a.y - C.py;
-                if ((nx | ny) == 0) continue;   // p itself
-                x_consider(b, pos, nx, ny, (int64_t)nx * nx + (int64_t)ny * ny, d);
-            }
-        });
-        if (kmax >= 0) {
-            if (k >= kmax) break;
-        } else {
-            K.shells++;
-            if (block_certifies(C, k, fminf(x_upper(b, d), tcap), d.fx, d.fy)) break;
+    RowWalk wk;
+    wk.start(prev ? prev->A : block_rect(C), Rect{1, 0, 1, 0});
+    for (;;) {
+        if (wk.pos < wk.end) {
+            const int pos = wk.pos++;
+            if (pos == ex1 || pos == ex2) continue;
+            const float2 a = sxy[pos];
+            const float ex = a.x - C.pxf, ey = a.y - C.pyf;
+            if (FILTER && !(key_lo_line(site_q(ex, ey), ex, ey, d.fx, d.fy) * CERT_DN <= lim))
+                continue;
+            if (!FILTER) ++K.evals;
+            const int nx = (int)a.x - C.px, ny = (int)a.y - C.py;
+            if ((nx | ny) == 0) continue;   // p itself
+            x_consider(b, pos, nx, ny, (int64_t)nx * nx + (int64_t)ny * ny, d);
+            continue;
         }
+        if (wk.next(C, bstart)) continue;
+        if (prev) break;   // the FP32 scan's rectangle already certifies the endpoint
+        K.shells++;
+        const Rect R = need_rect(C, fminf(x_upper(b, d), tcap), d.fx, d.fy);
+        if (rect_inside(R, wk.O)) break;
+        wk.start(grow_rect(wk.O, R), wk.O);
     }
 }
 
@@ -223,7 +227,7 @@ __device__ __forceinline__ int ray(const Cell &C, const float2 *__restrict__ sxy
     }
     XBest xb;
     if (MODE == 2) {
-        exact_scan<false>(C, sxy, bstart, d, -1, FINF, tu_hi, ex1, ex2, xb, K);
+        exact_scan<false>(C, sxy, bstart, d, nullptr, FINF, tu_hi, ex1, ex2, xb, K);
     } else {
         const ScanOut s = vmode ? scan_f32<true>(C, sxy, bstart, d.fx, d.fy, ex1, ex2, tu_hi, K)
                                 : scan_f32<false>(C, sxy, bstart, d.fx, d.fy, ex1, ex2, FINF, K);
@@ -235,7 +239,7 @@ __device__ __forceinline__ int ray(const Cell &C, const float2 *__restrict__ sxy
         }
         if (MODE == 0) return -1;
         K.exact++;
-        exact_scan<true>(C, sxy, bstart, d, s.kmax, vmode ? tu_hi : s.U, tu_hi, ex1, ex2, xb, K);
+        exact_scan<true>(C, sxy, bstart, d, &s, vmode ? tu_hi : s.U, tu_hi, ex1, ex2, xb, K);
     }
     // no line other than the two through u is crossed: u is the endpoint (a vertex)
     if (!xb.have) return vmode ? 1 : -1;

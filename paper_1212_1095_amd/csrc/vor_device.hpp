@@ -50,6 +50,7 @@ struct SetDesc {
     int32_t gx, gy;      // bucket grid
     int32_t s;           // bucket side
     int32_t bucket_off;  // first global bucket of the set
+    int32_t h;           // block half-width in buckets (shells 0..h scanned first)
 };
 
 // ------------------------------------------------------------------------------ FP32 filter
@@ -143,6 +144,7 @@ struct Line {
 
 struct Cell {       // per-cell constants
     int gx, gy, s, boff;  // the set's bucket grid
+    int h;                // half-width (in buckets) of the block scanned first
     float pxf, pyf; // p, relative to the box origin (exact floats)
     int px, py;
     int bx, by;     // p's bucket
@@ -260,6 +262,99 @@ __device__ __forceinline__ void seg_range(const Cell &C, const int *__restrict__
     lo = bstart[r + xa];
     hi = bstart[r + xb + 1];
 }
+
+// Bucket rectangle [x0, x1] x [y0, y1] (inclusive; empty when x0 > x1 or y0 > y1).
+struct Rect {
+    int x0, x1, y0, y1;
+};
+
+__device__ __forceinline__ bool rect_inside(const Rect &a, const Rect &b) {
+    return a.x0 >= b.x0 && a.x1 <= b.x1 && a.y0 >= b.y0 && a.y1 <= b.y1;
+}
+
+// The integer rectangle S_I[y, |y - p|] of eq. (S_I), in buckets and clipped to the grid, for
+// y = p + (T/2) d_s with T an upper bound of the endpoint parameter: by the lemma on sites in
+// the large square every site that is not farther from y than p lies in it, and the rectangles
+// of the points of [p, y] nest inside it.  A small margin (>= 2 coordinate units) keeps the
+// FP32 evaluation conservative; an infinite or undefined T gives the whole grid.
+__device__ __forceinline__ Rect need_rect(const Cell &C, float T, float dx, float dy) {
+    const float Tu = T * CERT_UP;
+    const float hx = 0.5f * Tu * dx, hy = 0.5f * Tu * dy;
+    const float yx = C.pxf + hx, yy = C.pyf + hy;
+    const float r = sqrtf(hx * hx + hy * hy);
+    Rect R{0, C.gx - 1, 0, C.gy - 1};
+    if (!(r < 1.0e30f) || !(fabsf(yx) < 1.0e30f) || !(fabsf(yy) < 1.0e30f)) return R;
+    const float M = (r + fabsf(yx) + fabsf(yy)) * 1.0e-5f + 2.0f;
+    const float inv = 1.0f / (float)C.s;
+    const float mx = (float)(C.gx - 1), my = (float)(C.gy - 1);
+    R.x0 = (int)fminf(fmaxf(floorf((yx - r - M) * inv), 0.0f), mx);
+    R.x1 = (int)fminf(fmaxf(floorf((yx + r + M) * inv), 0.0f), mx);
+    R.y0 = (int)fminf(fmaxf(floorf((yy - r - M) * inv), 0.0f), my);
+    R.y1 = (int)fminf(fmaxf(floorf((yy + r + M) * inv), 0.0f), my);
+    return R;
+}
+
+// The cell's first block: shells 0..h around p's bucket, clipped to the grid.
+__device__ __forceinline__ Rect block_rect(const Cell &C) {
+    return Rect{max(C.bx - C.h, 0), min(C.bx + C.h, C.gx - 1), max(C.by - C.h, 0),
+                min(C.by + C.h, C.gy - 1)};
+}
+
+// The next scanned rectangle: the bounding box of the scanned rectangle A and the needed
+// rectangle R, but at most A widened by its own size on each side (a poor first bound gives
+// a huge R; the region then grows geometrically and the bound tightens on the way).
+__device__ __forceinline__ Rect grow_rect(const Rect &A, const Rect &R) {
+    const int wx = A.x1 - A.x0 + 1, wy = A.y1 - A.y0 + 1;
+    return Rect{max(min(A.x0, R.x0), A.x0 - wx), min(max(A.x1, R.x1), A.x1 + wx),
+                max(min(A.y0, R.y0), A.y0 - wy), min(max(A.y1, R.y1), A.y1 + wy)};
+}
+
+// Walks the bucket rows of rectangle O minus rectangle I (I inside O, or empty) as
+// sorted-position segments: a row of O is one contiguous segment (row-major bucket order),
+// a row that crosses I splits into its parts left and right of I.  next() loads the next
+// segment into [pos, end) and returns false when O \ I is exhausted.
+struct RowWalk {
+    Rect O, I;
+    int row, part;
+    int pos, end;
+
+    __device__ __forceinline__ void start(Rect o, Rect i) {
+        O = o;
+        I = i;
+        row = o.y0;
+        part = 0;
+        pos = end = 0;
+    }
+    __device__ __forceinline__ bool next(const Cell &C, const int *__restrict__ bstart) {
+        if (row > O.y1) return false;
+        int xa, xb;
+        const int r = row;
+        if (row >= I.y0 && row <= I.y1) {
+            if (part == 0) {
+                xa = O.x0;
+                xb = min(O.x1, I.x0 - 1);
+                part = 1;
+            } else {
+                xa = max(O.x0, I.x1 + 1);
+                xb = O.x1;
+                part = 0;
+                ++row;
+            }
+        } else {
+            xa = O.x0;
+            xb = O.x1;
+            ++row;
+        }
+        if (xa > xb) {
+            pos = end = 0;
+        } else {
+            const int base = C.boff + r * C.gx;
+            pos = bstart[base + xa];
+            end = bstart[base + xb + 1];
+        }
+        return true;
+    }
+};
 
 // True when every site closer than p to the point y = p + (T/2) d_s (doubled-frame ray
 // parameter T, an upper bound of the endpoint) lies in the block of shells 0..k: the square

@@ -101,6 +101,7 @@ __device__ __forceinline__ Cell make_cell(const SetDesc &S, float2 p) {
     C.gy = S.gy;
     C.s = S.s;
     C.boff = S.bucket_off;
+    C.h = S.h;
     C.pxf = p.x;
     C.pyf = p.y;
     C.px = (int)p.x;
