@@ -53,51 +53,145 @@ __device__ __forceinline__ float upper_of(const Cell &C, const float2 *__restric
 
 // FP32 scan of the rays's candidates, shell by shell, until the block certifies the endpoint
 // (or the point at tcap, whichever is nearer).  Candidates ex1 / ex2 are skipped when EXCL.
+// Box sides the ray can leave through: at most one horizontal and one vertical side.
 template <bool EXCL>
-__device__ __forceinline__ ScanOut scan_f32(const Cell &C, const float2 *__restrict__ sxy,
+__device__ __forceinline__ void consider_sides(const Cell &C, float dx, float dy, int ex1, int ex2,
+                                               Best &b) {
+    const int sv = dy > 0.0f ? -3 : -1, sh = dx > 0.0f ? -2 : -4;
+    const Line Lv = side_line(C, sv), Lh = side_line(C, sh);
+    float kv = key_lo_line((float)Lv.c, (float)Lv.nx, (float)Lv.ny, dx, dy);
+    float kh = key_lo_line((float)Lh.c, (float)Lh.nx, (float)Lh.ny, dx, dy);
+    if (EXCL) {
+        kv = (sv == ex1 || sv == ex2) ? FINF : kv;
+        kh = (sh == ex1 || sh == ex2) ? FINF : kh;
+    }
+    consider(kv, sv, b);
+    consider(kh, sh, b);
+}
+
+template <bool EXCL>
+__device__ __forceinline__ void eval_site(const Cell &C, const float2 *__restrict__ sxy, int pos,
+                                          float dx, float dy, int ex1, int ex2, Best &b) {
+    const float2 a = sxy[pos];
+    const float ex = a.x - C.pxf, ey = a.y - C.pyf;
+    float key = key_lo_line(site_q(ex, ey), ex, ey, dx, dy);
+    if (EXCL) key = (pos == ex1 || pos == ex2) ? FINF : key;
+    consider(key, pos, b);
+}
+
+// Row ranges of the cell's warm-start block (up to MAXROWS rows, h <= 2), loaded once per
+// cell.  LdsRows keeps them in a per-thread column of LDS (the filtered pass);
+// GlobalRows reads them from the bucket starts each time (the exact passes).
+constexpr int MAXROWS = 5;
+
+template <int BLOCK>
+struct LdsRows {
+    int (*lo)[BLOCK];
+    int (*hi)[BLOCK];
+    int nrows;
+    __device__ __forceinline__ void load(const Cell &C, const int *__restrict__ bstart) {
+        const Rect A = block_rect(C);
+        nrows = A.y1 - A.y0 + 1;
+        if (nrows > MAXROWS) return;
+        for (int i = 0; i < nrows; ++i) {
+            const int base = C.boff + (A.y0 + i) * C.gx;
+            lo[i][threadIdx.x] = bstart[base + A.x0];
+            hi[i][threadIdx.x] = bstart[base + A.x1 + 1];
+        }
+    }
+    __device__ __forceinline__ void get(const Cell &, const int *__restrict__, int r, int &a,
+                                        int &b) const {
+        a = lo[r][threadIdx.x];
+        b = hi[r][threadIdx.x];
+    }
+};
+
+struct GlobalRows {
+    int nrows;
+    __device__ __forceinline__ void load(const Cell &C, const int *__restrict__) {
+        const Rect A = block_rect(C);
+        nrows = A.y1 - A.y0 + 1;
+    }
+    __device__ __forceinline__ void get(const Cell &C, const int *__restrict__ bstart, int r,
+                                        int &a, int &b) const {
+        const Rect A = block_rect(C);
+        const int base = C.boff + (A.y0 + r) * C.gx;
+        a = bstart[base + A.x0];
+        b = bstart[base + A.x1 + 1];
+    }
+};
+
+template <bool EXCL, class Rows>
+__device__ __forceinline__ ScanOut scan_f32(const Cell &C, const Rows &BR,
+                                            const float2 *__restrict__ sxy,
                                             const int *__restrict__ bstart, float dx, float dy,
                                             int ex1, int ex2, float tcap, Counters &K) {
     Best b{FINF, FINF, 0};
-#pragma unroll
-    for (int code = -1; code >= -4; --code) {
-        if (EXCL && (code == ex1 || code == ex2)) continue;
-        const Line L = side_line(C, code);
-        consider(key_lo_line((float)L.c, (float)L.nx, (float)L.ny, dx, dy), code, b);
-    }
-    // Method 11.6, one flat loop per lane (a lane pays only for its own candidates): the
-    // cell's block of shells 0..h is a warm start that bounds the endpoint by y; then the
-    // scanned rectangle grows towards the integer rectangle S_I[y, |y - p|] until it contains
-    // it.  The rectangles of later, nearer bounds nest inside the earlier ones, so the final
-    // scanned rectangle certifies the endpoint.
-    RowWalk wk;
-    wk.start(block_rect(C), Rect{1, 0, 1, 0});
-    float U = FINF;
-    for (;;) {
-        if (wk.pos < wk.end) {
-            const int pos = wk.pos++;
-            const float2 a = sxy[pos];
-            const float ex = a.x - C.pxf, ey = a.y - C.pyf;
-            float key = key_lo_line(site_q(ex, ey), ex, ey, dx, dy);
-            if (EXCL) key = (pos == ex1 || pos == ex2) ? FINF : key;
-            consider(key, pos, b);
-            ++K.evals;
-            continue;
+    consider_sides<EXCL>(C, dx, dy, ex1, ex2, b);
+    // Method 11.6.  Pass A: the cell's block of shells 0..h (a warm start that bounds the
+    // endpoint by y), one flat loop per lane over its rows; the row ranges are in registers,
+    // so a lane pays only for its own candidates plus a select per row.
+    const Rect A = block_rect(C);
+    if (BR.nrows <= MAXROWS) {
+        int r = 0, pos, end;
+        BR.get(C, bstart, 0, pos, end);
+        for (;;) {
+            if (pos < end) {
+                eval_site<EXCL>(C, sxy, pos, dx, dy, ex1, ex2, b);
+                ++pos;
+                ++K.evals;
+                continue;
+            }
+            if (++r >= BR.nrows) break;
+            BR.get(C, bstart, r, pos, end);
         }
-        if (wk.next(C, bstart)) continue;
-        // rectangle wk.O scanned: the rectangle needed by the current bound
-        K.shells++;
-        U = fminf(U, upper_of(C, sxy, b.w, dx, dy));
-        const Rect R = need_rect(C, fminf(U, tcap), dx, dy);
-        if (rect_inside(R, wk.O)) break;
-        wk.start(grow_rect(wk.O, R), wk.O);
+    } else {
+        RowWalk wk;
+        wk.start(A, Rect{1, 0, 1, 0});
+        for (;;) {
+            if (wk.pos < wk.end) {
+                eval_site<EXCL>(C, sxy, wk.pos, dx, dy, ex1, ex2, b);
+                ++wk.pos;
+                ++K.evals;
+                continue;
+            }
+            if (!wk.next(C, bstart)) break;
+        }
+    }
+    // One transition for all lanes: the integer rectangle S_I[y, |y - p|] of the bound.
+    K.shells++;
+    float U = upper_of(C, sxy, b.w, dx, dy);
+    Rect R = need_rect(C, fminf(U, tcap), dx, dy);
+    Rect O = A;
+    if (!rect_inside(R, A)) {
+        // Pass B (lanes whose rectangle sticks out of the block): grow the scanned rectangle
+        // towards S_I, at most doubling per step; the rectangles of later, nearer bounds nest
+        // inside the earlier ones, so the final scanned rectangle certifies the endpoint.
+        RowWalk wk;
+        wk.start(grow_rect(A, R), A);
+        for (;;) {
+            if (wk.pos < wk.end) {
+                eval_site<EXCL>(C, sxy, wk.pos, dx, dy, ex1, ex2, b);
+                ++wk.pos;
+                ++K.evals;
+                continue;
+            }
+            if (wk.next(C, bstart)) continue;
+            K.shells++;
+            U = fminf(U, upper_of(C, sxy, b.w, dx, dy));
+            R = need_rect(C, fminf(U, tcap), dx, dy);
+            if (rect_inside(R, wk.O)) break;
+            const Rect prev = wk.O;
+            wk.start(grow_rect(prev, R), prev);
+        }
+        O = wk.O;
     }
     const float Uw = upper_of(C, sxy, b.w, dx, dy);
-    U = fminf(U, Uw);
     ScanOut o;
     o.b = b;
     o.Uw = Uw;
-    o.U = U;
-    o.A = wk.O;
+    o.U = fminf(U, Uw);
+    o.A = O;
     return o;
 }
 
@@ -214,8 +308,8 @@ struct Sink {
 // Vertex ray (Den > 0, d = Z, u = Z / Den; lines ex1, ex2 through u skipped): returns 1 when u
 // is in the cell (a vertex), 0 when a line crosses [p, u) first (that line in out).
 // Returns -1 when undecided (MODE 0).
-template <int MODE>
-__device__ __forceinline__ int ray(const Cell &C, const float2 *__restrict__ sxy,
+template <int MODE, class Rows>
+__device__ __forceinline__ int ray(const Cell &C, const Rows &BR, const float2 *__restrict__ sxy,
                                    const int *__restrict__ bstart, const Dir &d, int64_t Den,
                                    int ex1, int ex2, Line &out, Counters &K) {
     const bool vmode = Den > 0;
@@ -229,8 +323,9 @@ __device__ __forceinline__ int ray(const Cell &C, const float2 *__restrict__ sxy
     if (MODE == 2) {
         exact_scan<false>(C, sxy, bstart, d, nullptr, FINF, tu_hi, ex1, ex2, xb, K);
     } else {
-        const ScanOut s = vmode ? scan_f32<true>(C, sxy, bstart, d.fx, d.fy, ex1, ex2, tu_hi, K)
-                                : scan_f32<false>(C, sxy, bstart, d.fx, d.fy, ex1, ex2, FINF, K);
+        const ScanOut s =
+            vmode ? scan_f32<true, Rows>(C, BR, sxy, bstart, d.fx, d.fy, ex1, ex2, tu_hi, K)
+                  : scan_f32<false, Rows>(C, BR, sxy, bstart, d.fx, d.fy, ex1, ex2, FINF, K);
         if (vmode && s.b.k1 * CERT_DN > tu_hi) return 1;
         const float uw = s.Uw * CERT_UP;
         if (uw < s.b.k2 * CERT_DN && (!vmode || uw < tu_lo)) {
@@ -257,15 +352,16 @@ __device__ __forceinline__ int ray(const Cell &C, const float2 *__restrict__ sxy
 // ------------------------------------------------------------------------------ one cell
 // Returns the number of lines written to the sink (>= 3), or
 //   -1 undecided in MODE 0, -2 stack / output capacity, -3 node limit (never expected).
-template <int MODE, class Stack>
+template <int MODE, class Stack, class Rows>
 __device__ __forceinline__ int run_cell(const Cell &C, const float2 *__restrict__ sxy,
                                         const int *__restrict__ bstart, Stack &st, int scap,
-                                        Sink &sink, int ocap, Counters &K) {
+                                        Rows &BR, Sink &sink, int ocap, Counters &K) {
     Line cur{}, B{}, L3{};
     int m = 0, first = 0, last = 0;
     const int node_limit = NODE_LIMIT_FACTOR * (scap + ocap) + 64;
     int nodes = 0;
     st.depth = 0;
+    BR.load(C, bstart);
     // phases 0..2: the projector's corner rays (7,-4), (0,1), (-7,-4): counter-clockwise,
     // consecutive gaps < pi.  Then the subedge loop.
     for (int phase = 0;; ++phase) {
@@ -297,7 +393,7 @@ __device__ __forceinline__ int run_cell(const Cell &C, const float2 *__restrict_
             }
         }
         if (!leaf) {
-            const int r = ray<MODE>(C, sxy, bstart, d, Den, ex1, ex2, L3, K);
+            const int r = ray<MODE, Rows>(C, BR, sxy, bstart, d, Den, ex1, ex2, L3, K);
             if (r < 0) return -1;
             leaf = (r == 1);
             // a shot ray (Lemma on shot rays) yields a corner; a ray that confirms a vertex

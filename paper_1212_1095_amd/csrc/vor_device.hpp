@@ -345,13 +345,14 @@ struct RowWalk {
             xb = O.x1;
             ++row;
         }
-        if (xa > xb) {
-            pos = end = 0;
-        } else {
+        int a = 0, b = 0;
+        if (xa <= xb) {
             const int base = C.boff + r * C.gx;
-            pos = bstart[base + xa];
-            end = bstart[base + xb + 1];
+            a = bstart[base + xa];
+            b = bstart[base + xb + 1];
         }
+        pos = a;
+        end = b;
         return true;
     }
 };

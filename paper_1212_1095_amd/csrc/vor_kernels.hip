@@ -136,6 +136,7 @@ __global__ __launch_bounds__(BLOCK) void k_cells_fast(
     int *__restrict__ queue, int *__restrict__ qcount, unsigned long long *__restrict__ stats,
     const int *__restrict__ status) {
     __shared__ int stk[SCAP][BLOCK];
+    __shared__ int rlo[MAXROWS][BLOCK], rhi[MAXROWS][BLOCK];
     __shared__ unsigned long long sh[SL_COUNT];
     if (*status) return;
     if (threadIdx.x < SL_COUNT) sh[threadIdx.x] = 0;
@@ -148,8 +149,9 @@ __global__ __launch_bounds__(BLOCK) void k_cells_fast(
         const Cell C = make_cell(S, sxy[pos]);
         const int g = S.site_off + sid[pos];
         LdsStack<BLOCK> st{stk, 0};
+        LdsRows<BLOCK> rows{rlo, rhi, 0};
         Sink sink{olines + (size_t)g * KOUT, sid};
-        const int r = run_cell<0>(C, sxy, bstart, st, SCAP, sink, KOUT, K);
+        const int r = run_cell<0>(C, sxy, bstart, st, SCAP, rows, sink, KOUT, K);
         ovf[g] = -1;
         if (r >= 0) {
             ocnt[g] = r;
@@ -197,8 +199,9 @@ __global__ __launch_bounds__(64) void k_cells_exact(
         const Cell C = make_cell(S, sxy[pos]);
         const int g = S.site_off + sid[pos];
         GStack st{area, 0};
+        GlobalRows rows{0};
         Sink sink{area + dcap, sid};
-        const int r = run_cell<MODE>(C, sxy, bstart, st, dcap, sink, dcap, K);
+        const int r = run_cell<MODE>(C, sxy, bstart, st, dcap, rows, sink, dcap, K);
         if (r == -2) {
             if (queue2) queue2[atomicAdd(qcount2, 1)] = pos;
             else atomicOr(status, ST_CAPACITY);
