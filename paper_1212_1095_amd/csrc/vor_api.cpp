@@ -74,7 +74,7 @@ struct HostBuf {   // pinned staging
 enum BufId {
     B_SETS, B_SETOFF, B_INX, B_INY, B_XYID, B_KEY, B_BCNT, B_BSTART, B_SXY, B_SID, B_OCNT,
     B_OLINES, B_OVF, B_POOL, B_QUEUE, B_QUEUE2, B_WBUF, B_WBUF2, B_CELLOFF, B_NBR, B_VTX,
-    B_DCNT, B_DELOFF, B_DEL, B_SCANTMP, B_SMALL, B_STATS, B_COUNT
+    B_DCNT, B_DELOFF, B_DEL, B_SCANTMP, B_SMALL, B_STATS, B_ECELL, B_COUNT
 };
 
 struct Workspace {
@@ -207,6 +207,7 @@ struct vor_ctx {
     Workspace ws;            // vor_compute / vor_compute_batch
     std::mutex mu;           // serialises vor_compute*
     bool use_graph = true;
+    long long coop_below = 4096;   // sets up to this size: one wave per cell
     // request loop
     Workspace rws[2];
     std::mutex qmu;
@@ -227,7 +228,7 @@ size_t footprint_bytes(uint64_t total, uint64_t gtot, bool vertices) {
     size_t b = 0;
     b += total * (4 + 4 + 8 + 4 + 8 + 4 + 4 + 4 + 4 + 4 + 4 + 4);   // inputs, grid, queues, counts
     b += total * 4ull * KOUT;                                       // filtered-pass lines
-    b += E * 4 * 2;                                                 // pool + nbr
+    b += E * 4 * 3;                                                 // pool, nbr, owners
     if (vertices) b += E * sizeof(vor_rat);
     b += (3 * total + 8) * 8;                                       // delaunay
     b += gtot * 8;
@@ -264,7 +265,11 @@ int launch(vor_ctx *ctx, Workspace &ws, const std::vector<HostSet> &sets, bool v
     const long long T = total;
     const long long E = 10 * T + 16;
     const long long D = 3 * T + 8;
-    const int exact_blocks = (int)std::min<long long>(1024, std::max<long long>(1, (T + 63) / 64));
+    const bool coop_all = !exact_only && T <= ctx->coop_below;
+    // one-wave workers of the exact pass: enough to fill the GPU when every cell goes through
+    // it, fewer when it only takes the cells the filtered pass deferred
+    const int exact_blocks =
+        (int)std::max<long long>(1, std::min<long long>(exact_only || coop_all ? 8192 : 2048, T));
     const long long stmp = scan_tmp_ints(std::max(T, gtot)) + 8;
     struct Need { int id; size_t bytes; } need[] = {
         {B_SETS, sizeof(SetDesc) * K}, {B_SETOFF, 4ull * (K + 1)}, {B_INX, 4ull * T},
@@ -272,11 +277,11 @@ int launch(vor_ctx *ctx, Workspace &ws, const std::vector<HostSet> &sets, bool v
         {B_BSTART, 4ull * (gtot + 1)}, {B_SXY, 8ull * T}, {B_SID, 4ull * T},
         {B_OCNT, 4ull * T}, {B_OLINES, 4ull * KOUT * T}, {B_OVF, 4ull * T}, {B_POOL, 4ull * E},
         {B_QUEUE, 4ull * T}, {B_QUEUE2, 4ull * T},
-        {B_WBUF, 4ull * 2 * DCAP1 * 64 * exact_blocks}, {B_WBUF2, 4ull * 2 * DCAP2 * 64 * DEEP_BLOCKS},
+        {B_WBUF, 4ull * 2 * DCAP1 * exact_blocks}, {B_WBUF2, 4ull * 2 * DCAP2 * DEEP_BLOCKS},
         {B_CELLOFF, 4ull * (T + 1)}, {B_NBR, 4ull * E},
         {B_VTX, vertices ? sizeof(vor_rat) * E : 16}, {B_DCNT, 4ull * T},
         {B_DELOFF, 4ull * (T + 1)}, {B_DEL, 8ull * D}, {B_SCANTMP, 4ull * stmp},
-        {B_SMALL, 4ull * SMALL_INTS}, {B_STATS, 8ull * SL_COUNT}};
+        {B_SMALL, 4ull * SMALL_INTS}, {B_STATS, 8ull * SL_COUNT}, {B_ECELL, 4ull * E}};
     bool grew = false;
     for (auto &q : need) {
         const size_t before = ws.b[q.id].cap;
@@ -342,6 +347,7 @@ int launch(vor_ctx *ctx, Workspace &ws, const std::vector<HostSet> &sets, bool v
     a.exact_blocks = exact_blocks;
     a.cell_off = ws.b[B_CELLOFF].as<int>();
     a.nbr = ws.b[B_NBR].as<int>();
+    a.ecell = ws.b[B_ECELL].as<int>();
     a.nbr_cap = E;
     a.vtx = ws.b[B_VTX].p;
     a.dcnt = ws.b[B_DCNT].as<int>();
@@ -355,6 +361,7 @@ int launch(vor_ctx *ctx, Workspace &ws, const std::vector<HostSet> &sets, bool v
     a.exact_only = exact_only;
     a.with_vertices = vertices;
     a.check_symmetry = symmetry;
+    a.coop_all = coop_all;
     a.time_stages = (ctx->opts.flags & VOR_TIME_KERNELS) != 0;
 
     ws.last_timed = a.time_stages;
@@ -718,6 +725,7 @@ int vor_create(const vor_opts *opts, vor_ctx **out) {
     }
     const char *g = std::getenv("VOR_NO_GRAPH");
     c->use_graph = !(g && g[0] == '1');
+    if (const char *cb = std::getenv("VOR_COOP_BELOW")) c->coop_below = std::atoll(cb);
     size_t fr = 0, tot = 0;
     (void)hipMemGetInfo(&fr, &tot);
     c->budget = c->opts.hbm_budget_bytes ? c->opts.hbm_budget_bytes : (uint64_t)(tot / 4 * 3);

@@ -23,6 +23,11 @@
 //
 // Exact ties at an endpoint (Remark 11.3): among the lines through the endpoint the one whose
 // outward normal is the most clockwise carries an edge of the cell; it is the one chosen.
+//
+// Lane policies.  Solo: one lane computes one cell (the filtered pass over all cells).
+// Coop: the 64 lanes of a wave compute one cell together -- every lane runs the same control
+// flow, the candidates of a row are split across the lanes and the per-lane results are merged
+// by a butterfly (the exact passes and small sets, where latency matters).
 #pragma once
 #include "vor_device.hpp"
 
@@ -32,6 +37,99 @@ struct Counters {
     uint32_t rays, nodes, evals, exact, shells, vtests;
 };
 
+// ------------------------------------------------------------------------------ exact argmin
+struct XBest {
+    int id;
+    int nx, ny;
+    uint64_t c;
+    u128 den;
+    bool have;
+};
+
+// true when candidate (c, den, n) beats the current exact best: nearer hit, or at an exact tie
+// the more clockwise normal (the smaller id if the normals were parallel, never for valid input)
+__device__ __forceinline__ bool x_better(const XBest &b, int id, int nx, int ny, uint64_t c,
+                                         u128 den) {
+    if (!b.have) return true;
+    const int s = cmp_t(c, den, b.c, b.den);
+    if (s != 0) return s < 0;
+    const int64_t cr = (int64_t)b.nx * ny - (int64_t)b.ny * nx;
+    if (cr != 0) return cr < 0;
+    return id < b.id;
+}
+
+__device__ __forceinline__ void x_consider(XBest &b, int id, int nx, int ny, int64_t c,
+                                           const Dir &d) {
+    const i128 den = (i128)nx * d.x + (i128)ny * d.y;
+    if (den <= 0) return;
+    if (!x_better(b, id, nx, ny, (uint64_t)c, (u128)den)) return;
+    b.id = id;
+    b.nx = nx;
+    b.ny = ny;
+    b.c = (uint64_t)c;
+    b.den = (u128)den;
+    b.have = true;
+}
+
+// Upper bound (FP32 key, scaled frame) of the exact winner's t = c / den.
+__device__ __forceinline__ float x_upper(const XBest &b, const Dir &d) {
+    if (!b.have) return FINF;
+    const double t = (double)b.c / u128_to_double(b.den);
+    return (float)ldexp(t, d.sigma) * CERT_UP;
+}
+
+// ------------------------------------------------------------------------------ lane policies
+struct Solo {
+    static constexpr int W = 1;
+    __device__ static __forceinline__ int lane() { return 0; }
+    __device__ static __forceinline__ void reduce(Best &) {}
+    __device__ static __forceinline__ void reduce(XBest &) {}
+};
+
+struct Coop {
+    static constexpr int W = 64;
+    __device__ static __forceinline__ int lane() { return threadIdx.x & 63; }
+    // Merge of two (smallest, second smallest, argmin) summaries; a candidate held by both
+    // halves (the winner carried over from an earlier pass) counts once.
+    __device__ static __forceinline__ void reduce(Best &b) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const float o1 = __shfl_xor(b.k1, off, 64);
+            const float o2 = __shfl_xor(b.k2, off, 64);
+            const int ow = __shfl_xor(b.w, off, 64);
+            if (ow == b.w) {
+                b.k2 = fminf(b.k2, o2);
+            } else if (o1 < b.k1 || (o1 == b.k1 && ow < b.w)) {
+                b.k2 = fminf(b.k1, o2);
+                b.k1 = o1;
+                b.w = ow;
+            } else {
+                b.k2 = fminf(b.k2, o1);
+            }
+        }
+    }
+    __device__ static __forceinline__ void reduce(XBest &b) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            XBest o;
+            o.id = __shfl_xor(b.id, off, 64);
+            o.nx = __shfl_xor(b.nx, off, 64);
+            o.ny = __shfl_xor(b.ny, off, 64);
+            const uint32_t c0 = __shfl_xor((uint32_t)b.c, off, 64);
+            const uint32_t c1 = __shfl_xor((uint32_t)(b.c >> 32), off, 64);
+            o.c = ((uint64_t)c1 << 32) | c0;
+            uint32_t dd[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) dd[q] = __shfl_xor((uint32_t)(b.den >> (32 * q)), off, 64);
+            o.den = ((u128)dd[3] << 96) | ((u128)dd[2] << 64) | ((u128)dd[1] << 32) | dd[0];
+            o.have = __shfl_xor((int)b.have, off, 64) != 0;
+            if (o.have && (!b.have || o.id != b.id) && x_better(b, o.id, o.nx, o.ny, o.c, o.den))
+                b = o;
+        }
+    }
+};
+
+// ------------------------------------------------------------------------------ FP32 scan
 struct ScanOut {
     Best b;
     float Uw;   // upper bound key of the final winner
@@ -51,37 +149,31 @@ __device__ __forceinline__ float upper_of(const Cell &C, const float2 *__restric
     return key_hi_line((float)L.c, (float)L.nx, (float)L.ny, dx, dy);
 }
 
-// FP32 scan of the rays's candidates, shell by shell, until the block certifies the endpoint
-// (or the point at tcap, whichever is nearer).  Candidates ex1 / ex2 are skipped when EXCL.
 // Box sides the ray can leave through: at most one horizontal and one vertical side.
-template <bool EXCL>
 __device__ __forceinline__ void consider_sides(const Cell &C, float dx, float dy, int ex1, int ex2,
                                                Best &b) {
     const int sv = dy > 0.0f ? -3 : -1, sh = dx > 0.0f ? -2 : -4;
     const Line Lv = side_line(C, sv), Lh = side_line(C, sh);
     float kv = key_lo_line((float)Lv.c, (float)Lv.nx, (float)Lv.ny, dx, dy);
     float kh = key_lo_line((float)Lh.c, (float)Lh.nx, (float)Lh.ny, dx, dy);
-    if (EXCL) {
-        kv = (sv == ex1 || sv == ex2) ? FINF : kv;
-        kh = (sh == ex1 || sh == ex2) ? FINF : kh;
-    }
+    kv = (sv == ex1 || sv == ex2) ? FINF : kv;
+    kh = (sh == ex1 || sh == ex2) ? FINF : kh;
     consider(kv, sv, b);
     consider(kh, sh, b);
 }
 
-template <bool EXCL>
 __device__ __forceinline__ void eval_site(const Cell &C, const float2 *__restrict__ sxy, int pos,
                                           float dx, float dy, int ex1, int ex2, Best &b) {
     const float2 a = sxy[pos];
     const float ex = a.x - C.pxf, ey = a.y - C.pyf;
     float key = key_lo_line(site_q(ex, ey), ex, ey, dx, dy);
-    if (EXCL) key = (pos == ex1 || pos == ex2) ? FINF : key;
+    key = (pos == ex1 || pos == ex2) ? FINF : key;
     consider(key, pos, b);
 }
 
 // Row ranges of the cell's warm-start block (up to MAXROWS rows, h <= 2), loaded once per
 // cell.  LdsRows keeps them in a per-thread column of LDS (the filtered pass);
-// GlobalRows reads them from the bucket starts each time (the exact passes).
+// GlobalRows reads them from the bucket starts each time.
 constexpr int MAXROWS = 5;
 
 template <int BLOCK>
@@ -121,156 +213,127 @@ struct GlobalRows {
     }
 };
 
-template <bool EXCL, class Rows>
+// Candidates of rectangle O \ I, one flat loop per lane (a lane pays only for its own
+// candidates); with the Coop policy lane i takes every 64th candidate of each row.
+template <class P>
+__device__ __forceinline__ void scan_rect_f32(const Cell &C, const float2 *__restrict__ sxy,
+                                              const int *__restrict__ bstart, Rect O, Rect I,
+                                              float dx, float dy, int ex1, int ex2, Best &b,
+                                              Counters &K) {
+    RowWalk wk;
+    wk.start(O, I);
+    int pos = 0, end = 0;
+    for (;;) {
+        if (pos < end) {
+            eval_site(C, sxy, pos, dx, dy, ex1, ex2, b);
+            pos += P::W;
+            ++K.evals;
+            continue;
+        }
+        if (!wk.next(C, bstart)) break;
+        pos = wk.pos + P::lane();
+        end = wk.end;
+    }
+}
+
+// One ray: FP32 argmin over the certified candidates (Method 11.6).
+template <class P, class Rows>
 __device__ __forceinline__ ScanOut scan_f32(const Cell &C, const Rows &BR,
                                             const float2 *__restrict__ sxy,
                                             const int *__restrict__ bstart, float dx, float dy,
                                             int ex1, int ex2, float tcap, Counters &K) {
-    Best b{FINF, FINF, 0};
-    consider_sides<EXCL>(C, dx, dy, ex1, ex2, b);
-    // Method 11.6.  Pass A: the cell's block of shells 0..h (a warm start that bounds the
-    // endpoint by y), one flat loop per lane over its rows; the row ranges are in registers,
-    // so a lane pays only for its own candidates plus a select per row.
+    Best b{FINF, FINF, -1};
+    // Pass A: the cell's block of shells 0..h, a warm start that bounds the endpoint by y.
     const Rect A = block_rect(C);
     if (BR.nrows <= MAXROWS) {
         int r = 0, pos, end;
         BR.get(C, bstart, 0, pos, end);
+        pos += P::lane();
         for (;;) {
             if (pos < end) {
-                eval_site<EXCL>(C, sxy, pos, dx, dy, ex1, ex2, b);
-                ++pos;
+                eval_site(C, sxy, pos, dx, dy, ex1, ex2, b);
+                pos += P::W;
                 ++K.evals;
                 continue;
             }
             if (++r >= BR.nrows) break;
             BR.get(C, bstart, r, pos, end);
+            pos += P::lane();
         }
     } else {
-        RowWalk wk;
-        wk.start(A, Rect{1, 0, 1, 0});
-        for (;;) {
-            if (wk.pos < wk.end) {
-                eval_site<EXCL>(C, sxy, wk.pos, dx, dy, ex1, ex2, b);
-                ++wk.pos;
-                ++K.evals;
-                continue;
-            }
-            if (!wk.next(C, bstart)) break;
-        }
+        scan_rect_f32<P>(C, sxy, bstart, A, Rect{1, 0, 1, 0}, dx, dy, ex1, ex2, b, K);
     }
-    // One transition for all lanes: the integer rectangle S_I[y, |y - p|] of the bound.
+    P::reduce(b);
+    consider_sides(C, dx, dy, ex1, ex2, b);
+    // The integer rectangle S_I[y, |y - p|] of the bound.  While it is not inside the scanned
+    // rectangle, grow the scanned rectangle towards it (at most doubling per step); the
+    // rectangles of later, nearer bounds nest inside the earlier ones, so the final scanned
+    // rectangle certifies the endpoint.
     K.shells++;
     float U = upper_of(C, sxy, b.w, dx, dy);
+    float Uw = U;
     Rect R = need_rect(C, fminf(U, tcap), dx, dy);
     Rect O = A;
-    if (!rect_inside(R, A)) {
-        // Pass B (lanes whose rectangle sticks out of the block): grow the scanned rectangle
-        // towards S_I, at most doubling per step; the rectangles of later, nearer bounds nest
-        // inside the earlier ones, so the final scanned rectangle certifies the endpoint.
-        RowWalk wk;
-        wk.start(grow_rect(A, R), A);
-        for (;;) {
-            if (wk.pos < wk.end) {
-                eval_site<EXCL>(C, sxy, wk.pos, dx, dy, ex1, ex2, b);
-                ++wk.pos;
-                ++K.evals;
-                continue;
-            }
-            if (wk.next(C, bstart)) continue;
-            K.shells++;
-            U = fminf(U, upper_of(C, sxy, b.w, dx, dy));
-            R = need_rect(C, fminf(U, tcap), dx, dy);
-            if (rect_inside(R, wk.O)) break;
-            const Rect prev = wk.O;
-            wk.start(grow_rect(prev, R), prev);
-        }
-        O = wk.O;
+    while (!rect_inside(R, O)) {
+        const Rect N = grow_rect(O, R);
+        scan_rect_f32<P>(C, sxy, bstart, N, O, dx, dy, ex1, ex2, b, K);
+        P::reduce(b);
+        O = N;
+        K.shells++;
+        Uw = upper_of(C, sxy, b.w, dx, dy);
+        U = fminf(U, Uw);
+        R = need_rect(C, fminf(U, tcap), dx, dy);
     }
-    const float Uw = upper_of(C, sxy, b.w, dx, dy);
     ScanOut o;
     o.b = b;
     o.Uw = Uw;
-    o.U = fminf(U, Uw);
+    o.U = U;
     o.A = O;
     return o;
 }
 
-// ------------------------------------------------------------------------------ exact argmin
-struct XBest {
-    int id;
-    int nx, ny;
-    uint64_t c;
-    u128 den;
-    bool have;
-};
-
-__device__ __forceinline__ void x_consider(XBest &b, int id, int nx, int ny, int64_t c,
-                                           const Dir &d) {
-    const i128 den = (i128)nx * d.x + (i128)ny * d.y;
-    if (den <= 0) return;
-    if (b.have) {
-        const int s = cmp_t((uint64_t)c, (u128)den, b.c, b.den);
-        if (s > 0) return;
-        if (s == 0) {
-            // tie at the endpoint: keep the most clockwise normal
-            const int64_t cr = (int64_t)b.nx * ny - (int64_t)b.ny * nx;
-            if (cr >= 0) return;
-        }
-    }
-    b.id = id;
-    b.nx = nx;
-    b.ny = ny;
-    b.c = (uint64_t)c;
-    b.den = (u128)den;
-    b.have = true;
-}
-
-// Upper bound (FP32 key, scaled frame) of the exact winner's t = c / den.
-__device__ __forceinline__ float x_upper(const XBest &b, const Dir &d) {
-    if (!b.have) return FINF;
-    const double t = (double)b.c / u128_to_double(b.den);
-    return (float)ldexp(t, d.sigma) * CERT_UP;
-}
-
-// Exact argmin over the rectangle an FP32 scan certified (prev), or over a block grown
-// towards the certified rectangle of the exact winner (prev == null: exact-only precision).  With FILTER only candidates whose FP32 lower bound is <= Tlim count.
-template <bool FILTER>
-__device__ __forceinline__ void exact_scan(const Cell &C, const float2 *__restrict__ sxy,
-                                           const int *__restrict__ bstart, const Dir &d,
-                                           const ScanOut *prev, float Tlim, float tcap, int ex1,
-                                           int ex2, XBest &b, Counters &K) {
-    b.have = false;
+// Exact argmin over rectangle O \ I.  With FILTER only candidates whose FP32 lower bound is
+// <= Tlim count.
+template <bool FILTER, class P>
+__device__ __forceinline__ void exact_rect(const Cell &C, const float2 *__restrict__ sxy,
+                                           const int *__restrict__ bstart, const Dir &d, Rect O,
+                                           Rect I, float Tlim, int ex1, int ex2, XBest &b,
+                                           Counters &K) {
     const float lim = Tlim * CERT_UP;
-    for (int code = -1; code >= -4; --code) {
-        if (code == ex1 || code == ex2) continue;
-        const Line L = side_line(C, code);
-        if (FILTER &&
-            !(key_lo_line((float)L.c, (float)L.nx, (float)L.ny, d.fx, d.fy) * CERT_DN <= lim))
-            continue;
-        x_consider(b, code, L.nx, L.ny, L.c, d);
-    }
     RowWalk wk;
-    wk.start(prev ? prev->A : block_rect(C), Rect{1, 0, 1, 0});
+    wk.start(O, I);
+    int pos = 0, end = 0;
     for (;;) {
-        if (wk.pos < wk.end) {
-            const int pos = wk.pos++;
-            if (pos == ex1 || pos == ex2) continue;
-            const float2 a = sxy[pos];
+        if (pos < end) {
+            const int q = pos;
+            pos += P::W;
+            if (q == ex1 || q == ex2) continue;
+            const float2 a = sxy[q];
             const float ex = a.x - C.pxf, ey = a.y - C.pyf;
             if (FILTER && !(key_lo_line(site_q(ex, ey), ex, ey, d.fx, d.fy) * CERT_DN <= lim))
                 continue;
             if (!FILTER) ++K.evals;
             const int nx = (int)a.x - C.px, ny = (int)a.y - C.py;
             if ((nx | ny) == 0) continue;   // p itself
-            x_consider(b, pos, nx, ny, (int64_t)nx * nx + (int64_t)ny * ny, d);
+            x_consider(b, q, nx, ny, (int64_t)nx * nx + (int64_t)ny * ny, d);
             continue;
         }
-        if (wk.next(C, bstart)) continue;
-        if (prev) break;   // the FP32 scan's rectangle already certifies the endpoint
-        K.shells++;
-        const Rect R = need_rect(C, fminf(x_upper(b, d), tcap), d.fx, d.fy);
-        if (rect_inside(R, wk.O)) break;
-        wk.start(grow_rect(wk.O, R), wk.O);
+        if (!wk.next(C, bstart)) break;
+        pos = wk.pos + P::lane();
+        end = wk.end;
+    }
+}
+
+__device__ __forceinline__ void exact_sides(const Cell &C, const Dir &d, float Tlim, bool filter,
+                                            int ex1, int ex2, XBest &b) {
+    const float lim = Tlim * CERT_UP;
+    for (int code = -1; code >= -4; --code) {
+        if (code == ex1 || code == ex2) continue;
+        const Line L = side_line(C, code);
+        if (filter &&
+            !(key_lo_line((float)L.c, (float)L.nx, (float)L.ny, d.fx, d.fy) * CERT_DN <= lim))
+            continue;
+        x_consider(b, code, L.nx, L.ny, L.c, d);
     }
 }
 
@@ -284,6 +347,8 @@ struct LdsStack {
     __device__ __forceinline__ int pop() { return s[--depth][threadIdx.x]; }
 };
 
+// Stack in global memory; with the Coop policy every lane writes the same value to the same
+// address.
 struct GStack {
     int *s;
     int depth;
@@ -308,24 +373,42 @@ struct Sink {
 // Vertex ray (Den > 0, d = Z, u = Z / Den; lines ex1, ex2 through u skipped): returns 1 when u
 // is in the cell (a vertex), 0 when a line crosses [p, u) first (that line in out).
 // Returns -1 when undecided (MODE 0).
-template <int MODE, class Rows>
+template <int MODE, class P, class Rows>
 __device__ __forceinline__ int ray(const Cell &C, const Rows &BR, const float2 *__restrict__ sxy,
                                    const int *__restrict__ bstart, const Dir &d, int64_t Den,
                                    int ex1, int ex2, Line &out, Counters &K) {
     const bool vmode = Den > 0;
     float tu_hi = FINF, tu_lo = FINF;
     if (vmode) {
-        const float tu = (float)ldexp(1.0 / (double)Den, d.sigma);
+        // t_u = 2^sigma / Den: Den rounds to FP32 with relative error <= u and v_rcp_f32 adds
+        // <= 2 ulp, both far inside the 2^-19 margins
+        const float tu = ldexpf(__builtin_amdgcn_rcpf((float)Den), d.sigma);
         tu_hi = tu * CERT_UP;
         tu_lo = tu * CERT_DN;
     }
     XBest xb;
+    xb.have = false;
     if (MODE == 2) {
-        exact_scan<false>(C, sxy, bstart, d, nullptr, FINF, tu_hi, ex1, ex2, xb, K);
+        // every decision exact: the block, then the rectangle the exact winner needs
+        const Rect A = block_rect(C);
+        exact_rect<false, P>(C, sxy, bstart, d, A, Rect{1, 0, 1, 0}, FINF, ex1, ex2, xb, K);
+        P::reduce(xb);
+        exact_sides(C, d, FINF, false, ex1, ex2, xb);
+        Rect O = A;
+        K.shells++;
+        Rect R = need_rect(C, fminf(x_upper(xb, d), tu_hi), d.fx, d.fy);
+        while (!rect_inside(R, O)) {
+            const Rect N = grow_rect(O, R);
+            exact_rect<false, P>(C, sxy, bstart, d, N, O, FINF, ex1, ex2, xb, K);
+            P::reduce(xb);
+            O = N;
+            K.shells++;
+            R = need_rect(C, fminf(x_upper(xb, d), tu_hi), d.fx, d.fy);
+        }
     } else {
-        const ScanOut s =
-            vmode ? scan_f32<true, Rows>(C, BR, sxy, bstart, d.fx, d.fy, ex1, ex2, tu_hi, K)
-                  : scan_f32<false, Rows>(C, BR, sxy, bstart, d.fx, d.fy, ex1, ex2, FINF, K);
+        // one scan variant for both kinds of rays (lanes of a wave may differ in kind)
+        const ScanOut s = scan_f32<P, Rows>(C, BR, sxy, bstart, d.fx, d.fy, ex1, ex2,
+                                            vmode ? tu_hi : FINF, K);
         if (vmode && s.b.k1 * CERT_DN > tu_hi) return 1;
         const float uw = s.Uw * CERT_UP;
         if (uw < s.b.k2 * CERT_DN && (!vmode || uw < tu_lo)) {
@@ -334,7 +417,11 @@ __device__ __forceinline__ int ray(const Cell &C, const Rows &BR, const float2 *
         }
         if (MODE == 0) return -1;
         K.exact++;
-        exact_scan<true>(C, sxy, bstart, d, &s, vmode ? tu_hi : s.U, tu_hi, ex1, ex2, xb, K);
+        // exact decision over the certified rectangle, FP32-plausible candidates only
+        const float Tlim = vmode ? tu_hi : s.U;
+        exact_rect<true, P>(C, sxy, bstart, d, s.A, Rect{1, 0, 1, 0}, Tlim, ex1, ex2, xb, K);
+        P::reduce(xb);
+        exact_sides(C, d, Tlim, true, ex1, ex2, xb);
     }
     // no line other than the two through u is crossed: u is the endpoint (a vertex)
     if (!xb.have) return vmode ? 1 : -1;
@@ -352,7 +439,7 @@ __device__ __forceinline__ int ray(const Cell &C, const Rows &BR, const float2 *
 // ------------------------------------------------------------------------------ one cell
 // Returns the number of lines written to the sink (>= 3), or
 //   -1 undecided in MODE 0, -2 stack / output capacity, -3 node limit (never expected).
-template <int MODE, class Stack, class Rows>
+template <int MODE, class P, class Stack, class Rows>
 __device__ __forceinline__ int run_cell(const Cell &C, const float2 *__restrict__ sxy,
                                         const int *__restrict__ bstart, Stack &st, int scap,
                                         Rows &BR, Sink &sink, int ocap, Counters &K) {
@@ -393,7 +480,7 @@ __device__ __forceinline__ int run_cell(const Cell &C, const float2 *__restrict_
             }
         }
         if (!leaf) {
-            const int r = ray<MODE, Rows>(C, BR, sxy, bstart, d, Den, ex1, ex2, L3, K);
+            const int r = ray<MODE, P, Rows>(C, BR, sxy, bstart, d, Den, ex1, ex2, L3, K);
             if (r < 0) return -1;
             leaf = (r == 1);
             // a shot ray (Lemma on shot rays) yields a corner; a ray that confirms a vertex

@@ -7,7 +7,7 @@ namespace vor {
 
 struct SetDesc;
 constexpr int SMALL_INTS = 16;   // status, qcount, qcount2, poolcnt, spare
-constexpr int DEEP_BLOCKS = 1;   // workers of the deep-cell pass = 64 * DEEP_BLOCKS
+constexpr int DEEP_BLOCKS = 8;   // one-wave workers of the deep-cell pass
 
 // Device pointers and sizes of one pipeline launch.
 struct PipeArgs {
@@ -31,6 +31,7 @@ struct PipeArgs {
     int exact_blocks;
     int *cell_off;          // [total + 1]
     int *nbr;
+    int *ecell;             // owner cell of each CSR entry [nbr_cap]
     long long nbr_cap;
     void *vtx;              // vor_rat [nbr_cap]
     int *dcnt, *del_off;    // [total], [total + 1]
@@ -41,6 +42,7 @@ struct PipeArgs {
     unsigned long long *stats;
     int block;
     bool exact_only, with_vertices, check_symmetry;
+    bool coop_all;              // every cell through the one-wave-per-cell pass (small sets)
     bool time_stages;           // HIP events between the stages (one graph per stage)
 
     int *status() const { return small; }

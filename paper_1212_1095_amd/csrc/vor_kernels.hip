@@ -14,6 +14,8 @@
 //
 // Every kernel reads the device status word first and returns when an input error is set, so
 // the whole sequence can be launched (or replayed as a HIP graph) without host round trips.
+#include <algorithm>
+
 #include "vor_cell.hpp"
 #include "vor_internal.h"
 
@@ -151,7 +153,7 @@ __global__ __launch_bounds__(BLOCK) void k_cells_fast(
         LdsStack<BLOCK> st{stk, 0};
         LdsRows<BLOCK> rows{rlo, rhi, 0};
         Sink sink{olines + (size_t)g * KOUT, sid};
-        const int r = run_cell<0>(C, sxy, bstart, st, SCAP, rows, sink, KOUT, K);
+        const int r = run_cell<0, Solo>(C, sxy, bstart, st, SCAP, rows, sink, KOUT, K);
         ovf[g] = -1;
         if (r >= 0) {
             ocnt[g] = r;
@@ -173,7 +175,8 @@ __global__ void k_queue_all(int total, int *__restrict__ queue, int *__restrict_
     if (i == 0) *qcount = total;
 }
 
-// Exact pass over a queue of cells (persistent grid; stack and output in a per-worker area).
+// Exact pass over a queue of cells: one wave per cell (the Coop policy), a persistent grid of
+// one-wave blocks; the cell's stack and output live in the block's area of dcap entries each.
 template <int MODE>
 __global__ __launch_bounds__(64) void k_cells_exact(
     const SetDesc *__restrict__ sets, int nsets, const int *__restrict__ set_off,
@@ -187,13 +190,12 @@ __global__ __launch_bounds__(64) void k_cells_exact(
     if (*status & (ST_DOMAIN | ST_DUP)) return;
     if (threadIdx.x < SL_COUNT) sh[threadIdx.x] = 0;
     __syncthreads();
-    const int w = blockIdx.x * blockDim.x + threadIdx.x;
-    const int nw = gridDim.x * blockDim.x;
+    const int lane = threadIdx.x;
     const int nq = *qcount;
-    int *area = wbuf + (size_t)w * 2 * dcap;
+    int *area = wbuf + (size_t)blockIdx.x * 2 * dcap;
     Counters K{0, 0, 0, 0, 0, 0};
     uint32_t edges = 0;
-    for (int qi = w; qi < nq; qi += nw) {
+    for (int qi = blockIdx.x; qi < nq; qi += gridDim.x) {
         const int pos = queue[qi];
         const SetDesc S = sets[find_set(set_off, nsets, pos)];
         const Cell C = make_cell(S, sxy[pos]);
@@ -201,32 +203,40 @@ __global__ __launch_bounds__(64) void k_cells_exact(
         GStack st{area, 0};
         GlobalRows rows{0};
         Sink sink{area + dcap, sid};
-        const int r = run_cell<MODE>(C, sxy, bstart, st, dcap, rows, sink, dcap, K);
+        const int r = run_cell<MODE, Coop>(C, sxy, bstart, st, dcap, rows, sink, dcap, K);
         if (r == -2) {
-            if (queue2) queue2[atomicAdd(qcount2, 1)] = pos;
-            else atomicOr(status, ST_CAPACITY);
+            if (lane == 0) {
+                if (queue2) queue2[atomicAdd(qcount2, 1)] = pos;
+                else atomicOr(status, ST_CAPACITY);
+            }
             continue;
         }
         if (r < 0) {
-            atomicOr(status, ST_INTERNAL);
+            if (lane == 0) atomicOr(status, ST_INTERNAL);
             continue;
         }
         edges += (uint32_t)r;
         const int *src = area + dcap;
-        if (r <= KOUT) {
-            int *dst = olines + (size_t)g * KOUT;
-            for (int t = 0; t < r; ++t) dst[t] = src[t];
-            ovf[g] = -1;
-        } else {
-            const int off = atomicAdd(poolcnt, r);
+        int off = -1;
+        if (r > KOUT) {
+            if (lane == 0) off = atomicAdd(poolcnt, r);
+            off = __shfl(off, 0, 64);
             if ((long long)off + r > poolcap) {
-                atomicOr(status, ST_CAPACITY);
+                if (lane == 0) atomicOr(status, ST_CAPACITY);
                 continue;
             }
-            for (int t = 0; t < r; ++t) pool[off + t] = src[t];
-            ovf[g] = off;
         }
-        ocnt[g] = r;
+        int *dst = off >= 0 ? pool + off : olines + (size_t)g * KOUT;
+        for (int t = lane; t < r; t += 64) dst[t] = src[t];
+        if (lane == 0) {
+            ovf[g] = off;
+            ocnt[g] = r;
+        }
+    }
+    // every lane ran the same control flow: count it once; evaluations are split across lanes
+    if (lane != 0) {
+        K.rays = K.nodes = K.exact = K.shells = K.vtests = 0;
+        edges = 0;
     }
     reduce_stats(K, edges, 0, sh, stats);
 }
@@ -349,17 +359,16 @@ struct Rat {
     int64_t d;
 };
 
+// Per cell: canonical rotation, neighbour ids, the owner of every CSR entry, Delaunay count.
 __global__ void k_fill(const SetDesc *__restrict__ sets, int nsets, const int *__restrict__ set_off,
                        int total, const int *__restrict__ ocnt, const int *__restrict__ olines,
                        const int *__restrict__ ovf, const int *__restrict__ pool,
-                       const int *__restrict__ cell_off, long long cap, const int2 *__restrict__ xyid,
-                       int *__restrict__ nbr, Rat *__restrict__ vtx, int *__restrict__ dcnt,
-                       int *__restrict__ status) {
+                       const int *__restrict__ cell_off, long long cap, int *__restrict__ nbr,
+                       int *__restrict__ ecell, int *__restrict__ dcnt, int *__restrict__ status) {
     if (*status) return;
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= total) return;
-    const SetDesc S = sets[find_set(set_off, nsets, g)];
-    const int k = g - S.site_off;
+    const int k = g - set_off[find_set(set_off, nsets, g)];
     const int m = ocnt[g];
     const long long base = cell_off[g];
     if (m < 3 || base + m > cap) {
@@ -374,25 +383,43 @@ __global__ void k_fill(const SetDesc *__restrict__ sets, int nsets, const int *_
     for (int t = 0; t < m; ++t) {
         const int a = src[(r + t) % m];
         nbr[base + t] = a;
+        ecell[base + t] = g;
         up += a > k;
-        if (vtx) {
-            const int b = src[(r + t + 1) % m];
-            long long n1x, n1y, c1, n2x, n2y, c2;
-            abs_line(S, xyid, k, a, n1x, n1y, c1);
-            abs_line(S, xyid, k, b, n2x, n2y, c2);
-            const long long D = n1x * n2y - n1y * n2x;
-            const i128 X = (i128)c1 * n2y - (i128)c2 * n1y;
-            const i128 Y = (i128)n1x * c2 - (i128)n2x * c1;
-            Rat v;
-            v.x_lo = (uint64_t)X;
-            v.x_hi = (int64_t)(X >> 64);
-            v.y_lo = (uint64_t)Y;
-            v.y_hi = (int64_t)(Y >> 64);
-            v.d = D;
-            vtx[base + t] = v;
-        }
     }
     dcnt[g] = up;
+}
+
+// Per CSR entry (consecutive threads write consecutive 40-byte vertices): vertex i of cell k is
+// line(nbr[i]) ∩ line(nbr[i+1 cyclic]) in pair form, Cramer's rule on the absolute lines.
+__global__ void k_vertices(const SetDesc *__restrict__ sets, int nsets,
+                           const int *__restrict__ set_off, int total,
+                           const int *__restrict__ cell_off, const int *__restrict__ nbr,
+                           const int *__restrict__ ecell, const int2 *__restrict__ xyid,
+                           Rat *__restrict__ vtx, const int *__restrict__ status) {
+    if (*status) return;
+    const long long E = cell_off[total];
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < E; e += stride) {
+        const int g = ecell[e];
+        const SetDesc S = sets[find_set(set_off, nsets, g)];
+        const int k = g - S.site_off;
+        const int lo = cell_off[g], hi = cell_off[g + 1];
+        const int a = nbr[e];
+        const int b = nbr[e + 1 == hi ? lo : e + 1];
+        long long n1x, n1y, c1, n2x, n2y, c2;
+        abs_line(S, xyid, k, a, n1x, n1y, c1);
+        abs_line(S, xyid, k, b, n2x, n2y, c2);
+        const long long D = n1x * n2y - n1y * n2x;
+        const i128 X = (i128)c1 * n2y - (i128)c2 * n1y;
+        const i128 Y = (i128)n1x * c2 - (i128)n2x * c1;
+        Rat v;
+        v.x_lo = (uint64_t)X;
+        v.x_hi = (int64_t)(X >> 64);
+        v.y_lo = (uint64_t)Y;
+        v.y_hi = (int64_t)(Y >> 64);
+        v.d = D;
+        vtx[e] = v;
+    }
 }
 
 __global__ void k_delaunay(const SetDesc *__restrict__ sets, int nsets,
@@ -477,7 +504,7 @@ void launch_stage(const PipeArgs &a, hipStream_t st, int stage) {
                                           a.status());
     } else if (stage == 1) {
     // 3. cells
-    if (a.exact_only) {
+    if (a.exact_only || a.coop_all) {
         k_queue_all<<<nblk(T, 256), 256, 0, st>>>(T, a.queue, a.qcount(), a.status());
     } else {
         const int B = a.block;
@@ -521,9 +548,14 @@ void launch_stage(const PipeArgs &a, hipStream_t st, int stage) {
     // 4. CSR
     launch_scan(a.ocnt, T, a.cell_off, a.scan_tmp, a.status(), 1, st);
     k_fill<<<nblk(T, 256), 256, 0, st>>>(a.sets, a.nsets, a.set_off, T, a.ocnt, a.olines, a.ovf,
-                                          a.pool, a.cell_off, a.nbr_cap, a.xyid, a.nbr,
-                                          a.with_vertices ? (Rat *)a.vtx : nullptr, a.dcnt,
+                                          a.pool, a.cell_off, a.nbr_cap, a.nbr, a.ecell, a.dcnt,
                                           a.status_rw());
+    if (a.with_vertices) {
+        const long long cap = a.nbr_cap;
+        const unsigned nb = (unsigned)std::min<long long>(nblk(cap, 256), 8192);
+        k_vertices<<<nb, 256, 0, st>>>(a.sets, a.nsets, a.set_off, T, a.cell_off, a.nbr, a.ecell,
+                                       a.xyid, (Rat *)a.vtx, a.status());
+    }
     launch_scan(a.dcnt, T, a.del_off, a.scan_tmp, a.status(), 1, st);
     k_delaunay<<<nblk(T, 256), 256, 0, st>>>(a.sets, a.nsets, a.set_off, T, a.cell_off, a.nbr,
                                               a.del_off, a.del, a.del_cap, a.status_rw());
