@@ -1,0 +1,160 @@
+"""Batched sets in one launch and the continuous-batching request loop, through the C ABI."""
+import time
+
+import numpy as np
+import pytest
+
+import sitegen
+from oracle import cdiagram
+from tests.gpu_util import assert_matches_oracle, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def vor():
+    import paper_1212_1095_amd as v
+    return v
+
+
+def same(a, b):
+    assert np.array_equal(a.cell_off, b.cell_off)
+    assert np.array_equal(a.nbr, b.nbr)
+    assert np.array_equal(a.dele, b.dele)
+    if a.vtx is not None or b.vtx is not None:
+        assert a.vtx.tobytes() == b.vtx.tobytes()
+
+
+def uneven_sets(k, seed, lo=32, hi=4096):
+    sizes = sitegen.batch_sizes(k, seed, lo, hi)
+    return sitegen.batch_sets(k, seed, B=1 << 20, lo=lo, hi=hi, sizes=sizes)
+
+
+def test_batch_matches_oracle_and_single(vor):
+    sets = uneven_sets(48, seed=4)
+    say(f"batch of {len(sets)} sets, total {sum(s.n for s in sets)} sites")
+    with vor.Context() as ctx:
+        rc, res = ctx.compute_batch([(s.x, s.y, s.box) for s in sets])
+        assert rc == vor.VOR_OK
+        for s, r in zip(sets, res):
+            assert r.status == vor.VOR_OK
+            assert_matches_oracle(r, s)
+        for s, r in zip(sets[:8], res[:8]):
+            same(r, ctx.compute(s.x, s.y, s.box))
+
+
+def test_batch_mixed_boxes_and_distributions(vor):
+    sets = [sitegen.uniform(700, 1 << 16, 11), sitegen.clustered(900, 1 << 24, 12),
+            sitegen.lattice(400, 1 << 24, 13), sitegen.small_integer_set(60, 12, 14),
+            sitegen.uniform(1, 1 << 10, 15)]
+    with vor.Context() as ctx:
+        rc, res = ctx.compute_batch([(s.x, s.y, s.box) for s in sets])
+        assert rc == vor.VOR_OK
+        for s, r in zip(sets, res):
+            assert_matches_oracle(r, s)
+
+
+def test_batch_with_a_bad_set(vor):
+    good = sitegen.uniform(300, 1 << 12, 21)
+    bad_x = np.array([5, 5, 9], np.int32)
+    bad_y = np.array([6, 6, 9], np.int32)
+    with vor.Context() as ctx:
+        rc, res = ctx.compute_batch([(good.x, good.y, good.box), (bad_x, bad_y, (0, 0, 20, 20)),
+                                     (good.x, good.y, good.box)])
+        assert rc == vor.VOR_E_DUPLICATE
+        assert res[1].status == vor.VOR_E_DUPLICATE
+        assert res[0].status == vor.VOR_OK and res[2].status == vor.VOR_OK
+        assert_matches_oracle(res[0], good)
+        same(res[0], res[2])
+
+
+def test_batch_repeated_calls_replay(vor):
+    """The second call with the same shapes replays the captured graph; results identical."""
+    sets = uneven_sets(16, seed=5, hi=2048)
+    args = [(s.x, s.y, s.box) for s in sets]
+    with vor.Context() as ctx:
+        _, r1 = ctx.compute_batch(args)
+        _, r2 = ctx.compute_batch(args)
+        for a, b in zip(r1, r2):
+            same(a, b)
+        assert r2[0].graph_replayed in (0, 1)
+
+
+def wait_all(ctx, tickets, timeout=120.0):
+    out = {}
+    t0 = time.time()
+    while len(out) < len(tickets):
+        for t in tickets:
+            if t in out:
+                continue
+            st, r = ctx.poll(t)
+            if st != 1:   # VOR_PENDING
+                out[t] = (st, r)
+        assert time.time() - t0 < timeout, "requests did not finish"
+        time.sleep(0.002)
+    return out
+
+
+def test_serving_results_identical_alone_and_in_mix(vor):
+    rng = np.random.default_rng(9)
+    reqs = []
+    for i in range(24):
+        kind = i % 4
+        n = int(rng.integers(100, 6000))
+        if kind == 0:
+            reqs.append(sitegen.uniform(n, 1 << 24, 100 + i))
+        elif kind == 1:
+            reqs.append(sitegen.clustered(n, 1 << 24, 100 + i))
+        elif kind == 2:
+            reqs.append(sitegen.lattice(n, 1 << 24, 100 + i))
+        else:
+            reqs.append(sitegen.uniform(n, 1 << 16, 100 + i))
+    with vor.Context() as ctx:
+        tickets = [ctx.submit(r.x, r.y, r.box) for r in reqs]
+        say(f"submitted {len(tickets)} requests")
+        done = wait_all(ctx, tickets)
+        for t, r in zip(tickets, reqs):
+            st, res = done[t]
+            assert st == vor.VOR_OK, (t, st)
+            ts, ta, td = ctx.times(t)
+            assert ts <= ta <= td
+            alone = ctx.compute(r.x, r.y, r.box)
+            same(res, alone)
+        for r, t in list(zip(reqs, tickets))[:6]:
+            assert_matches_oracle(done[t][1], r)
+        # a consumed ticket
+        st, _ = ctx.poll(tickets[0])
+        assert st == vor.VOR_E_TICKET
+        st, _ = ctx.poll(123456789)
+        assert st == vor.VOR_E_TICKET
+
+
+def test_serving_bad_request_and_budget(vor):
+    good = sitegen.uniform(2000, 1 << 20, 31)
+    # a budget that holds one such request at a time: admission queues, never fails
+    with vor.Context(hbm_budget_bytes=4 << 20) as ctx:
+        tickets = [ctx.submit(good.x, good.y, good.box) for _ in range(5)]
+        bad = ctx.submit(np.array([1, 1], np.int32), np.array([2, 2], np.int32), (0, 0, 8, 8))
+        done = wait_all(ctx, tickets + [bad])
+        ref = None
+        for t in tickets:
+            st, r = done[t]
+            assert st == vor.VOR_OK
+            if ref is None:
+                ref = r
+                assert_matches_oracle(r, good)
+            else:
+                same(r, ref)
+        assert done[bad][0] == vor.VOR_E_DUPLICATE
+        big = sitegen.uniform(60000, 1 << 24, 32)
+        t = ctx.submit(big.x, big.y, big.box)
+        st, _ = wait_all(ctx, [t])[t]
+        assert st == vor.VOR_E_NOMEM
+
+
+def test_destroy_with_pending_requests(vor):
+    ctx = vor.Context()
+    ps = sitegen.uniform(20000, 1 << 24, 41)
+    for _ in range(4):
+        ctx.submit(ps.x, ps.y, ps.box)
+    ctx.close()   # cancels pending requests, joins the loop, frees results
