@@ -36,9 +36,79 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def make_workload(n, B, seed):
+def make_workload(n, B, seed, dist="uniform"):
     import sitegen
-    return sitegen.uniform(n, B, seed=seed)
+    gen = {"uniform": sitegen.uniform, "clustered": sitegen.clustered,
+           "lattice": sitegen.lattice}[dist]
+    return gen(n, B, seed=seed)
+
+
+def bench_batched(vor, k=4096, seed=4, steps=3):
+    """4096 independent sets, sizes log-uniform in [32, 65536], uniform in [1, 2^20)^2, in one
+    launch per stage (graph replayed); host inputs and host results, as the batch API takes."""
+    import sitegen
+    sets = sitegen.batch_sets(k, seed, B=1 << 20, lo=32, hi=65536)
+    args = [(s.x, s.y, s.box) for s in sets]
+    total = sum(s.n for s in sets)
+    with vor.Context(flags=vor.VOR_NO_VERTICES) as ctx:
+        ctx.compute_batch(args)   # warm-up and graph capture
+        t0 = time.perf_counter()
+        dev = []
+        for _ in range(steps):
+            rc, res = ctx.compute_batch(args)
+            dev.append(res[0].device_ms)
+        wall = (time.perf_counter() - t0) / steps
+    return {"sets": k, "sites": int(total), "cells_per_s_end_to_end": round(total / wall, 1),
+            "cells_per_s_device": round(total / (np.mean(dev) / 1000.0), 1),
+            "device_ms": round(float(np.mean(dev)), 3), "wall_ms": round(1000 * wall, 3),
+            "vertices": False}
+
+
+def bench_served(vor, count=200, seed=5, qps=None, max_n=1 << 18):
+    """Poisson request stream (sizes log-uniform in [100, max_n], 45/45/10 uniform / clustered /
+    lattice, in [1, 2^24)^2): p50 / p99 latency from submission to result, and cells/s."""
+    import sitegen
+    reqs = sitegen.request_stream(count, qps or 1.0, seed=seed, hi=max_n)
+    with vor.Context(flags=vor.VOR_NO_VERTICES) as ctx:
+        # capacity: run the stream back to back once to size the arrival rate
+        t0 = time.perf_counter()
+        tks = [ctx.submit(r.x, r.y, r.box) for _, r in reqs]
+        pending = set(tks)
+        while pending:
+            for t in list(pending):
+                st, _ = ctx.poll(t)
+                if st != vor.VOR_PENDING:
+                    pending.discard(t)
+            time.sleep(0.0005)
+        cap_s = time.perf_counter() - t0
+        total = sum(r.n for _, r in reqs)
+        rate = count / cap_s          # requests per second at saturation
+        out = {"requests": count, "sites": int(total), "capacity_req_per_s": round(rate, 1)}
+        for rho in (0.5, 0.8):
+            arrivals = np.array([a for a, _ in reqs]) / (rho * rate)
+            lat, t_start = [], time.perf_counter()
+            tickets, i = [], 0
+            pending = {}
+            while i < count or pending:
+                now = time.perf_counter() - t_start
+                while i < count and arrivals[i] <= now:
+                    r = reqs[i][1]
+                    pending[ctx.submit(r.x, r.y, r.box)] = i
+                    i += 1
+                for t in list(pending):
+                    st, _ = ctx.poll(t)
+                    if st != vor.VOR_PENDING:
+                        ts, ta, td = ctx.times(t) if st == vor.VOR_OK else (0, 0, 0)
+                        lat.append(td - ts)
+                        del pending[t]
+                time.sleep(0.0002)
+            wall = time.perf_counter() - t_start
+            lat_ms = 1000 * np.array(lat)
+            out[f"load_{rho}"] = {"qps": round(rho * rate, 1),
+                                  "p50_ms": round(float(np.percentile(lat_ms, 50)), 3),
+                                  "p99_ms": round(float(np.percentile(lat_ms, 99)), 3),
+                                  "cells_per_s": round(total / wall, 1)}
+    return out
 
 
 def cpu_baseline(ps, res, budget_s=12.0, threads=None):
@@ -82,6 +152,7 @@ def main():
     ap.add_argument("--n", type=int, default=1 << 20)
     ap.add_argument("--box", type=int, default=1 << 24)
     ap.add_argument("--seed", type=int, default=2)
+    ap.add_argument("--dist", default="uniform", choices=["uniform", "clustered", "lattice"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--extras", action="store_true", help="also time exact-only mode")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
@@ -111,7 +182,7 @@ def main():
 
     assert torch.cuda.is_available(), "bench needs a GPU"
     dev = torch.device("cuda:0")
-    ps = make_workload(args.n, args.box, args.seed)
+    ps = make_workload(args.n, args.box, args.seed, args.dist)
     log(f"workload: n={ps.n} box={ps.box} seed={args.seed}")
     xd = torch.from_numpy(ps.x).to(dev)
     yd = torch.from_numpy(ps.y).to(dev)
@@ -187,6 +258,12 @@ def main():
             ew = (time.perf_counter() - t0) / k
         extra["exact_only_cells_per_s"] = round(ps.n / ew, 1)
         extra["exact_only_ms_per_step"] = round(1000 * ew, 3)
+        log("batched ...")
+        extra["batched"] = bench_batched(vor)
+        log(f"batched: {extra['batched']}")
+        log("served ...")
+        extra["served"] = bench_served(vor)
+        log(f"served: {extra['served']}")
 
     out = {
         "metric": "Voronoi cells/sec (bit-exact) plain vs batched; p50/p99 latency per request",
@@ -201,7 +278,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+i128",
         "data": "synthetic",
-        "config": {"workload": f"single set, n={ps.n} uniform sites in [1,{args.box})^2, "
+        "config": {"workload": f"single set, n={ps.n} {args.dist} sites in [1,{args.box})^2, "
                                f"X=[0,{args.box}]^2, seed {args.seed}, FP32 filter + exact "
                                f"fallback, vertices and Delaunay edges",
                    "n": ps.n, "box": args.box, "mode": "plain (single set)"},
