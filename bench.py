@@ -36,6 +36,34 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+KERNEL_SOURCES = ("paper_1212_1095_amd/csrc/vor_cell.hpp", "paper_1212_1095_amd/csrc/vor_device.hpp",
+                  "paper_1212_1095_amd/csrc/vor_kernels.hip", "paper_1212_1095_amd/csrc/vor_internal.h")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, tag):
+    """HBM bytes per launch of `kernel` from the committed counter summary of this workload
+    (FETCH_SIZE and WRITE_SIZE, scaled by a plain-copy calibration), or None when there is no
+    summary or the kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{tag}.md")
+    try:
+        text = open(path).read()
+        rec = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+    except (OSError, IndexError, ValueError):
+        return None
+    if rec.get("kernel") != kernel or rec.get("source_hash") != kernel_source_hash():
+        return None
+    return int(rec["bytes_per_launch"])
+
+
 def make_workload(n, B, seed, dist="uniform"):
     import sitegen
     gen = {"uniform": sitegen.uniform, "clustered": sitegen.clustered,
@@ -224,9 +252,14 @@ def main():
     evals = st.evals
     kern_s = float(np.mean(cells_ms)) / 1000.0
     achieved = evals * FLOPS_PER_EVAL / kern_s / 1e12
+    kname = "vor::k_cells_fast<256>"
+    traffic = (measured_traffic(kname, f"{args.dist}_n{ps.n}")
+               if (args.box, args.seed) == (1 << 24, 2) else None)
     roofline = {"bound": "alu", "achieved": round(achieved, 4), "peak": PEAK_FP32_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 6), "traffic": None,
-                "kernel": "k_cells_fast<256>", "kernel_ms": round(1000 * kern_s, 4),
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 6),
+                "traffic": traffic, "traffic_unit": "bytes per launch",
+                "traffic_GBps": (round(traffic / kern_s / 1e9, 1) if traffic else None),
+                "kernel": kname, "kernel_ms": round(1000 * kern_s, 4),
                 "flops_per_eval": FLOPS_PER_EVAL, "evals_per_launch": int(evals),
                 "frac_nonpacked_peak": round(achieved / PEAK_FP32_NONPACKED, 6)}
 
