@@ -184,6 +184,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--extras", action="store_true", help="also time exact-only mode")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--path", default=None, choices=["grid", "tree"],
+                    help="scan path (default: the library's)")
+    ap.add_argument("--sites-per-bucket", type=float, default=None)
+    ap.add_argument("--block-halfwidth", type=int, default=None)
+    ap.add_argument("--leaf-halfwidth", type=int, default=None)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB mebibytes (counter calibration)")
     args = ap.parse_args()
@@ -218,6 +223,13 @@ def main():
 
     ctx = vor.Context(device=0, precision=vor.VOR_FP32_FILTERED,
                       flags=vor.VOR_RESULT_DEVICE | vor.VOR_TIME_KERNELS)
+    tuning = list(vor.vor_get_tuning(ctx.h))
+    for i, v in ((0, args.sites_per_bucket), (2, args.block_halfwidth), (3, args.leaf_halfwidth),
+                 (4, None if args.path is None else (1 if args.path == "tree" else 0))):
+        if v is not None:
+            tuning[i] = v
+    ctx.tune(*tuning)
+    log(f"tuning (sites/bucket, block, h, leaf h, path): {tuning}")
 
     def step():
         return ctx.compute((xd.data_ptr(), ps.n), (yd.data_ptr(), ps.n), ps.box,
@@ -226,11 +238,12 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    cells_ms, dev_ms, last = [], [], None
+    cells_ms, adapt_ms, dev_ms, last = [], [], [], None
     t0 = time.perf_counter()
     for _ in range(args.steps):
         last = step()
         cells_ms.append(last.cells_ms)
+        adapt_ms.append(last.adaptive_ms)
         dev_ms.append(last.device_ms)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -238,7 +251,8 @@ def main():
     value = ps.n / (wall / args.steps)
     st = last.stats
     log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step, device {np.mean(dev_ms):.3f} ms, "
-        f"grid {last.grid_ms:.3f} cells {np.mean(cells_ms):.3f} exact {last.exact_ms:.3f} "
+        f"grid {last.grid_ms:.3f} cells {np.mean(cells_ms):.3f} adaptive {np.mean(adapt_ms):.3f} "
+        f"exact {last.exact_ms:.3f} "
         f"emit {last.emit_ms:.3f} ms, graph {last.graph_replayed}; stats {st}")
     ctx.close()
 
@@ -246,13 +260,21 @@ def main():
     res = None
     if not args.no_cpu:
         with vor.Context(device=0) as hctx:
+            hctx.tune(*tuning)
             res = hctx.compute(ps.x, ps.y, ps.box)
 
-    # roofline of the dominant kernel: algorithmic flops per launch / mean launch duration
-    evals = st.evals
-    kern_s = float(np.mean(cells_ms)) / 1000.0
+    # roofline of the dominant kernel: algorithmic flops per launch / mean launch duration.
+    # The filtered grid pass and the adaptive (coordinate-rectangle) pass each run as one
+    # kernel; the evaluations of the exact pass (a few hundred cells) count with the grid pass.
+    if float(np.mean(adapt_ms)) > float(np.mean(cells_ms)):
+        evals = st.adaptive_evals
+        kern_s = float(np.mean(adapt_ms)) / 1000.0
+        kname = "vor::k_cells_tree<128>"
+    else:
+        evals = st.evals - st.adaptive_evals
+        kern_s = float(np.mean(cells_ms)) / 1000.0
+        kname = "vor::k_cells_fast<256>"
     achieved = evals * FLOPS_PER_EVAL / kern_s / 1e12
-    kname = "vor::k_cells_fast<256>"
     traffic = (measured_traffic(kname, f"{args.dist}_n{ps.n}")
                if (args.box, args.seed) == (1 << 24, 2) else None)
     roofline = {"bound": "alu", "achieved": round(achieved, 4), "peak": PEAK_FP32_TFLOPS,
@@ -324,7 +346,12 @@ def main():
                   "exact_decisions": st.exact_decisions, "deferred_cells": st.deferred_cells,
                   "edges_per_cell": round(st.edges / ps.n, 3),
                   "device_ms": round(float(np.mean(dev_ms)), 4),
+                  "adaptive_cells": st.adaptive_cells,
+                  "tuning": {"sites_per_bucket": tuning[0], "block": tuning[1],
+                             "block_halfwidth": tuning[2], "leaf_halfwidth": tuning[3],
+                             "path": "tree" if tuning[4] == 1 else "grid-first"},
                   "stage_ms": {"grid": round(last.grid_ms, 4), "cells": round(last.cells_ms, 4),
+                               "adaptive": round(last.adaptive_ms, 4),
                                "exact": round(last.exact_ms, 4), "emit": round(last.emit_ms, 4)},
                   "graph_replayed": bool(last.graph_replayed)},
     }

@@ -102,6 +102,9 @@ typedef struct {
     uint64_t shells;          /* bucket shells scanned                                        */
     uint64_t edges;           /* sum of e_k                                                   */
     uint64_t vertex_tests;    /* rays towards a candidate vertex that confirmed it            */
+    uint64_t adaptive_cells;  /* cells whose scans met a crowded bucket, computed again over
+                                 the refined buckets (adaptive bucketing of Method 11.5)      */
+    uint64_t adaptive_evals;  /* candidate evaluations of that pass (included in evals)       */
 } vor_stats;
 
 /* Result of one point set.  Host memory owned by the library (device memory with
@@ -120,10 +123,11 @@ typedef struct {
     float device_ms;           /* device time of the pipeline (HIP events)                     */
     float cells_ms;            /* with VOR_TIME_KERNELS: filtered cell pass                    */
     float exact_ms;            /* with VOR_TIME_KERNELS: exact / deep cell passes              */
-    float grid_ms;             /* with VOR_TIME_KERNELS: validation and grid build             */
+    float grid_ms;             /* with VOR_TIME_KERNELS: validation, grid build, refinement    */
     float emit_ms;             /* with VOR_TIME_KERNELS: CSR, vertices, Delaunay edges         */
     int32_t graph_replayed;    /* 1 when the pipeline ran as replayed HIP graph(s)            */
     int32_t status;            /* VOR_OK, or the error of this set inside a batch             */
+    float adaptive_ms;         /* with VOR_TIME_KERNELS: the pass over refined buckets         */
 } vor_result;
 
 /* Create a context on opts->device (NULL opts: device 0, FP32 filtered, host results). */
@@ -158,11 +162,19 @@ const char *vor_strerror(int status);
 /* Tuning knobs (chosen by the autotuner).  sites_per_bucket: target mean bucket occupancy
  * of the uniform grid (Method 11.5); block: threads per workgroup of the cell kernel
  * (64, 128 or 256); block_halfwidth: h, the cell's (2h+1)^2 bucket block scanned before
- * further shells (1..16, 0 = round(2 / sqrt(sites_per_bucket))). */
+ * further shells (1..16, 0 = round(2 / sqrt(sites_per_bucket))); leaf_halfwidth: leaf sides
+ * around p's leaf bucket that the coordinate-rectangle scan takes first (0..4); scan_path:
+ * VOR_PATH_GRID_FIRST (bucket-rectangle scans, cells that meet a crowded bucket move to the
+ * coordinate-rectangle scan over the refined buckets) or VOR_PATH_TREE (every cell through the
+ * coordinate-rectangle scan).  Results do not depend on any knob. */
+#define VOR_PATH_GRID_FIRST 0
+#define VOR_PATH_TREE 1
 typedef struct {
     float sites_per_bucket;
     int32_t block;
     int32_t block_halfwidth;
+    int32_t leaf_halfwidth;
+    int32_t scan_path;
 } vor_tuning;
 
 int vor_set_tuning(vor_ctx *ctx, const vor_tuning *t);

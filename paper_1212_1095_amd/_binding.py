@@ -16,6 +16,7 @@ VOR_E_INVAL, VOR_E_DOMAIN, VOR_E_DUPLICATE, VOR_E_NOMEM = -1, -2, -3, -4
 VOR_E_DEVICE, VOR_E_TICKET, VOR_E_CAPACITY = -5, -6, -7
 VOR_SET_DEVICE, VOR_RESULT_DEVICE, VOR_NO_VERTICES, VOR_CHECK_SYMMETRY = 0x1, 0x2, 0x4, 0x8
 VOR_TIME_KERNELS = 0x10
+VOR_PATH_GRID_FIRST, VOR_PATH_TREE = 0, 1
 VOR_EXACT_ONLY, VOR_FP32_FILTERED = 0, 1
 
 
@@ -41,7 +42,8 @@ class vor_rat(C.Structure):
 class vor_stats(C.Structure):
     _fields_ = [(k, C.c_uint64) for k in ("rays", "nodes", "evals", "exact_decisions",
                                            "deferred_cells", "asym_pairs", "shells", "edges",
-                                           "vertex_tests")]
+                                           "vertex_tests", "adaptive_cells",
+                                           "adaptive_evals")]
 
 
 class vor_result(C.Structure):
@@ -49,12 +51,14 @@ class vor_result(C.Structure):
                 ("vtx", C.c_void_p), ("m", C.c_uint64), ("del_", C.c_void_p),
                 ("stats", vor_stats), ("device_ms", C.c_float), ("cells_ms", C.c_float),
                 ("exact_ms", C.c_float), ("grid_ms", C.c_float), ("emit_ms", C.c_float),
-                ("graph_replayed", C.c_int32), ("status", C.c_int32)]
+                ("graph_replayed", C.c_int32), ("status", C.c_int32),
+                ("adaptive_ms", C.c_float)]
 
 
 class vor_tuning(C.Structure):
     _fields_ = [("sites_per_bucket", C.c_float), ("block", C.c_int32),
-                ("block_halfwidth", C.c_int32)]
+                ("block_halfwidth", C.c_int32), ("leaf_halfwidth", C.c_int32),
+                ("scan_path", C.c_int32)]
 
 
 _lib = None
@@ -150,6 +154,8 @@ class Stats:
     shells: int
     edges: int
     vertex_tests: int
+    adaptive_cells: int
+    adaptive_evals: int
 
 
 @dataclass
@@ -167,6 +173,7 @@ class Result:
     grid_ms: float = 0.0
     emit_ms: float = 0.0
     graph_replayed: int = 0
+    adaptive_ms: float = 0.0
 
     def lines(self, k: int) -> list:
         return self.nbr[self.cell_off[k]:self.cell_off[k + 1]].tolist()
@@ -191,7 +198,7 @@ def _to_result(rp, device: bool = False) -> Result:
         res = Result(n, np.zeros(0, np.uint32), np.zeros(0, np.int32), None,
                      np.zeros((0, 2), np.uint32), st, float(r.device_ms), int(r.status),
                      float(r.cells_ms), float(r.exact_ms), float(r.grid_ms),
-                     float(r.emit_ms), int(r.graph_replayed))
+                     float(r.emit_ms), int(r.graph_replayed), float(r.adaptive_ms))
         res.device_ptrs = {"cell_off": r.cell_off, "nbr": r.nbr, "vtx": r.vtx, "del": r.del_,
                            "m": int(r.m)}
         return res
@@ -199,7 +206,7 @@ def _to_result(rp, device: bool = False) -> Result:
         return Result(n, np.zeros(0, np.uint32), np.zeros(0, np.int32), None,
                       np.zeros((0, 2), np.uint32), st, float(r.device_ms), int(r.status),
                       float(r.cells_ms), float(r.exact_ms), float(r.grid_ms), float(r.emit_ms),
-                      int(r.graph_replayed))
+                      int(r.graph_replayed), float(r.adaptive_ms))
     off = np.ctypeslib.as_array(C.cast(r.cell_off, C.POINTER(C.c_uint32)), (n + 1,)).copy()
     E = int(off[-1])
     nbr = (np.ctypeslib.as_array(C.cast(r.nbr, C.POINTER(C.c_int32)), (E,)).copy()
@@ -213,7 +220,7 @@ def _to_result(rp, device: bool = False) -> Result:
             .reshape(m, 2) if m else np.zeros((0, 2), np.uint32))
     return Result(n, off, nbr, vtx, dele, st, float(r.device_ms), int(r.status),
                   float(r.cells_ms), float(r.exact_ms), float(r.grid_ms), float(r.emit_ms),
-                  int(r.graph_replayed))
+                  int(r.graph_replayed), float(r.adaptive_ms))
 
 
 def vor_result_free(rp) -> None:
@@ -283,15 +290,17 @@ def vor_ticket_times(ctx, ticket: int):
     return a.value, b.value, c.value
 
 
-def vor_set_tuning(ctx, sites_per_bucket: float, block: int, block_halfwidth: int = 0) -> None:
-    t = vor_tuning(sites_per_bucket, block, block_halfwidth)
+def vor_set_tuning(ctx, sites_per_bucket: float, block: int, block_halfwidth: int = 0,
+                   leaf_halfwidth: int = 0, scan_path: int = 0) -> None:
+    t = vor_tuning(sites_per_bucket, block, block_halfwidth, leaf_halfwidth, scan_path)
     _check(lib().vor_set_tuning(ctx, C.byref(t)), "vor_set_tuning")
 
 
 def vor_get_tuning(ctx):
     t = vor_tuning()
     _check(lib().vor_get_tuning(ctx, C.byref(t)), "vor_get_tuning")
-    return float(t.sites_per_bucket), int(t.block), int(t.block_halfwidth)
+    return (float(t.sites_per_bucket), int(t.block), int(t.block_halfwidth),
+            int(t.leaf_halfwidth), int(t.scan_path))
 
 
 class Context:
@@ -318,8 +327,9 @@ class Context:
     def times(self, ticket):
         return vor_ticket_times(self.h, ticket)
 
-    def tune(self, sites_per_bucket, block, block_halfwidth=0):
-        vor_set_tuning(self.h, sites_per_bucket, block, block_halfwidth)
+    def tune(self, sites_per_bucket, block, block_halfwidth=0, leaf_halfwidth=0, scan_path=0):
+        vor_set_tuning(self.h, sites_per_bucket, block, block_halfwidth, leaf_halfwidth,
+                       scan_path)
 
     def close(self):
         if self.h:

@@ -19,6 +19,7 @@
 #include "vor.h"
 #include "vor_device.hpp"
 #include "vor_internal.h"
+#include "vor_tree.hpp"
 
 using namespace vor;
 
@@ -74,7 +75,8 @@ struct HostBuf {   // pinned staging
 enum BufId {
     B_SETS, B_SETOFF, B_INX, B_INY, B_XYID, B_KEY, B_BCNT, B_BSTART, B_SXY, B_SID, B_OCNT,
     B_OLINES, B_OVF, B_POOL, B_QUEUE, B_QUEUE2, B_WBUF, B_WBUF2, B_CELLOFF, B_NBR, B_VTX,
-    B_DCNT, B_DELOFF, B_DEL, B_SCANTMP, B_SMALL, B_STATS, B_ECELL, B_COUNT
+    B_DCNT, B_DELOFF, B_DEL, B_SCANTMP, B_SMALL, B_STATS, B_ECELL, B_TCHILD, B_NODES, B_TXY,
+    B_TID, B_QUEUE3, B_SETTREE, B_TREF, B_COUNT
 };
 
 struct Workspace {
@@ -203,7 +205,7 @@ struct Request {
 struct vor_ctx {
     int device = 0;
     vor_opts opts{};
-    vor_tuning tune{1.0f, 256, 0};
+    vor_tuning tune{1.0f, 256, 0, 0, VOR_PATH_GRID_FIRST};
     Workspace ws;            // vor_compute / vor_compute_batch
     std::mutex mu;           // serialises vor_compute*
     bool use_graph = true;
@@ -231,7 +233,10 @@ size_t footprint_bytes(uint64_t total, uint64_t gtot, bool vertices) {
     b += E * 4 * 3;                                                 // pool, nbr, owners
     if (vertices) b += E * sizeof(vor_rat);
     b += (3 * total + 8) * 8;                                       // delaunay
-    b += gtot * 8;
+    b += gtot * 16;                                                 // counts, starts, tree slots
+    b += total * (8 + 4 + 4);                                       // refinement scratch, queue
+    b += (3 * total + 1024) * 8;                                    // sub-bucket tables
+    b += (TREE_LEVELS * (total / (TREE_C1 + 1)) + 64) * sizeof(TNode);
     return b;
 }
 
@@ -255,6 +260,7 @@ int launch(vor_ctx *ctx, Workspace &ws, const std::vector<HostSet> &sets, bool v
         d.n = (int32_t)s.n;
         d.site_off = (int32_t)total;
         choose_grid(s.box, s.n, ctx->tune.sites_per_bucket, ctx->tune.block_halfwidth, d);
+        d.ht = ctx->tune.leaf_halfwidth;
         d.bucket_off = (int32_t)gtot;
         set_off[i] = (int)total;
         total += s.n;
@@ -271,10 +277,17 @@ int launch(vor_ctx *ctx, Workspace &ws, const std::vector<HostSet> &sets, bool v
     const int exact_blocks =
         (int)std::max<long long>(1, std::min<long long>(exact_only || coop_all ? 8192 : 2048, T));
     const long long stmp = scan_tmp_ints(std::max(T, gtot)) + 8;
+    // refinement: every node holds > TREE_C1 sites and the nodes of one level are disjoint;
+    // a node's table has m*m + 1 <= 2 cnt + 1 entries; a table or node overflow leaves the
+    // bucket unrefined (slower, still exact)
+    const long long ncap = std::max<long long>(64, TREE_LEVELS * (T / (TREE_C1 + 1)) + 64);
+    const long long tabcap = 3 * T + 1024;
     struct Need { int id; size_t bytes; } need[] = {
         {B_SETS, sizeof(SetDesc) * K}, {B_SETOFF, 4ull * (K + 1)}, {B_INX, 4ull * T},
         {B_INY, 4ull * T}, {B_XYID, 8ull * T}, {B_KEY, 4ull * T}, {B_BCNT, 4ull * gtot},
-        {B_BSTART, 4ull * (gtot + 1)}, {B_SXY, 8ull * T}, {B_SID, 4ull * T},
+        {B_BSTART, 4ull * (gtot + 1 + tabcap)}, {B_TCHILD, 4ull * (gtot + 1 + tabcap)},
+        {B_NODES, sizeof(TNode) * ncap}, {B_TXY, 8ull * T}, {B_TID, 4ull * T},
+        {B_QUEUE3, 4ull * T}, {B_SETTREE, 4ull * K}, {B_TREF, 4ull * (gtot + 1)}, {B_SXY, 8ull * T}, {B_SID, 4ull * T},
         {B_OCNT, 4ull * T}, {B_OLINES, 4ull * KOUT * T}, {B_OVF, 4ull * T}, {B_POOL, 4ull * E},
         {B_QUEUE, 4ull * T}, {B_QUEUE2, 4ull * T},
         {B_WBUF, 4ull * 2 * DCAP1 * exact_blocks}, {B_WBUF2, 4ull * 2 * DCAP2 * DEEP_BLOCKS},
@@ -333,6 +346,15 @@ int launch(vor_ctx *ctx, Workspace &ws, const std::vector<HostSet> &sets, bool v
     a.key = ws.b[B_KEY].as<int>();
     a.bcnt = ws.b[B_BCNT].as<int>();
     a.bstart = ws.b[B_BSTART].as<int>();
+    a.tchild = ws.b[B_TCHILD].as<int>();
+    a.nodes = ws.b[B_NODES].as<TNode>();
+    a.ncap = (int)ncap;
+    a.tabcap = tabcap;
+    a.txy = ws.b[B_TXY].as<float2>();
+    a.tid = ws.b[B_TID].as<int>();
+    a.queue3 = ws.b[B_QUEUE3].as<int>();
+    a.set_tree = ws.b[B_SETTREE].as<int>();
+    a.tref = ws.b[B_TREF].as<int>();
     a.sxy = ws.b[B_SXY].as<float2>();
     a.sid = ws.b[B_SID].as<int>();
     a.ocnt = ws.b[B_OCNT].as<int>();
@@ -358,6 +380,7 @@ int launch(vor_ctx *ctx, Workspace &ws, const std::vector<HostSet> &sets, bool v
     a.small = ws.b[B_SMALL].as<int>();
     a.stats = ws.b[B_STATS].as<unsigned long long>();
     a.block = ctx->tune.block;
+    a.tree_all = ctx->tune.scan_path == VOR_PATH_TREE;
     a.exact_only = exact_only;
     a.with_vertices = vertices;
     a.check_symmetry = symmetry;
@@ -456,7 +479,7 @@ Summary read_summary(Workspace &ws) {
             if (hipEventElapsedTime(&s.stage_ms[g], ws.ek[g], ws.ek[g + 1]) != hipSuccess)
                 s.stage_ms[g] = -1.0f;
         s.cells_ms = s.stage_ms[1];
-        s.exact_ms = s.stage_ms[2];
+        s.exact_ms = s.stage_ms[3];
     }
     s.graph = ws.used_graph;
     return s;
@@ -472,6 +495,8 @@ void fill_stats(vor_stats &st, const Summary &s) {
     st.shells = s.stats[SL_SHELLS];
     st.edges = s.stats[SL_EDGES];
     st.vertex_tests = s.stats[SL_VTESTS];
+    st.adaptive_cells = s.stats[SL_TREE];
+    st.adaptive_evals = s.stats[SL_TEVALS];
 }
 
 // Copy the results of every set back to host ResultBoxes (after the stream is idle).
@@ -516,7 +541,8 @@ int collect_host(Workspace &ws, const PipeArgs &a, const std::vector<SetDesc> &d
         r->cells_ms = sm.cells_ms;
         r->exact_ms = sm.exact_ms;
         r->grid_ms = sm.stage_ms[0];
-        r->emit_ms = sm.stage_ms[3];
+        r->adaptive_ms = sm.stage_ms[2];
+        r->emit_ms = sm.stage_ms[4];
         r->graph_replayed = sm.graph ? 1 : 0;
         r->status = VOR_OK;
         outs[i] = r;
@@ -556,7 +582,8 @@ int run_sync(vor_ctx *ctx, Workspace &ws, const std::vector<HostSet> &sets,
         r->cells_ms = sm.cells_ms;
         r->exact_ms = sm.exact_ms;
         r->grid_ms = sm.stage_ms[0];
-        r->emit_ms = sm.stage_ms[3];
+        r->adaptive_ms = sm.stage_ms[2];
+        r->emit_ms = sm.stage_ms[4];
         r->graph_replayed = sm.graph ? 1 : 0;
         r->status = VOR_OK;
         outs.assign(1, r);
@@ -758,6 +785,8 @@ int vor_set_tuning(vor_ctx *ctx, const vor_tuning *t) {
     if (!(t->sites_per_bucket >= 0.0625f && t->sites_per_bucket <= 64.0f)) return VOR_E_INVAL;
     if (t->block != 64 && t->block != 128 && t->block != 256) return VOR_E_INVAL;
     if (t->block_halfwidth < 0 || t->block_halfwidth > 16) return VOR_E_INVAL;
+    if (t->leaf_halfwidth < 0 || t->leaf_halfwidth > 4) return VOR_E_INVAL;
+    if (t->scan_path != VOR_PATH_GRID_FIRST && t->scan_path != VOR_PATH_TREE) return VOR_E_INVAL;
     std::lock_guard<std::mutex> lk(ctx->mu);
     ctx->tune = *t;
     return VOR_OK;

@@ -30,6 +30,7 @@
 // by a butterfly (the exact passes and small sets, where latency matters).
 #pragma once
 #include "vor_device.hpp"
+#include "vor_tree.hpp"
 
 namespace vor {
 
@@ -134,12 +135,14 @@ struct ScanOut {
     Best b;
     float Uw;   // upper bound key of the final winner
     float U;    // smallest upper bound seen
+    float Tr;   // the bound whose S_I the scanned region contains
     Rect A;     // the scanned rectangle (it contains S_I of the endpoint)
 };
 
 // Upper bound key of candidate w (sorted position or side code).
 __device__ __forceinline__ float upper_of(const Cell &C, const float2 *__restrict__ sxy, int w,
                                           float dx, float dy) {
+    if (w == NO_TAG) return FINF;
     if (w >= 0) {
         const float2 a = sxy[w];
         const float ex = a.x - C.pxf, ey = a.y - C.pyf;
@@ -173,7 +176,7 @@ __device__ __forceinline__ void eval_site(const Cell &C, const float2 *__restric
 
 // Row ranges of the cell's warm-start block (up to MAXROWS rows, h <= 2), loaded once per
 // cell.  LdsRows keeps them in a per-thread column of LDS (the filtered pass);
-// GlobalRows reads them from the bucket starts each time.
+// GlobalRows reads them from the bucket starts each time.  load() returns the longest row.
 constexpr int MAXROWS = 5;
 
 template <int BLOCK>
@@ -181,15 +184,19 @@ struct LdsRows {
     int (*lo)[BLOCK];
     int (*hi)[BLOCK];
     int nrows;
-    __device__ __forceinline__ void load(const Cell &C, const int *__restrict__ bstart) {
+    __device__ __forceinline__ int load(const Cell &C, const int *__restrict__ bstart) {
         const Rect A = block_rect(C);
         nrows = A.y1 - A.y0 + 1;
-        if (nrows > MAXROWS) return;
+        if (nrows > MAXROWS) return 0;
+        int longest = 0;
         for (int i = 0; i < nrows; ++i) {
             const int base = C.boff + (A.y0 + i) * C.gx;
-            lo[i][threadIdx.x] = bstart[base + A.x0];
-            hi[i][threadIdx.x] = bstart[base + A.x1 + 1];
+            const int a = bstart[base + A.x0], b = bstart[base + A.x1 + 1];
+            lo[i][threadIdx.x] = a;
+            hi[i][threadIdx.x] = b;
+            longest = max(longest, b - a);
         }
+        return longest;
     }
     __device__ __forceinline__ void get(const Cell &, const int *__restrict__, int r, int &a,
                                         int &b) const {
@@ -200,9 +207,10 @@ struct LdsRows {
 
 struct GlobalRows {
     int nrows;
-    __device__ __forceinline__ void load(const Cell &C, const int *__restrict__) {
+    __device__ __forceinline__ int load(const Cell &C, const int *__restrict__) {
         const Rect A = block_rect(C);
         nrows = A.y1 - A.y0 + 1;
+        return 0;
     }
     __device__ __forceinline__ void get(const Cell &C, const int *__restrict__ bstart, int r,
                                         int &a, int &b) const {
@@ -214,12 +222,13 @@ struct GlobalRows {
 };
 
 // Candidates of rectangle O \ I, one flat loop per lane (a lane pays only for its own
-// candidates); with the Coop policy lane i takes every 64th candidate of each row.
-template <class P>
+// candidates); with the Coop policy lane i takes every 64th candidate of each row.  With
+// DETECT a row segment longer than SEG_HEAVY stops the walk and sets `heavy`.
+template <class P, bool DETECT>
 __device__ __forceinline__ void scan_rect_f32(const Cell &C, const float2 *__restrict__ sxy,
                                               const int *__restrict__ bstart, Rect O, Rect I,
                                               float dx, float dy, int ex1, int ex2, Best &b,
-                                              Counters &K) {
+                                              Counters &K, bool &heavy) {
     RowWalk wk;
     wk.start(O, I);
     int pos = 0, end = 0;
@@ -231,69 +240,28 @@ __device__ __forceinline__ void scan_rect_f32(const Cell &C, const float2 *__res
             continue;
         }
         if (!wk.next(C, bstart)) break;
+        if (DETECT && wk.end - wk.pos > SEG_HEAVY) {
+            heavy = true;
+            break;
+        }
         pos = wk.pos + P::lane();
         end = wk.end;
     }
 }
 
-// One ray: FP32 argmin over the certified candidates (Method 11.6).
-template <class P, class Rows>
-__device__ __forceinline__ ScanOut scan_f32(const Cell &C, const Rows &BR,
-                                            const float2 *__restrict__ sxy,
-                                            const int *__restrict__ bstart, float dx, float dy,
-                                            int ex1, int ex2, float tcap, Counters &K) {
-    Best b{FINF, FINF, -1};
-    // Pass A: the cell's block of shells 0..h, a warm start that bounds the endpoint by y.
-    const Rect A = block_rect(C);
-    if (BR.nrows <= MAXROWS) {
-        int r = 0, pos, end;
-        BR.get(C, bstart, 0, pos, end);
-        pos += P::lane();
-        for (;;) {
-            if (pos < end) {
-                eval_site(C, sxy, pos, dx, dy, ex1, ex2, b);
-                pos += P::W;
-                ++K.evals;
-                continue;
-            }
-            if (++r >= BR.nrows) break;
-            BR.get(C, bstart, r, pos, end);
-            pos += P::lane();
-        }
-    } else {
-        scan_rect_f32<P>(C, sxy, bstart, A, Rect{1, 0, 1, 0}, dx, dy, ex1, ex2, b, K);
-    }
-    P::reduce(b);
-    consider_sides(C, dx, dy, ex1, ex2, b);
-    // The integer rectangle S_I[y, |y - p|] of the bound.  While it is not inside the scanned
-    // rectangle, grow the scanned rectangle towards it (at most doubling per step); the
-    // rectangles of later, nearer bounds nest inside the earlier ones, so the final scanned
-    // rectangle certifies the endpoint.
-    K.shells++;
-    float U = upper_of(C, sxy, b.w, dx, dy);
-    float Uw = U;
-    Rect R = need_rect(C, fminf(U, tcap), dx, dy);
-    Rect O = A;
-    while (!rect_inside(R, O)) {
-        const Rect N = grow_rect(O, R);
-        scan_rect_f32<P>(C, sxy, bstart, N, O, dx, dy, ex1, ex2, b, K);
-        P::reduce(b);
-        O = N;
-        K.shells++;
-        Uw = upper_of(C, sxy, b.w, dx, dy);
-        U = fminf(U, Uw);
-        R = need_rect(C, fminf(U, tcap), dx, dy);
-    }
-    ScanOut o;
-    o.b = b;
-    o.Uw = Uw;
-    o.U = U;
-    o.A = O;
-    return o;
-}
-
 // Exact argmin over rectangle O \ I.  With FILTER only candidates whose FP32 lower bound is
 // <= Tlim count.
+template <bool FILTER, class P>
+__device__ __forceinline__ void exact_site(const Cell &C, float2 a, int q, const Dir &d,
+                                           float lim, XBest &b, Counters &K) {
+    const float ex = a.x - C.pxf, ey = a.y - C.pyf;
+    if (FILTER && !(key_lo_line(site_q(ex, ey), ex, ey, d.fx, d.fy) * CERT_DN <= lim)) return;
+    if (!FILTER) ++K.evals;
+    const int nx = (int)a.x - C.px, ny = (int)a.y - C.py;
+    if ((nx | ny) == 0) return;   // p itself
+    x_consider(b, q, nx, ny, (int64_t)nx * nx + (int64_t)ny * ny, d);
+}
+
 template <bool FILTER, class P>
 __device__ __forceinline__ void exact_rect(const Cell &C, const float2 *__restrict__ sxy,
                                            const int *__restrict__ bstart, const Dir &d, Rect O,
@@ -308,14 +276,7 @@ __device__ __forceinline__ void exact_rect(const Cell &C, const float2 *__restri
             const int q = pos;
             pos += P::W;
             if (q == ex1 || q == ex2) continue;
-            const float2 a = sxy[q];
-            const float ex = a.x - C.pxf, ey = a.y - C.pyf;
-            if (FILTER && !(key_lo_line(site_q(ex, ey), ex, ey, d.fx, d.fy) * CERT_DN <= lim))
-                continue;
-            if (!FILTER) ++K.evals;
-            const int nx = (int)a.x - C.px, ny = (int)a.y - C.py;
-            if ((nx | ny) == 0) continue;   // p itself
-            x_consider(b, q, nx, ny, (int64_t)nx * nx + (int64_t)ny * ny, d);
+            exact_site<FILTER, P>(C, sxy[q], q, d, lim, b, K);
             continue;
         }
         if (!wk.next(C, bstart)) break;
@@ -336,6 +297,429 @@ __device__ __forceinline__ void exact_sides(const Cell &C, const Dir &d, float T
         x_consider(b, code, L.nx, L.ny, L.c, d);
     }
 }
+
+// ------------------------------------------------------------------------------ scanners
+// A scanner answers the three questions a ray asks: the FP32 argmin over a certified region
+// (scan), the exact argmin over the region a scan certified (exact), and the exact argmin with
+// its own certification (exact_all, every decision exact).
+
+// Uniform bucket grid: regions are rectangles of buckets, rows are contiguous ranges.
+template <class P, class Rows, bool DETECT>
+struct GridScan {
+    Rows BR;
+    const int *bstart;
+    bool heavy;
+
+    __device__ __forceinline__ void load(const Cell &C, const float2 *__restrict__) {
+        const int longest = BR.load(C, bstart);
+        heavy = DETECT && longest > SEG_HEAVY;
+    }
+
+    // FP32 argmin (Method 11.6): the cell's block of shells 0..h (a warm start that bounds the
+    // endpoint by y), then while the integer rectangle S_I[y, |y - p|] of the bound is not
+    // inside the scanned rectangle, grow the scanned rectangle towards it (at most doubling per
+    // step); the rectangles of later, nearer bounds nest inside the earlier ones, so the final
+    // scanned rectangle certifies the endpoint.
+    __device__ __forceinline__ ScanOut scan(const Cell &C, const float2 *__restrict__ sxy,
+                                            float dx, float dy, int ex1, int ex2, float tcap,
+                                            Counters &K) {
+        Best b{FINF, FINF, NO_TAG};
+        const Rect A = block_rect(C);
+        if (BR.nrows <= MAXROWS) {
+            int r = 0, pos, end;
+            BR.get(C, bstart, 0, pos, end);
+            pos += P::lane();
+            for (;;) {
+                if (pos < end) {
+                    eval_site(C, sxy, pos, dx, dy, ex1, ex2, b);
+                    pos += P::W;
+                    ++K.evals;
+                    continue;
+                }
+                if (++r >= BR.nrows) break;
+                BR.get(C, bstart, r, pos, end);
+                pos += P::lane();
+            }
+        } else {
+            scan_rect_f32<P, DETECT>(C, sxy, bstart, A, Rect{1, 0, 1, 0}, dx, dy, ex1, ex2, b, K,
+                                     heavy);
+        }
+        P::reduce(b);
+        consider_sides(C, dx, dy, ex1, ex2, b);
+        K.shells++;
+        float U = upper_of(C, sxy, b.w, dx, dy);
+        float Uw = U;
+        Rect R = need_rect(C, fminf(U, tcap), dx, dy);
+        Rect O = A;
+        while (!(DETECT && heavy) && !rect_inside(R, O)) {
+            const Rect N = grow_rect(O, R);
+            scan_rect_f32<P, DETECT>(C, sxy, bstart, N, O, dx, dy, ex1, ex2, b, K, heavy);
+            P::reduce(b);
+            O = N;
+            K.shells++;
+            Uw = upper_of(C, sxy, b.w, dx, dy);
+            U = fminf(U, Uw);
+            R = need_rect(C, fminf(U, tcap), dx, dy);
+        }
+        ScanOut o;
+        o.b = b;
+        o.Uw = Uw;
+        o.U = U;
+        o.Tr = fminf(U, tcap);
+        o.A = O;
+        return o;
+    }
+
+    __device__ __forceinline__ void exact(const Cell &C, const float2 *__restrict__ sxy,
+                                          const Dir &d, const ScanOut &s, float Tlim, int ex1,
+                                          int ex2, XBest &xb, Counters &K) {
+        exact_rect<true, P>(C, sxy, bstart, d, s.A, Rect{1, 0, 1, 0}, Tlim, ex1, ex2, xb, K);
+        P::reduce(xb);
+        exact_sides(C, d, Tlim, true, ex1, ex2, xb);
+    }
+
+    __device__ __forceinline__ void exact_all(const Cell &C, const float2 *__restrict__ sxy,
+                                              const Dir &d, float tu_hi, int ex1, int ex2,
+                                              XBest &xb, Counters &K) {
+        const Rect A = block_rect(C);
+        exact_rect<false, P>(C, sxy, bstart, d, A, Rect{1, 0, 1, 0}, FINF, ex1, ex2, xb, K);
+        P::reduce(xb);
+        exact_sides(C, d, FINF, false, ex1, ex2, xb);
+        Rect O = A;
+        K.shells++;
+        Rect R = need_rect(C, fminf(x_upper(xb, d), tu_hi), d.fx, d.fy);
+        while (!rect_inside(R, O)) {
+            const Rect N = grow_rect(O, R);
+            exact_rect<false, P>(C, sxy, bstart, d, N, O, FINF, ex1, ex2, xb, K);
+            P::reduce(xb);
+            O = N;
+            K.shells++;
+            R = need_rect(C, fminf(x_upper(xb, d), tu_hi), d.fx, d.fy);
+        }
+    }
+};
+
+// Per-cell candidate cache of the coordinate-rectangle scan: the sorted positions of every site
+// in a region G around p, gathered once and grown on demand, so that a ray whose S_I square
+// fits in G is answered by one flat pass over the list instead of a walk of the tree.
+struct NoList {
+    static constexpr int K = 0;
+    __device__ __forceinline__ void put(int, int) {}
+    __device__ __forceinline__ int get(int) const { return 0; }
+};
+template <int BLOCK, int KC>
+struct LdsList {
+    static constexpr int K = KC;
+    int (*l)[BLOCK];
+    __device__ __forceinline__ void put(int i, int v) { l[i][threadIdx.x] = v; }
+    __device__ __forceinline__ int get(int i) const { return l[i][threadIdx.x]; }
+};
+
+// Adaptive buckets: regions are rectangles in coordinates; a pass over N \ O visits the leaves
+// that meet it (and the disk of the current bound) and evaluates exactly the sites inside N and
+// outside O.  With a list (LS::K > 0, one lane per cell) the sites of the growing region G are
+// kept and later rays start from them.
+template <class P, class FS, class LS = NoList>
+struct TreeScan {
+    Tree T;
+    FS fs;
+    LS ls;
+    Rect Q0;
+    bool heavy;
+    Rect G;      // region whose sites are all in the list (while cached)
+    int nl;      // sites in the list (may exceed LS::K: overflow)
+    bool cached;
+    int work;    // sub-buckets visited + evaluations for this cell (lane-per-cell scans)
+
+    // Appends the sites of N \ O to the list; false (and the list as before) on overflow.
+    __device__ __forceinline__ bool gather(const Cell &C, const float2 *__restrict__ sxy, Rect N,
+                                           Rect O) {
+        const int n0 = nl;
+        TreeWalk wk;
+        const Disk all{0.0f, 0.0f, FINF};
+        wk.start(C, T, N, O, all);
+        while (wk.next(C, T, fs)) {
+            for (int q = wk.pos; q < wk.end; ++q) {
+                const float2 a = sxy[q];
+                if (!wk.full && !(in_rect(N, a.x, a.y) && !in_rect(O, a.x, a.y))) continue;
+                if (nl >= LS::K) {
+                    nl = n0;
+                    return false;
+                }
+                ls.put(nl++, q);
+            }
+        }
+        return true;
+    }
+
+    // The list starts with p's leaf and grows by one leaf side per step while it holds fewer
+    // than TREE_LIST_FILL sites and the next ring fits.
+    __device__ __forceinline__ void load(const Cell &C, const float2 *__restrict__ sxy) {
+        Q0 = tree_block(C, T, C.ht);
+        heavy = false;
+        work = 0;
+        if (LS::K > 0) {
+            G = tree_block(C, T, 0);
+            nl = 0;
+            cached = gather(C, sxy, G, NO_RECT);
+            const int side = G.x1 - G.x0 + 1;
+            for (int ring = 0; cached && nl < TREE_LIST_FILL && ring < 4; ++ring) {
+                const Rect N{max(G.x0 - side, 0), min(G.x1 + side, C.W), max(G.y0 - side, 0),
+                             min(G.y1 + side, C.H)};
+                if (rect_inside(N, G) || !gather(C, sxy, N, G)) break;
+                G = N;
+            }
+        }
+    }
+
+    // Sites of N \ O.  CACHE: every such site is evaluated and appended to the list (no disk
+    // pruning, the list must hold the whole region) until it is full (then nl > LS::K).
+    // Otherwise sites and leaves outside the disk of the bound Tr are skipped, and the disk
+    // shrinks whenever a new winner lowers the bound (Tr = min(Tr, its upper key), capped by
+    // tcap): a site outside the disk of an evaluated site's upper bound is strictly worse.
+    template <bool CACHE>
+    __device__ __forceinline__ void visit_f32(const Cell &C, const float2 *__restrict__ sxy,
+                                              Rect N, Rect O, float &Tr, float tcap, float dx,
+                                              float dy, int ex1, int ex2, Best &b, Counters &K) {
+        TreeWalk wk;
+        const Disk all{0.0f, 0.0f, FINF};
+        wk.start(C, T, N, O, CACHE ? all : need_disk(C, Tr, dx, dy));
+        int pos = 0, end = 0, ev = 0;
+        bool full = true;
+        for (;;) {
+            if (LS::K > 0 && work + wk.steps + ev > TREE_BUDGET) {
+                heavy = true;   // the lane gives the cell to the one-wave-per-cell pass
+                break;
+            }
+            if (pos < end) {
+                const int q = pos;
+                pos += P::W;
+                ++ev;
+                const float2 a = sxy[q];
+                if (!full && !(in_rect(N, a.x, a.y) && !in_rect(O, a.x, a.y))) continue;
+                const float ex = a.x - C.pxf, ey = a.y - C.pyf;
+                if (CACHE) {
+                    if (nl < LS::K) ls.put(nl, q);
+                    ++nl;
+                } else if (!in_disk(wk.D, ex, ey)) {
+                    continue;
+                }
+                const float qq = site_q(ex, ey);
+                float key = key_lo_line(qq, ex, ey, dx, dy);
+                key = (q == ex1 || q == ex2) ? FINF : key;
+                const bool win = key < b.k1;
+                consider(key, q, b);
+                ++K.evals;
+                if (!CACHE && P::W == 1 && win) {
+                    const float t = fminf(key_hi_line(qq, ex, ey, dx, dy), tcap);
+                    if (t < Tr) {
+                        Tr = t;
+                        wk.D = need_disk(C, Tr, dx, dy);
+                    }
+                }
+                continue;
+            }
+            if (!wk.next(C, T, fs)) break;
+            pos = wk.pos + P::lane();
+            end = wk.end;
+            full = wk.full;
+        }
+        work += wk.steps + ev;
+    }
+
+    // Probes the leaves at the points p + (Tr 2^-k / 2) d_s, k = 1..TREE_PROBES, of the ray: a
+    // bound found far out along a ray that enters a denser region tightens quickly, so the
+    // region pass that follows prunes most of that region.  Any candidates are valid here.
+    __device__ __forceinline__ void probe(const Cell &C, const float2 *__restrict__ sxy,
+                                          float dx, float dy, int ex1, int ex2, float Tr,
+                                          Best &b, Counters &K) {
+        if (!(Tr < 1.0e30f)) return;
+        float t = Tr;
+        for (int k = 0; k < TREE_PROBES; ++k) {
+            t *= 0.5f;
+            const int x = C.px + (int)fminf(fmaxf(0.5f * t * dx, -(float)C.W), (float)C.W);
+            const int y = C.py + (int)fminf(fmaxf(0.5f * t * dy, -(float)C.H), (float)C.H);
+            if (x < 0 || x >= C.W || y < 0 || y >= C.H) continue;
+            int lo, hi;
+            leaf_at(C, T, x, y, lo, hi);
+            for (int q = lo + P::lane(); q < hi; q += P::W) {
+                const float2 a = sxy[q];
+                const float ex = a.x - C.pxf, ey = a.y - C.pyf;
+                float key = key_lo_line(site_q(ex, ey), ex, ey, dx, dy);
+                key = (q == ex1 || q == ex2 || (ex == 0.0f && ey == 0.0f)) ? FINF : key;
+                consider(key, q, b);
+                ++K.evals;
+            }
+            work += hi - lo + 4;
+        }
+        P::reduce(b);
+    }
+
+    // FP32 argmin starting from the cached list: its region G replaces the warm start.
+    __device__ __forceinline__ ScanOut scan_cached(const Cell &C, const float2 *__restrict__ sxy,
+                                                   float dx, float dy, int ex1, int ex2,
+                                                   float tcap, Counters &K) {
+        Best b{FINF, FINF, NO_TAG};
+        for (int i = 0; i < nl; ++i) {
+            const int q = ls.get(i);
+            const float2 a = sxy[q];
+            const float ex = a.x - C.pxf, ey = a.y - C.pyf;
+            float key = key_lo_line(site_q(ex, ey), ex, ey, dx, dy);
+            key = (q == ex1 || q == ex2) ? FINF : key;
+            consider(key, q, b);
+        }
+        K.evals += nl;
+        work += nl;
+        consider_sides(C, dx, dy, ex1, ex2, b);
+        K.shells++;
+        float U = upper_of(C, sxy, b.w, dx, dy);
+        float Uw = U;
+        float Tr = fminf(U, tcap);
+        Rect R = need_crect(C, Tr, dx, dy);
+        Rect O = G;
+        bool grow = true;   // O is still the list's region: the list may follow it
+        if (!rect_inside(R, O)) {
+            probe(C, sxy, dx, dy, ex1, ex2, Tr, b, K);
+            Uw = upper_of(C, sxy, b.w, dx, dy);
+            U = fminf(U, Uw);
+            Tr = fminf(U, tcap);
+            R = need_crect(C, Tr, dx, dy);
+        }
+        while (!heavy && !rect_inside(R, O)) {
+            const Rect N = grow_crect(O, R);
+            if (grow) {
+                const int n0 = nl;
+                float Tn = FINF;
+                visit_f32<true>(C, sxy, N, O, Tn, tcap, dx, dy, ex1, ex2, b, K);
+                if (nl <= LS::K) {
+                    G = N;
+                } else {
+                    nl = n0;   // full: the list keeps region G, this ray goes on without it
+                    grow = false;
+                }
+            } else {
+                float Tv = Tr;
+                visit_f32<false>(C, sxy, N, O, Tv, tcap, dx, dy, ex1, ex2, b, K);
+            }
+            O = N;
+            K.shells++;
+            Uw = upper_of(C, sxy, b.w, dx, dy);
+            U = fminf(U, Uw);
+            Tr = fminf(U, tcap);
+            R = need_crect(C, Tr, dx, dy);
+        }
+        ScanOut o;
+        o.b = b;
+        o.Uw = Uw;
+        o.U = U;
+        o.Tr = Tr;
+        o.A = O;
+        return o;
+    }
+
+    __device__ __forceinline__ ScanOut scan(const Cell &C, const float2 *__restrict__ sxy,
+                                            float dx, float dy, int ex1, int ex2, float tcap,
+                                            Counters &K) {
+        if (LS::K > 0 && cached) return scan_cached(C, sxy, dx, dy, ex1, ex2, tcap, K);
+        Best b{FINF, FINF, NO_TAG};
+        float T0 = FINF;
+        visit_f32<false>(C, sxy, Q0, NO_RECT, T0, tcap, dx, dy, ex1, ex2, b, K);
+        P::reduce(b);
+        consider_sides(C, dx, dy, ex1, ex2, b);
+        K.shells++;
+        float U = upper_of(C, sxy, b.w, dx, dy);
+        float Uw = U;
+        float Tr = fminf(U, tcap);
+        Rect R = need_crect(C, Tr, dx, dy);
+        Rect O = Q0;
+        if (!rect_inside(R, O)) {
+            probe(C, sxy, dx, dy, ex1, ex2, Tr, b, K);
+            Uw = upper_of(C, sxy, b.w, dx, dy);
+            U = fminf(U, Uw);
+            Tr = fminf(U, tcap);
+            R = need_crect(C, Tr, dx, dy);
+        }
+        while (!heavy && !rect_inside(R, O)) {
+            const Rect N = grow_crect(O, R);
+            float Tv = Tr;
+            visit_f32<false>(C, sxy, N, O, Tv, tcap, dx, dy, ex1, ex2, b, K);
+            P::reduce(b);
+            O = N;
+            K.shells++;
+            Uw = upper_of(C, sxy, b.w, dx, dy);
+            U = fminf(U, Uw);
+            Tr = fminf(U, tcap);
+            R = need_crect(C, Tr, dx, dy);
+        }
+        ScanOut o;
+        o.b = b;
+        o.Uw = Uw;
+        o.U = U;
+        o.Tr = Tr;
+        o.A = O;
+        return o;
+    }
+
+    template <bool FILTER>
+    __device__ __forceinline__ void visit_exact(const Cell &C, const float2 *__restrict__ sxy,
+                                                const Dir &d, Rect N, Rect O, const Disk &Dk,
+                                                float Tlim, int ex1, int ex2, XBest &xb,
+                                                Counters &K) {
+        const float lim = Tlim * CERT_UP;
+        TreeWalk wk;
+        wk.start(C, T, N, O, Dk);
+        int pos = 0, end = 0;
+        bool full = true;
+        for (;;) {
+            if (pos < end) {
+                const int q = pos;
+                pos += P::W;
+                if (q == ex1 || q == ex2) continue;
+                const float2 a = sxy[q];
+                if (!full && !(in_rect(N, a.x, a.y) && !in_rect(O, a.x, a.y))) continue;
+                if (!in_disk(Dk, a.x - C.pxf, a.y - C.pyf)) continue;
+                exact_site<FILTER, P>(C, a, q, d, lim, xb, K);
+                continue;
+            }
+            if (!wk.next(C, T, fs)) break;
+            pos = wk.pos + P::lane();
+            end = wk.end;
+            full = wk.full;
+        }
+    }
+
+    __device__ __forceinline__ void exact(const Cell &C, const float2 *__restrict__ sxy,
+                                          const Dir &d, const ScanOut &s, float Tlim, int ex1,
+                                          int ex2, XBest &xb, Counters &K) {
+        visit_exact<true>(C, sxy, d, s.A, NO_RECT, need_disk(C, s.Tr, d.fx, d.fy), Tlim, ex1,
+                          ex2, xb, K);
+        P::reduce(xb);
+        exact_sides(C, d, Tlim, true, ex1, ex2, xb);
+    }
+
+    __device__ __forceinline__ void exact_all(const Cell &C, const float2 *__restrict__ sxy,
+                                              const Dir &d, float tu_hi, int ex1, int ex2,
+                                              XBest &xb, Counters &K) {
+        const Disk all{0.0f, 0.0f, FINF};
+        visit_exact<false>(C, sxy, d, Q0, NO_RECT, all, FINF, ex1, ex2, xb, K);
+        P::reduce(xb);
+        exact_sides(C, d, FINF, false, ex1, ex2, xb);
+        Rect O = Q0;
+        K.shells++;
+        float Tr = fminf(x_upper(xb, d), tu_hi);
+        Rect R = need_crect(C, Tr, d.fx, d.fy);
+        while (!rect_inside(R, O)) {
+            const Rect N = grow_crect(O, R);
+            visit_exact<false>(C, sxy, d, N, O, need_disk(C, Tr, d.fx, d.fy), FINF, ex1, ex2, xb,
+                               K);
+            P::reduce(xb);
+            O = N;
+            K.shells++;
+            Tr = fminf(x_upper(xb, d), tu_hi);
+            R = need_crect(C, Tr, d.fx, d.fy);
+        }
+    }
+};
 
 // ------------------------------------------------------------------------------ stacks / outputs
 template <int BLOCK>
@@ -372,11 +756,11 @@ struct Sink {
 // Plain ray (Den == 0): out = the line the endpoint lies on; returns 0.
 // Vertex ray (Den > 0, d = Z, u = Z / Den; lines ex1, ex2 through u skipped): returns 1 when u
 // is in the cell (a vertex), 0 when a line crosses [p, u) first (that line in out).
-// Returns -1 when undecided (MODE 0).
-template <int MODE, class P, class Rows>
-__device__ __forceinline__ int ray(const Cell &C, const Rows &BR, const float2 *__restrict__ sxy,
-                                   const int *__restrict__ bstart, const Dir &d, int64_t Den,
-                                   int ex1, int ex2, Line &out, Counters &K) {
+// Returns -1 when undecided (MODE 0), -4 when the scanner met a heavy bucket.
+template <int MODE, class P, class Sc>
+__device__ __forceinline__ int ray(const Cell &C, Sc &sc, const float2 *__restrict__ sxy,
+                                   const Dir &d, int64_t Den, int ex1, int ex2, Line &out,
+                                   Counters &K) {
     const bool vmode = Den > 0;
     float tu_hi = FINF, tu_lo = FINF;
     if (vmode) {
@@ -389,26 +773,11 @@ __device__ __forceinline__ int ray(const Cell &C, const Rows &BR, const float2 *
     XBest xb;
     xb.have = false;
     if (MODE == 2) {
-        // every decision exact: the block, then the rectangle the exact winner needs
-        const Rect A = block_rect(C);
-        exact_rect<false, P>(C, sxy, bstart, d, A, Rect{1, 0, 1, 0}, FINF, ex1, ex2, xb, K);
-        P::reduce(xb);
-        exact_sides(C, d, FINF, false, ex1, ex2, xb);
-        Rect O = A;
-        K.shells++;
-        Rect R = need_rect(C, fminf(x_upper(xb, d), tu_hi), d.fx, d.fy);
-        while (!rect_inside(R, O)) {
-            const Rect N = grow_rect(O, R);
-            exact_rect<false, P>(C, sxy, bstart, d, N, O, FINF, ex1, ex2, xb, K);
-            P::reduce(xb);
-            O = N;
-            K.shells++;
-            R = need_rect(C, fminf(x_upper(xb, d), tu_hi), d.fx, d.fy);
-        }
+        sc.exact_all(C, sxy, d, tu_hi, ex1, ex2, xb, K);
     } else {
         // one scan variant for both kinds of rays (lanes of a wave may differ in kind)
-        const ScanOut s = scan_f32<P, Rows>(C, BR, sxy, bstart, d.fx, d.fy, ex1, ex2,
-                                            vmode ? tu_hi : FINF, K);
+        const ScanOut s = sc.scan(C, sxy, d.fx, d.fy, ex1, ex2, vmode ? tu_hi : FINF, K);
+        if (sc.heavy) return -4;
         if (vmode && s.b.k1 * CERT_DN > tu_hi) return 1;
         const float uw = s.Uw * CERT_UP;
         if (uw < s.b.k2 * CERT_DN && (!vmode || uw < tu_lo)) {
@@ -417,11 +786,8 @@ __device__ __forceinline__ int ray(const Cell &C, const Rows &BR, const float2 *
         }
         if (MODE == 0) return -1;
         K.exact++;
-        // exact decision over the certified rectangle, FP32-plausible candidates only
-        const float Tlim = vmode ? tu_hi : s.U;
-        exact_rect<true, P>(C, sxy, bstart, d, s.A, Rect{1, 0, 1, 0}, Tlim, ex1, ex2, xb, K);
-        P::reduce(xb);
-        exact_sides(C, d, Tlim, true, ex1, ex2, xb);
+        // exact decision over the certified region, FP32-plausible candidates only
+        sc.exact(C, sxy, d, s, vmode ? tu_hi : s.U, ex1, ex2, xb, K);
     }
     // no line other than the two through u is crossed: u is the endpoint (a vertex)
     if (!xb.have) return vmode ? 1 : -1;
@@ -438,17 +804,18 @@ __device__ __forceinline__ int ray(const Cell &C, const Rows &BR, const float2 *
 
 // ------------------------------------------------------------------------------ one cell
 // Returns the number of lines written to the sink (>= 3), or
-//   -1 undecided in MODE 0, -2 stack / output capacity, -3 node limit (never expected).
-template <int MODE, class P, class Stack, class Rows>
-__device__ __forceinline__ int run_cell(const Cell &C, const float2 *__restrict__ sxy,
-                                        const int *__restrict__ bstart, Stack &st, int scap,
-                                        Rows &BR, Sink &sink, int ocap, Counters &K) {
+//   -1 undecided in MODE 0, -2 stack / output capacity, -3 node limit (never expected),
+//   -4 the scanner met a heavy bucket (the cell belongs to the adaptive pass).
+template <int MODE, class P, class Stack, class Sc>
+__device__ __forceinline__ int run_cell(const Cell &C, const float2 *__restrict__ sxy, Sc &sc,
+                                        Stack &st, int scap, Sink &sink, int ocap, Counters &K) {
     Line cur{}, B{}, L3{};
     int m = 0, first = 0, last = 0;
     const int node_limit = NODE_LIMIT_FACTOR * (scap + ocap) + 64;
     int nodes = 0;
     st.depth = 0;
-    BR.load(C, bstart);
+    sc.load(C, sxy);
+    if (sc.heavy) return -4;
     // phases 0..2: the projector's corner rays (7,-4), (0,1), (-7,-4): counter-clockwise,
     // consecutive gaps < pi.  Then the subedge loop.
     for (int phase = 0;; ++phase) {
@@ -480,8 +847,8 @@ __device__ __forceinline__ int run_cell(const Cell &C, const float2 *__restrict_
             }
         }
         if (!leaf) {
-            const int r = ray<MODE, P, Rows>(C, BR, sxy, bstart, d, Den, ex1, ex2, L3, K);
-            if (r < 0) return -1;
+            const int r = ray<MODE, P, Sc>(C, sc, sxy, d, Den, ex1, ex2, L3, K);
+            if (r < 0) return r == -4 ? -4 : -1;
             leaf = (r == 1);
             // a shot ray (Lemma on shot rays) yields a corner; a ray that confirms a vertex
             // is the in-cell test of the vertex

@@ -39,7 +39,7 @@ enum : int { ST_DOMAIN = 1, ST_DUP = 2, ST_CAPACITY = 4, ST_INTERNAL = 8 };
 // stats slots
 enum : int {
     SL_RAYS = 0, SL_NODES, SL_EVALS, SL_EXACT, SL_DEFERRED, SL_ASYM, SL_SHELLS, SL_EDGES,
-    SL_VTESTS, SL_COUNT
+    SL_VTESTS, SL_TREE, SL_TEVALS, SL_COUNT
 };
 
 struct SetDesc {
@@ -51,6 +51,7 @@ struct SetDesc {
     int32_t s;           // bucket side
     int32_t bucket_off;  // first global bucket of the set
     int32_t h;           // block half-width in buckets (shells 0..h scanned first)
+    int32_t ht;          // leaf sides around p's leaf scanned first (coordinate scans)
 };
 
 // ------------------------------------------------------------------------------ FP32 filter
@@ -68,10 +69,14 @@ constexpr float FINF = __builtin_huge_valf();
 
 struct Best {
     float k1, k2;   // smallest and second smallest lower bound
-    int w;          // sorted position (>= 0) or side code (-1..-4) of the smallest
+    int w;          // sorted position (>= 0) or side code (-1..-4) of the smallest, or NO_TAG
 };
+constexpr int NO_TAG = INT32_MIN;   // no candidate yet
 
+// A second evaluation of the current winner is ignored (it would pose as its own runner-up);
+// a second evaluation of any other candidate leaves the summary unchanged anyway.
 __device__ __forceinline__ void consider(float key, int tag, Best &b) {
+    if (tag == b.w) return;
     const bool better = key < b.k1;
     b.k2 = fminf(b.k2, fmaxf(b.k1, key));
     b.w = better ? tag : b.w;
@@ -145,6 +150,7 @@ struct Line {
 struct Cell {       // per-cell constants
     int gx, gy, s, boff;  // the set's bucket grid
     int h;                // half-width (in buckets) of the block scanned first
+    int ht;               // leaf sides around p's leaf scanned first (coordinate scans)
     float pxf, pyf; // p, relative to the box origin (exact floats)
     int px, py;
     int bx, by;     // p's bucket
@@ -272,25 +278,39 @@ __device__ __forceinline__ bool rect_inside(const Rect &a, const Rect &b) {
     return a.x0 >= b.x0 && a.x1 <= b.x1 && a.y0 >= b.y0 && a.y1 <= b.y1;
 }
 
+// The point y = p + (T/2) d_s and its distance r from p, in p's frame (so that rounding errors
+// scale with r, not with the coordinates), and the margin M that covers them: the products
+// and the square root round with relative error below 4e-7 and d_s is within 1.01 u of the
+// scaled direction, so M = 1e-5 r + 2 (>= 2 coordinate units) keeps every test conservative.
+// Returns false for an infinite or undefined T.
+__device__ __forceinline__ bool bound_point(float T, float dx, float dy, float &hx, float &hy,
+                                            float &r, float &M) {
+    const float Tu = T * CERT_UP;
+    hx = 0.5f * Tu * dx;
+    hy = 0.5f * Tu * dy;
+    r = sqrtf(hx * hx + hy * hy);
+    M = r * 1.0e-5f + 2.0f;
+    return r < 1.0e30f;
+}
+
 // The integer rectangle S_I[y, |y - p|] of eq. (S_I), in buckets and clipped to the grid, for
 // y = p + (T/2) d_s with T an upper bound of the endpoint parameter: by the lemma on sites in
 // the large square every site that is not farther from y than p lies in it, and the rectangles
-// of the points of [p, y] nest inside it.  A small margin (>= 2 coordinate units) keeps the
-// FP32 evaluation conservative; an infinite or undefined T gives the whole grid.
+// of the points of [p, y] nest inside it.  The square is widened by the margin M of
+// bound_point; an infinite or undefined T gives the whole grid.
 __device__ __forceinline__ Rect need_rect(const Cell &C, float T, float dx, float dy) {
-    const float Tu = T * CERT_UP;
-    const float hx = 0.5f * Tu * dx, hy = 0.5f * Tu * dy;
-    const float yx = C.pxf + hx, yy = C.pyf + hy;
-    const float r = sqrtf(hx * hx + hy * hy);
+    float hx, hy, r, M;
     Rect R{0, C.gx - 1, 0, C.gy - 1};
-    if (!(r < 1.0e30f) || !(fabsf(yx) < 1.0e30f) || !(fabsf(yy) < 1.0e30f)) return R;
-    const float M = (r + fabsf(yx) + fabsf(yy)) * 1.0e-5f + 2.0f;
-    const float inv = 1.0f / (float)C.s;
-    const float mx = (float)(C.gx - 1), my = (float)(C.gy - 1);
-    R.x0 = (int)fminf(fmaxf(floorf((yx - r - M) * inv), 0.0f), mx);
-    R.x1 = (int)fminf(fmaxf(floorf((yx + r + M) * inv), 0.0f), mx);
-    R.y0 = (int)fminf(fmaxf(floorf((yy - r - M) * inv), 0.0f), my);
-    R.y1 = (int)fminf(fmaxf(floorf((yy + r + M) * inv), 0.0f), my);
+    if (!bound_point(T, dx, dy, hx, hy, r, M)) return R;
+    const float ext = (float)C.W + (float)C.H + 2.0f;   // clamp before converting
+    const int lx = C.px + (int)fminf(fmaxf(floorf(hx - r - M), -ext), ext);
+    const int ux = C.px + (int)fminf(fmaxf(ceilf(hx + r + M), -ext), ext);
+    const int ly = C.py + (int)fminf(fmaxf(floorf(hy - r - M), -ext), ext);
+    const int uy = C.py + (int)fminf(fmaxf(ceilf(hy + r + M), -ext), ext);
+    R.x0 = min(max(lx, 0) / C.s, C.gx - 1);
+    R.x1 = min(max(ux, 0) / C.s, C.gx - 1);
+    R.y0 = min(max(ly, 0) / C.s, C.gy - 1);
+    R.y1 = min(max(uy, 0) / C.s, C.gy - 1);
     return R;
 }
 

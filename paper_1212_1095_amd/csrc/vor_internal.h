@@ -6,7 +6,8 @@
 namespace vor {
 
 struct SetDesc;
-constexpr int SMALL_INTS = 16;   // status, qcount, qcount2, poolcnt, spare
+struct TNode;
+constexpr int SMALL_INTS = 16;   // status, queue counters, pool / tree counters, spare
 constexpr int DEEP_BLOCKS = 8;   // one-wave workers of the deep-cell pass
 
 // Device pointers and sizes of one pipeline launch.
@@ -20,7 +21,16 @@ struct PipeArgs {
     int2 *xyid;             // relative coordinates by site [total]
     int *key;               // bucket of each site [total]
     int *bcnt;              // [gtot]
-    int *bstart;            // [gtot + 1]
+    int *bstart;            // [gtot + 1 + tabcap]: bucket starts, then sub-bucket starts
+    int *tchild;            // [gtot + 1 + tabcap]: refining node of each slot, or -1
+    TNode *nodes;           // [ncap] refinement nodes
+    int ncap;
+    long long tabcap;       // sub-bucket table entries after the grid's
+    float2 *txy;            // [total] refinement scratch
+    int *tid;               // [total]
+    int *queue3;            // cells handed to the adaptive pass [total]
+    int *tref;              // [gtot + 1] refined grid buckets before each bucket
+    int *set_tree;          // [nsets] 1 when the set has refined buckets
     float2 *sxy;            // sorted coordinates [total]
     int *sid;               // local id of each sorted site [total]
     int *ocnt, *olines, *ovf;
@@ -43,6 +53,7 @@ struct PipeArgs {
     int block;
     bool exact_only, with_vertices, check_symmetry;
     bool coop_all;              // every cell through the one-wave-per-cell pass (small sets)
+    bool tree_all;              // every cell through the coordinate-rectangle pass
     bool time_stages;           // HIP events between the stages (one graph per stage)
 
     int *status() const { return small; }
@@ -50,10 +61,15 @@ struct PipeArgs {
     int *qcount() const { return small + 1; }
     int *qcount2() const { return small + 2; }
     int *poolcnt() const { return small + 3; }
+    int *nodecnt() const { return small + 4; }
+    int *tabcnt() const { return small + 5; }
+    int *level() const { return small + 6; }     // [lo, hi) of the nodes to refine next
+    int *qcount3() const { return small + 8; }
 };
 
-// stages: 0 grid build, 1 filtered cell pass, 2 exact / deep passes, 3 CSR and Delaunay
-constexpr int NSTAGES = 4;
+// stages: 0 grid build and refinement, 1 filtered cell pass, 2 adaptive pass, 3 exact / deep
+// passes, 4 CSR, vertices and Delaunay edges
+constexpr int NSTAGES = 5;
 void launch_stage(const PipeArgs &a, hipStream_t st, int stage);
 void launch_pipeline(const PipeArgs &a, hipStream_t st);
 long long scan_tmp_ints(long long n);

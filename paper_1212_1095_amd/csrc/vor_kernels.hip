@@ -3,9 +3,13 @@
 //   prep      validate, relative coordinates, bucket of every site (Method 11.5)
 //   scan      bucket counts -> bucket starts (counting sort)
 //   scatter   sites into bucket order (structure of arrays, FP32 coordinates)
-//   dups      equal sites share a bucket: compare inside buckets (lexicographic check of the
-//             distinctness remark in Appendix 2, done per bucket)
-//   cells     the projector algorithm per cell, FP32 filtered; undecided cells are queued
+//   refine    buckets with many sites become grids of sub-buckets, recursively (adaptive
+//             bucketing for clustered sets; the sites of every sub-bucket stay contiguous)
+//   dups      equal sites share a leaf bucket: compare inside leaves (lexicographic check of
+//             the distinctness remark in Appendix 2, done per leaf)
+//   cells     the projector algorithm per cell, FP32 filtered; undecided cells are queued,
+//             cells whose scans meet a crowded bucket are handed to the adaptive pass
+//   adaptive  those cells again, scanning the refined buckets by coordinate rectangles
 //   exact     queued cells again with exact fallback (or every cell, exact-only precision)
 //   deep      cells deeper than the exact pass's per-worker capacity
 //   scan      line counts -> CSR offsets
@@ -18,6 +22,7 @@
 
 #include "vor_cell.hpp"
 #include "vor_internal.h"
+#include "vor_tree.hpp"
 
 namespace vor {
 
@@ -38,9 +43,10 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
 }
 
 __global__ void k_clear(int *__restrict__ p, long long n, int *__restrict__ small, int nsmall,
-                        unsigned long long *__restrict__ stats) {
+                        unsigned long long *__restrict__ stats, int *__restrict__ q, int nq) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0;
+    if (i < nq) q[i] = 0;
     if (i < nsmall) small[i] = 0;
     if (i < SL_COUNT) stats[i] = 0;
 }
@@ -79,21 +85,233 @@ __global__ void k_scatter(const SetDesc *__restrict__ sets, int nsets, const int
     sid[pos] = i - set_off[find_set(set_off, nsets, i)];
 }
 
+// Leaf bucket of the site at sorted position pos: its first sorted position.
+__device__ __forceinline__ int leaf_start(const SetDesc &S, float2 a, const int *__restrict__ tstart,
+                                          const int *__restrict__ tchild,
+                                          const TNode *__restrict__ nodes) {
+    const int x = (int)a.x, y = (int)a.y;
+    int k = S.bucket_off + min(y / S.s, S.gy - 1) * S.gx + min(x / S.s, S.gx - 1);
+    int c = tchild[k];
+    for (int lv = 0; c >= 0 && lv < TREE_LEVELS; ++lv) {
+        const TNode nd = nodes[c];
+        const int i = min((x - nd.ox) / nd.ss, nd.m - 1), j = min((y - nd.oy) / nd.ss, nd.m - 1);
+        k = nd.tab + j * nd.m + i;
+        c = tchild[k];
+    }
+    return tstart[k];
+}
+
 __global__ void k_dups(const SetDesc *__restrict__ sets, int nsets, const int *__restrict__ set_off,
-                       int total, const float2 *__restrict__ sxy, const int *__restrict__ bstart,
+                       int total, const float2 *__restrict__ sxy, const int *__restrict__ tstart,
+                       const int *__restrict__ tchild, const TNode *__restrict__ nodes,
                        int *__restrict__ status) {
     const int pos = blockIdx.x * blockDim.x + threadIdx.x;
     if (pos >= total) return;
     const SetDesc S = sets[find_set(set_off, nsets, pos)];
     const float2 a = sxy[pos];
-    const int bx = min((int)a.x / S.s, S.gx - 1), by = min((int)a.y / S.s, S.gy - 1);
-    const int lo = bstart[S.bucket_off + by * S.gx + bx];
+    const int lo = leaf_start(S, a, tstart, tchild, nodes);
     for (int j = lo; j < pos; ++j) {
         const float2 b = sxy[j];
         if (b.x == a.x && b.y == a.y) {
             atomicOr(status, ST_DUP);
             break;
         }
+    }
+}
+
+// ------------------------------------------------------------------------------ refinement
+// Set of global bucket b (sets are stored in bucket order too).
+__device__ __forceinline__ int find_set_bucket(const SetDesc *__restrict__ sets, int nsets, long long b) {
+    int lo = 0, hi = nsets - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (sets[mid].bucket_off <= b) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Every grid bucket with more than TREE_C0 sites gets a refinement node.
+__global__ void k_tree_mark0(const SetDesc *__restrict__ sets, int nsets, long long gtot,
+                             const int *__restrict__ bstart, int *__restrict__ tchild,
+                             int *__restrict__ refined, TNode *__restrict__ nodes, int ncap,
+                             int *__restrict__ nodecnt, int *__restrict__ set_tree,
+                             const int *__restrict__ status) {
+    if (*status) return;
+    const long long b = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b > gtot) return;
+    if (b == gtot) {
+        tchild[b] = -1;
+        return;
+    }
+    const int cnt = bstart[b + 1] - bstart[b];
+    int id = -1;
+    if (cnt > TREE_C0) {
+        const int si = find_set_bucket(sets, nsets, b);
+        const SetDesc S = sets[si];
+        const int local = (int)(b - S.bucket_off);
+        id = atomicAdd(nodecnt, 1);
+        if (id < ncap) {
+            TNode t;
+            t.ox = (local % S.gx) * S.s;
+            t.oy = (local / S.gx) * S.s;
+            t.size = S.s;
+            t.a = bstart[b];
+            t.cnt = cnt;
+            t.pk = (int)b;
+            t.ss = t.m = t.tab = 0;
+            nodes[id] = t;
+            set_tree[si] = 1;
+        } else {
+            id = -1;
+        }
+    }
+    tchild[b] = id;
+    refined[b] = id >= 0 ? 1 : 0;
+}
+
+// [lo, hi) of the nodes the next refinement level processes.
+__global__ void k_tree_level(int *__restrict__ lvl, const int *__restrict__ nodecnt, int ncap) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        lvl[0] = lvl[1];
+        lvl[1] = min(*nodecnt, ncap);
+    }
+}
+
+// One block per node: counting sort of the node's sites into an m x m grid of sub-buckets
+// (through the scratch arrays), the node's sub-bucket starts, and nodes for crowded
+// sub-buckets (refined by the next level).
+constexpr int REFINE_BLOCK = 256;
+constexpr int REFINE_MAXSUB = TREE_MMAX * TREE_MMAX;
+
+__global__ __launch_bounds__(REFINE_BLOCK) void k_tree_refine(
+    TNode *__restrict__ nodes, const int *__restrict__ lvl, int *__restrict__ nodecnt, int ncap,
+    int *__restrict__ tstart, int *__restrict__ tchild, int *__restrict__ tabcnt, long long tab0,
+    long long tabcap, float2 *__restrict__ sxy, int *__restrict__ sid, float2 *__restrict__ txy,
+    int *__restrict__ tid, int last_level, int *__restrict__ status) {
+    __shared__ int cnt[REFINE_MAXSUB];
+    __shared__ int pre[REFINE_MAXSUB + 1];
+    __shared__ int sh_tab, sh_part[REFINE_BLOCK];
+    __shared__ int sh_box[4];
+    if (*status) return;
+    const int lo = lvl[0], hi = lvl[1];
+    for (int id = lo + blockIdx.x; id < hi; id += gridDim.x) {
+        TNode t = nodes[id];
+        // bounding square of the node's sites
+        if (threadIdx.x == 0) {
+            sh_box[0] = INT32_MAX; sh_box[1] = INT32_MIN; sh_box[2] = INT32_MAX;
+            sh_box[3] = INT32_MIN;
+        }
+        __syncthreads();
+        {
+            int x0 = INT32_MAX, x1 = INT32_MIN, y0 = INT32_MAX, y1 = INT32_MIN;
+            for (int p = t.a + threadIdx.x; p < t.a + t.cnt; p += REFINE_BLOCK) {
+                const float2 q = sxy[p];
+                x0 = min(x0, (int)q.x); x1 = max(x1, (int)q.x);
+                y0 = min(y0, (int)q.y); y1 = max(y1, (int)q.y);
+            }
+            atomicMin(&sh_box[0], x0); atomicMax(&sh_box[1], x1);
+            atomicMin(&sh_box[2], y0); atomicMax(&sh_box[3], y1);
+        }
+        __syncthreads();
+        t.ox = sh_box[0];
+        t.oy = sh_box[2];
+        t.size = max(sh_box[1] - sh_box[0], sh_box[3] - sh_box[2]) + 1;
+        // sub-buckets per axis: a power of two near sqrt(cnt), at most TREE_MMAX and the side
+        int m = 2;
+        while (m < TREE_MMAX && 2 * m * m <= t.cnt) m *= 2;
+        m = min(m, t.size);
+        const int ss = (t.size + m - 1) / m;
+        const int mm = m * m;
+        if (threadIdx.x == 0) {
+            const int tb = atomicAdd(tabcnt, mm + 1);
+            sh_tab = ((long long)tb + mm + 1 > tabcap || t.size < 2) ? -1 : tb;
+            if (t.size < 2) atomicOr(status, ST_DUP);   // > TREE_C0 sites on one lattice point
+        }
+        for (int k = threadIdx.x; k < mm; k += REFINE_BLOCK) cnt[k] = 0;
+        __syncthreads();
+        const int tb = sh_tab;
+        if (tb < 0) {
+            if (threadIdx.x == 0) tchild[t.pk] = -1;   // stays a leaf
+            __syncthreads();
+            continue;
+        }
+        for (int p = t.a + threadIdx.x; p < t.a + t.cnt; p += REFINE_BLOCK) {
+            const float2 q = sxy[p];
+            const int i = min(((int)q.x - t.ox) / ss, m - 1), j = min(((int)q.y - t.oy) / ss, m - 1);
+            atomicAdd(&cnt[j * m + i], 1);
+        }
+        __syncthreads();
+        // exclusive scan of cnt[0..mm) into pre: a chunk per thread, then the chunk sums
+        const int per = (mm + REFINE_BLOCK - 1) / REFINE_BLOCK;
+        const int c0 = threadIdx.x * per, c1 = min(c0 + per, mm);
+        int sum = 0;
+        for (int k = c0; k < c1; ++k) sum += cnt[k];
+        sh_part[threadIdx.x] = sum;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int acc = 0;
+            for (int u = 0; u < REFINE_BLOCK; ++u) {
+                const int v = sh_part[u];
+                sh_part[u] = acc;
+                acc += v;
+            }
+        }
+        __syncthreads();
+        int acc = sh_part[threadIdx.x];
+        for (int k = c0; k < c1; ++k) {
+            pre[k] = acc;
+            acc += cnt[k];
+        }
+        if (threadIdx.x == 0) pre[mm] = t.cnt;
+        __syncthreads();
+        const long long base = tab0 + tb;
+        for (int k = threadIdx.x; k <= mm; k += REFINE_BLOCK) tstart[base + k] = t.a + pre[k];
+        // scatter into the scratch arrays, then back (the range is the node's own)
+        for (int k = threadIdx.x; k < mm; k += REFINE_BLOCK) cnt[k] = pre[k];
+        __syncthreads();
+        for (int p = t.a + threadIdx.x; p < t.a + t.cnt; p += REFINE_BLOCK) {
+            const float2 q = sxy[p];
+            const int i = min(((int)q.x - t.ox) / ss, m - 1), j = min(((int)q.y - t.oy) / ss, m - 1);
+            const int dst = t.a + atomicAdd(&cnt[j * m + i], 1);
+            txy[dst] = q;
+            tid[dst] = sid[p];
+        }
+        __syncthreads();
+        for (int p = t.a + threadIdx.x; p < t.a + t.cnt; p += REFINE_BLOCK) {
+            sxy[p] = txy[p];
+            sid[p] = tid[p];
+        }
+        // children
+        for (int k = threadIdx.x; k < mm; k += REFINE_BLOCK) {
+            const int c = pre[k + 1] - pre[k];
+            int cid = -1;
+            if (c > TREE_C1 && !last_level) {
+                cid = atomicAdd(nodecnt, 1);
+                if (cid < ncap) {
+                    TNode u;
+                    u.ox = t.ox + (k % m) * ss;
+                    u.oy = t.oy + (k / m) * ss;
+                    u.size = ss;
+                    u.a = t.a + pre[k];
+                    u.cnt = c;
+                    u.pk = (int)(base + k);
+                    u.ss = u.m = u.tab = 0;
+                    nodes[cid] = u;
+                } else {
+                    cid = -1;
+                }
+            }
+            tchild[base + k] = cid;
+        }
+        if (threadIdx.x == 0) {
+            nodes[id].ox = t.ox;
+            nodes[id].oy = t.oy;
+            nodes[id].size = t.size;
+            nodes[id].ss = ss;
+            nodes[id].m = m;
+            nodes[id].tab = (int)base;
+        }
+        __syncthreads();
     }
 }
 
@@ -104,6 +322,7 @@ __device__ __forceinline__ Cell make_cell(const SetDesc &S, float2 p) {
     C.s = S.s;
     C.boff = S.bucket_off;
     C.h = S.h;
+    C.ht = S.ht;
     C.pxf = p.x;
     C.pyf = p.y;
     C.px = (int)p.x;
@@ -116,7 +335,8 @@ __device__ __forceinline__ Cell make_cell(const SetDesc &S, float2 p) {
 }
 
 __device__ __forceinline__ void reduce_stats(const Counters &K, uint32_t edges, uint32_t deferred,
-                                             unsigned long long *sh, unsigned long long *stats) {
+                                             uint32_t tree, unsigned long long *sh,
+                                             unsigned long long *stats) {
     atomicAdd(&sh[SL_RAYS], (unsigned long long)K.rays);
     atomicAdd(&sh[SL_NODES], (unsigned long long)K.nodes);
     atomicAdd(&sh[SL_EVALS], (unsigned long long)K.evals);
@@ -125,17 +345,23 @@ __device__ __forceinline__ void reduce_stats(const Counters &K, uint32_t edges, 
     atomicAdd(&sh[SL_EDGES], (unsigned long long)edges);
     atomicAdd(&sh[SL_DEFERRED], (unsigned long long)deferred);
     atomicAdd(&sh[SL_VTESTS], (unsigned long long)K.vtests);
+    if (tree) {
+        atomicAdd(&sh[SL_TREE], (unsigned long long)tree);
+        atomicAdd(&sh[SL_TEVALS], (unsigned long long)K.evals);
+    }
     __syncthreads();
     if (threadIdx.x < SL_COUNT && sh[threadIdx.x]) atomicAdd(&stats[threadIdx.x], sh[threadIdx.x]);
 }
 
-// Filtered pass: one thread per cell, cells in bucket order, stack in LDS.
+// Filtered pass: one thread per cell, cells in bucket order, stack in LDS.  Cells whose scans
+// meet a crowded bucket go to the adaptive pass (queue3), undecided cells to the exact pass.
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_cells_fast(
     const SetDesc *__restrict__ sets, int nsets, const int *__restrict__ set_off,
     const float2 *__restrict__ sxy, const int *__restrict__ sid, const int *__restrict__ bstart,
     int total, int *__restrict__ ocnt, int *__restrict__ olines, int *__restrict__ ovf,
-    int *__restrict__ queue, int *__restrict__ qcount, unsigned long long *__restrict__ stats,
+    int *__restrict__ queue, int *__restrict__ qcount, int *__restrict__ queue3,
+    int *__restrict__ qcount3, unsigned long long *__restrict__ stats,
     const int *__restrict__ status) {
     __shared__ int stk[SCAP][BLOCK];
     __shared__ int rlo[MAXROWS][BLOCK], rhi[MAXROWS][BLOCK];
@@ -151,22 +377,76 @@ __global__ __launch_bounds__(BLOCK) void k_cells_fast(
         const Cell C = make_cell(S, sxy[pos]);
         const int g = S.site_off + sid[pos];
         LdsStack<BLOCK> st{stk, 0};
-        LdsRows<BLOCK> rows{rlo, rhi, 0};
+        GridScan<Solo, LdsRows<BLOCK>, true> sc{LdsRows<BLOCK>{rlo, rhi, 0}, bstart, false};
         Sink sink{olines + (size_t)g * KOUT, sid};
-        const int r = run_cell<0, Solo>(C, sxy, bstart, st, SCAP, rows, sink, KOUT, K);
+        const int r = run_cell<0, Solo>(C, sxy, sc, st, SCAP, sink, KOUT, K);
         ovf[g] = -1;
         if (r >= 0) {
             ocnt[g] = r;
             edges = (uint32_t)r;
         } else {
             ocnt[g] = -1;
-            queue[atomicAdd(qcount, 1)] = pos;
-            deferred = 1;
+            if (r == -4) {
+                queue3[atomicAdd(qcount3, 1)] = pos;
+            } else {
+                queue[atomicAdd(qcount, 1)] = pos;
+                deferred = 1;
+            }
         }
     }
-    reduce_stats(K, edges, deferred, sh, stats);
+    reduce_stats(K, edges, deferred, 0, sh, stats);
 }
 
+// Adaptive pass: the cells handed on by the filtered pass, one thread per cell over a
+// persistent grid, scanning the refined buckets (TreeScan).  Undecided cells go to the exact
+// pass.
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_cells_tree(
+    const SetDesc *__restrict__ sets, int nsets, const int *__restrict__ set_off,
+    const float2 *__restrict__ sxy, const int *__restrict__ sid, const int *__restrict__ tstart,
+    const int *__restrict__ tchild, const TNode *__restrict__ nodes, const int *__restrict__ tref,
+    int *__restrict__ ocnt,
+    int *__restrict__ olines, int *__restrict__ ovf, const int *__restrict__ queue3,
+    const int *__restrict__ qcount3,
+    int *__restrict__ queue, int *__restrict__ qcount, unsigned long long *__restrict__ stats,
+    const int *__restrict__ status) {
+    __shared__ int stk[SCAP][BLOCK];
+    __shared__ int fr[TFRAMES][3][BLOCK];
+    __shared__ int lst[TREE_LIST][BLOCK];
+    __shared__ unsigned long long sh[SL_COUNT];
+    if (*status) return;
+    const int nq = *qcount3;
+    if ((int)(blockIdx.x * BLOCK) >= nq) return;
+    if (threadIdx.x < SL_COUNT) sh[threadIdx.x] = 0;
+    __syncthreads();
+    Counters K{0, 0, 0, 0, 0, 0};
+    uint32_t edges = 0, deferred = 0, handled = 0;
+    for (int qi = blockIdx.x * BLOCK + threadIdx.x; qi < nq; qi += gridDim.x * BLOCK) {
+        const int pos = queue3[qi];
+        const SetDesc S = sets[find_set(set_off, nsets, pos)];
+        const Cell C = make_cell(S, sxy[pos]);
+        const int g = S.site_off + sid[pos];
+        LdsStack<BLOCK> st{stk, 0};
+        TreeScan<Solo, LdsFrames<BLOCK>, LdsList<BLOCK, TREE_LIST>> sc{
+            Tree{tstart, tchild, nodes, tref}, LdsFrames<BLOCK>{fr},
+            LdsList<BLOCK, TREE_LIST>{lst},
+            Rect{}, false, Rect{}, 0, false};
+        Sink sink{olines + (size_t)g * KOUT, sid};
+        const int r = run_cell<0, Solo>(C, sxy, sc, st, SCAP, sink, KOUT, K);
+        ++handled;
+        if (r >= 0) {
+            ovf[g] = -1;
+            ocnt[g] = r;
+            edges += (uint32_t)r;
+        } else {
+            queue[atomicAdd(qcount, 1)] = pos;
+            ++deferred;
+        }
+    }
+    reduce_stats(K, edges, deferred, handled, sh, stats);
+}
+
+// Every cell into a queue, in bucket order.
 __global__ void k_queue_all(int total, int *__restrict__ queue, int *__restrict__ qcount,
                             const int *__restrict__ status) {
     if (*status) return;
@@ -175,18 +455,31 @@ __global__ void k_queue_all(int total, int *__restrict__ queue, int *__restrict_
     if (i == 0) *qcount = total;
 }
 
+// One cell by one wave (the Coop policy) with scanner Sc; the cell's stack and output live in
+// the worker's area of dcap entries each.
+template <int MODE, class Sc>
+__device__ __forceinline__ int coop_cell(const Cell &C, const float2 *__restrict__ sxy,
+                                         const int *__restrict__ sid, Sc &sc, int *area, int dcap,
+                                         Counters &K) {
+    GStack st{area, 0};
+    Sink sink{area + dcap, sid};
+    return run_cell<MODE, Coop>(C, sxy, sc, st, dcap, sink, dcap, K);
+}
+
 // Exact pass over a queue of cells: one wave per cell (the Coop policy), a persistent grid of
-// one-wave blocks; the cell's stack and output live in the block's area of dcap entries each.
+// one-wave blocks.  Sets with refined buckets are scanned through the tree.
 template <int MODE>
 __global__ __launch_bounds__(64) void k_cells_exact(
     const SetDesc *__restrict__ sets, int nsets, const int *__restrict__ set_off,
     const float2 *__restrict__ sxy, const int *__restrict__ sid, const int *__restrict__ bstart,
-    int *__restrict__ ocnt, int *__restrict__ olines, int *__restrict__ ovf,
-    int *__restrict__ pool, int *__restrict__ poolcnt, long long poolcap,
+    const int *__restrict__ tchild, const TNode *__restrict__ nodes, const int *__restrict__ tref,
+    const int *__restrict__ set_tree, int *__restrict__ ocnt, int *__restrict__ olines,
+    int *__restrict__ ovf, int *__restrict__ pool, int *__restrict__ poolcnt, long long poolcap,
     const int *__restrict__ queue, const int *__restrict__ qcount, int *__restrict__ queue2,
     int *__restrict__ qcount2, int *__restrict__ wbuf, int dcap,
     unsigned long long *__restrict__ stats, int *__restrict__ status) {
     __shared__ unsigned long long sh[SL_COUNT];
+    __shared__ int fr[TFRAMES][3];
     if (*status & (ST_DOMAIN | ST_DUP)) return;
     if (threadIdx.x < SL_COUNT) sh[threadIdx.x] = 0;
     __syncthreads();
@@ -197,13 +490,20 @@ __global__ __launch_bounds__(64) void k_cells_exact(
     uint32_t edges = 0;
     for (int qi = blockIdx.x; qi < nq; qi += gridDim.x) {
         const int pos = queue[qi];
-        const SetDesc S = sets[find_set(set_off, nsets, pos)];
+        const int si = find_set(set_off, nsets, pos);
+        const SetDesc S = sets[si];
         const Cell C = make_cell(S, sxy[pos]);
         const int g = S.site_off + sid[pos];
-        GStack st{area, 0};
-        GlobalRows rows{0};
-        Sink sink{area + dcap, sid};
-        const int r = run_cell<MODE, Coop>(C, sxy, bstart, st, dcap, rows, sink, dcap, K);
+        int r;
+        if (set_tree[si]) {
+            TreeScan<Coop, WaveFrames> sc{Tree{bstart, tchild, nodes, tref}, WaveFrames{fr},
+                                          NoList{},
+                                          Rect{}, false, Rect{}, 0, false};
+            r = coop_cell<MODE>(C, sxy, sid, sc, area, dcap, K);
+        } else {
+            GridScan<Coop, GlobalRows, false> sc{GlobalRows{0}, bstart, false};
+            r = coop_cell<MODE>(C, sxy, sid, sc, area, dcap, K);
+        }
         if (r == -2) {
             if (lane == 0) {
                 if (queue2) queue2[atomicAdd(qcount2, 1)] = pos;
@@ -238,7 +538,7 @@ __global__ __launch_bounds__(64) void k_cells_exact(
         K.rays = K.nodes = K.exact = K.shells = K.vtests = 0;
         edges = 0;
     }
-    reduce_stats(K, edges, 0, sh, stats);
+    reduce_stats(K, edges, 0, 0, sh, stats);
 }
 
 // ------------------------------------------------------------------------------ scan
@@ -485,83 +785,103 @@ void launch_scan(const int *in, long long n, int *out, int *tmp, const int *stat
 
 long long scan_tmp_ints(long long n) { return (long long)nblk(n, SCAN_TILE) + 1; }
 
+template <int BLOCK>
+static void launch_fast(const PipeArgs &a, hipStream_t st) {
+    const unsigned nb = (nblk(a.total, BLOCK) + 7) & ~7u;
+    k_cells_fast<BLOCK><<<nb, BLOCK, 0, st>>>(a.sets, a.nsets, a.set_off, a.sxy, a.sid, a.bstart,
+                                             a.total, a.ocnt, a.olines, a.ovf, a.queue,
+                                             a.qcount(), a.queue3, a.qcount3(), a.stats,
+                                             a.status());
+}
+
+template <int MODE>
+static void launch_exact(const PipeArgs &a, hipStream_t st) {
+    k_cells_exact<MODE><<<a.exact_blocks, 64, 0, st>>>(
+        a.sets, a.nsets, a.set_off, a.sxy, a.sid, a.bstart, a.tchild, a.nodes, a.tref, a.set_tree,
+        a.ocnt, a.olines, a.ovf, a.pool, a.poolcnt(), a.poolcap, a.queue, a.qcount(), a.queue2,
+        a.qcount2(), a.wbuf, DCAP1, a.stats, a.status_rw());
+    // deep cells: few workers with a large area each
+    k_cells_exact<MODE><<<DEEP_BLOCKS, 64, 0, st>>>(
+        a.sets, a.nsets, a.set_off, a.sxy, a.sid, a.bstart, a.tchild, a.nodes, a.tref, a.set_tree,
+        a.ocnt, a.olines, a.ovf, a.pool, a.poolcnt(), a.poolcap, a.queue2, a.qcount2(), nullptr,
+        nullptr,
+        a.wbuf2, DCAP2, a.stats, a.status_rw());
+}
+
+constexpr int TREE_PASS_BLOCK = 128;
+
 void launch_stage(const PipeArgs &a, hipStream_t st, int stage) {
     const int T = a.total;
     if (stage == 0) {
-    // 1. clear counters (no memset nodes: the sequence is captured as a graph)
-    {
+        // clear counters (no memset nodes: the sequence is captured as a graph)
         const long long n = a.gtot;
         const long long big = n > 64 ? n : 64;
-        k_clear<<<nblk(big, 256), 256, 0, st>>>(a.bcnt, n, a.small, SMALL_INTS, a.stats);
-    }
-    // 2. grid build
-    k_prep<<<nblk(T, 256), 256, 0, st>>>(a.sets, a.nsets, a.set_off, a.in_x, a.in_y, T, a.xyid,
-                                          a.key, a.bcnt, a.status());
-    launch_scan(a.bcnt, a.gtot, a.bstart, a.scan_tmp, a.status(), 0, st);
-    k_scatter<<<nblk(T, 256), 256, 0, st>>>(a.sets, a.nsets, a.set_off, T, a.xyid, a.key, a.bstart,
-                                             a.bcnt, a.sxy, a.sid);
-    k_dups<<<nblk(T, 256), 256, 0, st>>>(a.sets, a.nsets, a.set_off, T, a.sxy, a.bstart,
-                                          a.status());
+        k_clear<<<nblk(big, 256), 256, 0, st>>>(a.bcnt, n, a.small, SMALL_INTS, a.stats,
+                                                 a.set_tree, a.nsets);
+        // grid build (Method 11.5), then adaptive refinement of crowded buckets
+        k_prep<<<nblk(T, 256), 256, 0, st>>>(a.sets, a.nsets, a.set_off, a.in_x, a.in_y, T,
+                                              a.xyid, a.key, a.bcnt, a.status());
+        launch_scan(a.bcnt, a.gtot, a.bstart, a.scan_tmp, a.status(), 0, st);
+        k_scatter<<<nblk(T, 256), 256, 0, st>>>(a.sets, a.nsets, a.set_off, T, a.xyid, a.key,
+                                                 a.bstart, a.bcnt, a.sxy, a.sid);
+        k_tree_mark0<<<nblk(a.gtot + 1, 256), 256, 0, st>>>(a.sets, a.nsets, a.gtot, a.bstart,
+                                                            a.tchild, a.bcnt, a.nodes, a.ncap,
+                                                            a.nodecnt(), a.set_tree, a.status());
+        launch_scan(a.bcnt, a.gtot, a.tref, a.scan_tmp, a.status(), 1, st);
+        const unsigned rb = (unsigned)std::max(1, std::min(2048, a.ncap));
+        for (int lv = 0; lv < TREE_LEVELS; ++lv) {
+            k_tree_level<<<1, 64, 0, st>>>(a.level(), a.nodecnt(), a.ncap);
+            k_tree_refine<<<rb, REFINE_BLOCK, 0, st>>>(
+                a.nodes, a.level(), a.nodecnt(), a.ncap, a.bstart, a.tchild, a.tabcnt(),
+                a.gtot + 1, a.tabcap, a.sxy, a.sid, a.txy, a.tid, lv == TREE_LEVELS - 1 ? 1 : 0,
+                a.status_rw());
+        }
+        k_dups<<<nblk(T, 256), 256, 0, st>>>(a.sets, a.nsets, a.set_off, T, a.sxy, a.bstart,
+                                              a.tchild, a.nodes, a.status_rw());
     } else if (stage == 1) {
-    // 3. cells
-    if (a.exact_only || a.coop_all) {
-        k_queue_all<<<nblk(T, 256), 256, 0, st>>>(T, a.queue, a.qcount(), a.status());
-    } else {
-        const int B = a.block;
-        const unsigned nb = (nblk(T, B) + 7) & ~7u;
-        if (B == 64)
-            k_cells_fast<64><<<nb, 64, 0, st>>>(a.sets, a.nsets, a.set_off, a.sxy, a.sid, a.bstart,
-                                               T, a.ocnt, a.olines, a.ovf, a.queue, a.qcount(),
-                                               a.stats, a.status());
-        else if (B == 128)
-            k_cells_fast<128><<<nb, 128, 0, st>>>(a.sets, a.nsets, a.set_off, a.sxy, a.sid,
-                                                 a.bstart, T, a.ocnt, a.olines, a.ovf, a.queue,
-                                                 a.qcount(), a.stats, a.status());
+        // filtered cell pass
+        if (a.exact_only || a.coop_all)
+            k_queue_all<<<nblk(T, 256), 256, 0, st>>>(T, a.queue, a.qcount(), a.status());
+        else if (a.tree_all)
+            k_queue_all<<<nblk(T, 256), 256, 0, st>>>(T, a.queue3, a.qcount3(), a.status());
+        else if (a.block == 64)
+            launch_fast<64>(a, st);
+        else if (a.block == 128)
+            launch_fast<128>(a, st);
         else
-            k_cells_fast<256><<<nb, 256, 0, st>>>(a.sets, a.nsets, a.set_off, a.sxy, a.sid,
-                                                 a.bstart, T, a.ocnt, a.olines, a.ovf, a.queue,
-                                                 a.qcount(), a.stats, a.status());
-    }
+            launch_fast<256>(a, st);
     } else if (stage == 2) {
-    if (a.exact_only)
-        k_cells_exact<2><<<a.exact_blocks, 64, 0, st>>>(
-            a.sets, a.nsets, a.set_off, a.sxy, a.sid, a.bstart, a.ocnt, a.olines, a.ovf, a.pool,
-            a.poolcnt(), a.poolcap, a.queue, a.qcount(), a.queue2, a.qcount2(), a.wbuf, DCAP1,
-            a.stats, a.status_rw());
-    else
-        k_cells_exact<1><<<a.exact_blocks, 64, 0, st>>>(
-            a.sets, a.nsets, a.set_off, a.sxy, a.sid, a.bstart, a.ocnt, a.olines, a.ovf, a.pool,
-            a.poolcnt(), a.poolcap, a.queue, a.qcount(), a.queue2, a.qcount2(), a.wbuf, DCAP1,
-            a.stats, a.status_rw());
-    // deep cells: few workers with a large area each
-    if (a.exact_only)
-        k_cells_exact<2><<<DEEP_BLOCKS, 64, 0, st>>>(
-            a.sets, a.nsets, a.set_off, a.sxy, a.sid, a.bstart, a.ocnt, a.olines, a.ovf, a.pool,
-            a.poolcnt(), a.poolcap, a.queue2, a.qcount2(), nullptr, nullptr, a.wbuf2, DCAP2,
-            a.stats, a.status_rw());
-    else
-        k_cells_exact<1><<<DEEP_BLOCKS, 64, 0, st>>>(
-            a.sets, a.nsets, a.set_off, a.sxy, a.sid, a.bstart, a.ocnt, a.olines, a.ovf, a.pool,
-            a.poolcnt(), a.poolcap, a.queue2, a.qcount2(), nullptr, nullptr, a.wbuf2, DCAP2,
-            a.stats, a.status_rw());
+        // adaptive pass over the cells that met crowded buckets
+        if (!(a.exact_only || a.coop_all)) {
+            const unsigned nb = (unsigned)std::max<long long>(
+                1, std::min<long long>(nblk(T, TREE_PASS_BLOCK), 2048));
+            k_cells_tree<TREE_PASS_BLOCK><<<nb, TREE_PASS_BLOCK, 0, st>>>(
+                a.sets, a.nsets, a.set_off, a.sxy, a.sid, a.bstart, a.tchild, a.nodes, a.tref,
+                a.ocnt, a.olines, a.ovf, a.queue3, a.qcount3(), a.queue, a.qcount(), a.stats,
+                a.status());
+        }
+    } else if (stage == 3) {
+        if (a.exact_only) launch_exact<2>(a, st);
+        else launch_exact<1>(a, st);
     } else {
-    // 4. CSR
-    launch_scan(a.ocnt, T, a.cell_off, a.scan_tmp, a.status(), 1, st);
-    k_fill<<<nblk(T, 256), 256, 0, st>>>(a.sets, a.nsets, a.set_off, T, a.ocnt, a.olines, a.ovf,
-                                          a.pool, a.cell_off, a.nbr_cap, a.nbr, a.ecell, a.dcnt,
-                                          a.status_rw());
-    if (a.with_vertices) {
-        const long long cap = a.nbr_cap;
-        const unsigned nb = (unsigned)std::min<long long>(nblk(cap, 256), 8192);
-        k_vertices<<<nb, 256, 0, st>>>(a.sets, a.nsets, a.set_off, T, a.cell_off, a.nbr, a.ecell,
-                                       a.xyid, (Rat *)a.vtx, a.status());
-    }
-    launch_scan(a.dcnt, T, a.del_off, a.scan_tmp, a.status(), 1, st);
-    k_delaunay<<<nblk(T, 256), 256, 0, st>>>(a.sets, a.nsets, a.set_off, T, a.cell_off, a.nbr,
-                                              a.del_off, a.del, a.del_cap, a.status_rw());
-    if (a.check_symmetry)
-        k_symmetry<<<nblk(T, 256), 256, 0, st>>>(a.sets, a.nsets, a.set_off, T, a.cell_off, a.nbr,
-                                                  a.stats, a.status());
+        // CSR, vertices, Delaunay edges
+        launch_scan(a.ocnt, T, a.cell_off, a.scan_tmp, a.status(), 1, st);
+        k_fill<<<nblk(T, 256), 256, 0, st>>>(a.sets, a.nsets, a.set_off, T, a.ocnt, a.olines,
+                                              a.ovf, a.pool, a.cell_off, a.nbr_cap, a.nbr,
+                                              a.ecell, a.dcnt, a.status_rw());
+        if (a.with_vertices) {
+            const long long cap = a.nbr_cap;
+            const unsigned nb = (unsigned)std::min<long long>(nblk(cap, 256), 8192);
+            k_vertices<<<nb, 256, 0, st>>>(a.sets, a.nsets, a.set_off, T, a.cell_off, a.nbr,
+                                           a.ecell, a.xyid, (Rat *)a.vtx, a.status());
+        }
+        launch_scan(a.dcnt, T, a.del_off, a.scan_tmp, a.status(), 1, st);
+        k_delaunay<<<nblk(T, 256), 256, 0, st>>>(a.sets, a.nsets, a.set_off, T, a.cell_off,
+                                                  a.nbr, a.del_off, a.del, a.del_cap,
+                                                  a.status_rw());
+        if (a.check_symmetry)
+            k_symmetry<<<nblk(T, 256), 256, 0, st>>>(a.sets, a.nsets, a.set_off, T, a.cell_off,
+                                                      a.nbr, a.stats, a.status());
     }
 }
 
