@@ -165,13 +165,33 @@ __device__ __forceinline__ void consider_sides(const Cell &C, float dx, float dy
     consider(kh, sh, b);
 }
 
-__device__ __forceinline__ void eval_site(const Cell &C, const float2 *__restrict__ sxy, int pos,
-                                          float dx, float dy, int ex1, int ex2, Best &b) {
-    const float2 a = sxy[pos];
+__device__ __forceinline__ void eval_at(const Cell &C, float2 a, int pos, float dx, float dy,
+                                        int ex1, int ex2, Best &b) {
     const float ex = a.x - C.pxf, ey = a.y - C.pyf;
     float key = key_lo_line(site_q(ex, ey), ex, ey, dx, dy);
     key = (pos == ex1 || pos == ex2) ? FINF : key;
     consider(key, pos, b);
+}
+__device__ __forceinline__ void eval_site(const Cell &C, const float2 *__restrict__ sxy, int pos,
+                                          float dx, float dy, int ex1, int ex2, Best &b) {
+    eval_at(C, sxy[pos], pos, dx, dy, ex1, ex2, b);
+}
+
+// Candidates [pos, end) with stride W, two per step so that their loads overlap.
+template <int W>
+__device__ __forceinline__ void eval_range(const Cell &C, const float2 *__restrict__ sxy, int pos,
+                                           int end, float dx, float dy, int ex1, int ex2, Best &b,
+                                           Counters &K) {
+    for (; pos + W < end; pos += 2 * W) {
+        const float2 a0 = sxy[pos], a1 = sxy[pos + W];
+        eval_at(C, a0, pos, dx, dy, ex1, ex2, b);
+        eval_at(C, a1, pos + W, dx, dy, ex1, ex2, b);
+        K.evals += 2;
+    }
+    if (pos < end) {
+        eval_site(C, sxy, pos, dx, dy, ex1, ex2, b);
+        ++K.evals;
+    }
 }
 
 // Row ranges of the cell's warm-start block (up to MAXROWS rows, h <= 2), loaded once per
@@ -231,21 +251,12 @@ __device__ __forceinline__ void scan_rect_f32(const Cell &C, const float2 *__res
                                               Counters &K, bool &heavy) {
     RowWalk wk;
     wk.start(O, I);
-    int pos = 0, end = 0;
-    for (;;) {
-        if (pos < end) {
-            eval_site(C, sxy, pos, dx, dy, ex1, ex2, b);
-            pos += P::W;
-            ++K.evals;
-            continue;
-        }
-        if (!wk.next(C, bstart)) break;
+    while (wk.next(C, bstart)) {
         if (DETECT && wk.end - wk.pos > SEG_HEAVY) {
             heavy = true;
             break;
         }
-        pos = wk.pos + P::lane();
-        end = wk.end;
+        eval_range<P::W>(C, sxy, wk.pos + P::lane(), wk.end, dx, dy, ex1, ex2, b, K);
     }
 }
 
@@ -326,19 +337,10 @@ struct GridScan {
         Best b{FINF, FINF, NO_TAG};
         const Rect A = block_rect(C);
         if (BR.nrows <= MAXROWS) {
-            int r = 0, pos, end;
-            BR.get(C, bstart, 0, pos, end);
-            pos += P::lane();
-            for (;;) {
-                if (pos < end) {
-                    eval_site(C, sxy, pos, dx, dy, ex1, ex2, b);
-                    pos += P::W;
-                    ++K.evals;
-                    continue;
-                }
-                if (++r >= BR.nrows) break;
+            for (int r = 0; r < BR.nrows; ++r) {
+                int pos, end;
                 BR.get(C, bstart, r, pos, end);
-                pos += P::lane();
+                eval_range<P::W>(C, sxy, pos + P::lane(), end, dx, dy, ex1, ex2, b, K);
             }
         } else {
             scan_rect_f32<P, DETECT>(C, sxy, bstart, A, Rect{1, 0, 1, 0}, dx, dy, ex1, ex2, b, K,
@@ -508,7 +510,7 @@ struct TreeScan {
                 float key = key_lo_line(qq, ex, ey, dx, dy);
                 key = (q == ex1 || q == ex2) ? FINF : key;
                 const bool win = key < b.k1;
-                consider(key, q, b);
+                consider_once(key, q, b);
                 ++K.evals;
                 if (!CACHE && P::W == 1 && win) {
                     const float t = fminf(key_hi_line(qq, ex, ey, dx, dy), tcap);
@@ -547,7 +549,7 @@ struct TreeScan {
                 const float ex = a.x - C.pxf, ey = a.y - C.pyf;
                 float key = key_lo_line(site_q(ex, ey), ex, ey, dx, dy);
                 key = (q == ex1 || q == ex2 || (ex == 0.0f && ey == 0.0f)) ? FINF : key;
-                consider(key, q, b);
+                consider_once(key, q, b);
                 ++K.evals;
             }
             work += hi - lo + 4;

@@ -73,14 +73,18 @@ struct Best {
 };
 constexpr int NO_TAG = INT32_MIN;   // no candidate yet
 
-// A second evaluation of the current winner is ignored (it would pose as its own runner-up);
-// a second evaluation of any other candidate leaves the summary unchanged anyway.
 __device__ __forceinline__ void consider(float key, int tag, Best &b) {
-    if (tag == b.w) return;
     const bool better = key < b.k1;
     b.k2 = fminf(b.k2, fmaxf(b.k1, key));
     b.w = better ? tag : b.w;
     b.k1 = fminf(b.k1, key);
+}
+
+// For scans that may meet a candidate twice: a second evaluation of the current winner is
+// ignored (it would pose as its own runner-up); a second evaluation of any other candidate
+// leaves the summary unchanged anyway.
+__device__ __forceinline__ void consider_once(float key, int tag, Best &b) {
+    if (tag != b.w) consider(key, tag, b);
 }
 
 #pragma clang fp contract(off)
