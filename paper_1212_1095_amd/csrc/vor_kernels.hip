@@ -355,8 +355,9 @@ __device__ __forceinline__ void reduce_stats(const Counters &K, uint32_t edges, 
 
 // Filtered pass: one thread per cell, cells in bucket order, stack in LDS.  Cells whose scans
 // meet a crowded bucket go to the adaptive pass (queue3), undecided cells to the exact pass.
+// Five waves per SIMD (the register budget that this asks for beats the few spills it costs).
 template <int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_cells_fast(
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_cells_fast(
     const SetDesc *__restrict__ sets, int nsets, const int *__restrict__ set_off,
     const float2 *__restrict__ sxy, const int *__restrict__ sid, const int *__restrict__ bstart,
     int total, int *__restrict__ ocnt, int *__restrict__ olines, int *__restrict__ ovf,
