@@ -30,7 +30,6 @@ struct PipeArgs {
     int *tid;               // [total]
     int *queue3;            // cells handed to the adaptive pass [total]
     int *tref;              // [gtot + 1] refined grid buckets before each bucket
-    int *set_tree;          // [nsets] 1 when the set has refined buckets
     float2 *sxy;            // sorted coordinates [total]
     int *sid;               // local id of each sorted site [total]
     int *ocnt, *olines, *ovf;

@@ -43,10 +43,9 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
 }
 
 __global__ void k_clear(int *__restrict__ p, long long n, int *__restrict__ small, int nsmall,
-                        unsigned long long *__restrict__ stats, int *__restrict__ q, int nq) {
+                        unsigned long long *__restrict__ stats) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0;
-    if (i < nq) q[i] = 0;
     if (i < nsmall) small[i] = 0;
     if (i < SL_COUNT) stats[i] = 0;
 }
@@ -134,8 +133,7 @@ __device__ __forceinline__ int find_set_bucket(const SetDesc *__restrict__ sets,
 __global__ void k_tree_mark0(const SetDesc *__restrict__ sets, int nsets, long long gtot,
                              const int *__restrict__ bstart, int *__restrict__ tchild,
                              int *__restrict__ refined, TNode *__restrict__ nodes, int ncap,
-                             int *__restrict__ nodecnt, int *__restrict__ set_tree,
-                             const int *__restrict__ status) {
+                             int *__restrict__ nodecnt, const int *__restrict__ status) {
     if (*status) return;
     const long long b = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (b > gtot) return;
@@ -146,8 +144,7 @@ __global__ void k_tree_mark0(const SetDesc *__restrict__ sets, int nsets, long l
     const int cnt = bstart[b + 1] - bstart[b];
     int id = -1;
     if (cnt > TREE_C0) {
-        const int si = find_set_bucket(sets, nsets, b);
-        const SetDesc S = sets[si];
+        const SetDesc S = sets[find_set_bucket(sets, nsets, b)];
         const int local = (int)(b - S.bucket_off);
         id = atomicAdd(nodecnt, 1);
         if (id < ncap) {
@@ -160,7 +157,6 @@ __global__ void k_tree_mark0(const SetDesc *__restrict__ sets, int nsets, long l
             t.pk = (int)b;
             t.ss = t.m = t.tab = 0;
             nodes[id] = t;
-            set_tree[si] = 1;
         } else {
             id = -1;
         }
@@ -468,19 +464,18 @@ __device__ __forceinline__ int coop_cell(const Cell &C, const float2 *__restrict
 }
 
 // Exact pass over a queue of cells: one wave per cell (the Coop policy), a persistent grid of
-// one-wave blocks.  Sets with refined buckets are scanned through the tree.
+// one-wave blocks.  The scans run over the uniform grid even where buckets were refined: with
+// 64 lanes a crowded bucket is read in coalesced rows, which beats walking its sub-buckets.
 template <int MODE>
 __global__ __launch_bounds__(64) void k_cells_exact(
     const SetDesc *__restrict__ sets, int nsets, const int *__restrict__ set_off,
     const float2 *__restrict__ sxy, const int *__restrict__ sid, const int *__restrict__ bstart,
-    const int *__restrict__ tchild, const TNode *__restrict__ nodes, const int *__restrict__ tref,
-    const int *__restrict__ set_tree, int *__restrict__ ocnt, int *__restrict__ olines,
+    int *__restrict__ ocnt, int *__restrict__ olines,
     int *__restrict__ ovf, int *__restrict__ pool, int *__restrict__ poolcnt, long long poolcap,
     const int *__restrict__ queue, const int *__restrict__ qcount, int *__restrict__ queue2,
     int *__restrict__ qcount2, int *__restrict__ wbuf, int dcap,
     unsigned long long *__restrict__ stats, int *__restrict__ status) {
     __shared__ unsigned long long sh[SL_COUNT];
-    __shared__ int fr[TFRAMES][3];
     if (*status & (ST_DOMAIN | ST_DUP)) return;
     if (threadIdx.x < SL_COUNT) sh[threadIdx.x] = 0;
     __syncthreads();
@@ -491,20 +486,11 @@ __global__ __launch_bounds__(64) void k_cells_exact(
     uint32_t edges = 0;
     for (int qi = blockIdx.x; qi < nq; qi += gridDim.x) {
         const int pos = queue[qi];
-        const int si = find_set(set_off, nsets, pos);
-        const SetDesc S = sets[si];
+        const SetDesc S = sets[find_set(set_off, nsets, pos)];
         const Cell C = make_cell(S, sxy[pos]);
         const int g = S.site_off + sid[pos];
-        int r;
-        if (set_tree[si]) {
-            TreeScan<Coop, WaveFrames> sc{Tree{bstart, tchild, nodes, tref}, WaveFrames{fr},
-                                          NoList{},
-                                          Rect{}, false, Rect{}, 0, false};
-            r = coop_cell<MODE>(C, sxy, sid, sc, area, dcap, K);
-        } else {
-            GridScan<Coop, GlobalRows, false> sc{GlobalRows{0}, bstart, false};
-            r = coop_cell<MODE>(C, sxy, sid, sc, area, dcap, K);
-        }
+        GridScan<Coop, GlobalRows, false> sc{GlobalRows{0}, bstart, false};
+        const int r = coop_cell<MODE>(C, sxy, sid, sc, area, dcap, K);
         if (r == -2) {
             if (lane == 0) {
                 if (queue2) queue2[atomicAdd(qcount2, 1)] = pos;
@@ -798,13 +784,11 @@ static void launch_fast(const PipeArgs &a, hipStream_t st) {
 template <int MODE>
 static void launch_exact(const PipeArgs &a, hipStream_t st) {
     k_cells_exact<MODE><<<a.exact_blocks, 64, 0, st>>>(
-        a.sets, a.nsets, a.set_off, a.sxy, a.sid, a.bstart, a.tchild, a.nodes, a.tref, a.set_tree,
-        a.ocnt, a.olines, a.ovf, a.pool, a.poolcnt(), a.poolcap, a.queue, a.qcount(), a.queue2,
+        a.sets, a.nsets, a.set_off, a.sxy, a.sid, a.bstart, a.ocnt, a.olines, a.ovf, a.pool, a.poolcnt(), a.poolcap, a.queue, a.qcount(), a.queue2,
         a.qcount2(), a.wbuf, DCAP1, a.stats, a.status_rw());
     // deep cells: few workers with a large area each
     k_cells_exact<MODE><<<DEEP_BLOCKS, 64, 0, st>>>(
-        a.sets, a.nsets, a.set_off, a.sxy, a.sid, a.bstart, a.tchild, a.nodes, a.tref, a.set_tree,
-        a.ocnt, a.olines, a.ovf, a.pool, a.poolcnt(), a.poolcap, a.queue2, a.qcount2(), nullptr,
+        a.sets, a.nsets, a.set_off, a.sxy, a.sid, a.bstart, a.ocnt, a.olines, a.ovf, a.pool, a.poolcnt(), a.poolcap, a.queue2, a.qcount2(), nullptr,
         nullptr,
         a.wbuf2, DCAP2, a.stats, a.status_rw());
 }
@@ -817,8 +801,7 @@ void launch_stage(const PipeArgs &a, hipStream_t st, int stage) {
         // clear counters (no memset nodes: the sequence is captured as a graph)
         const long long n = a.gtot;
         const long long big = n > 64 ? n : 64;
-        k_clear<<<nblk(big, 256), 256, 0, st>>>(a.bcnt, n, a.small, SMALL_INTS, a.stats,
-                                                 a.set_tree, a.nsets);
+        k_clear<<<nblk(big, 256), 256, 0, st>>>(a.bcnt, n, a.small, SMALL_INTS, a.stats);
         // grid build (Method 11.5), then adaptive refinement of crowded buckets
         k_prep<<<nblk(T, 256), 256, 0, st>>>(a.sets, a.nsets, a.set_off, a.in_x, a.in_y, T,
                                               a.xyid, a.key, a.bcnt, a.status());
@@ -827,7 +810,7 @@ void launch_stage(const PipeArgs &a, hipStream_t st, int stage) {
                                                  a.bstart, a.bcnt, a.sxy, a.sid);
         k_tree_mark0<<<nblk(a.gtot + 1, 256), 256, 0, st>>>(a.sets, a.nsets, a.gtot, a.bstart,
                                                             a.tchild, a.bcnt, a.nodes, a.ncap,
-                                                            a.nodecnt(), a.set_tree, a.status());
+                                                            a.nodecnt(), a.status());
         launch_scan(a.bcnt, a.gtot, a.tref, a.scan_tmp, a.status(), 1, st);
         const unsigned rb = (unsigned)std::max(1, std::min(2048, a.ncap));
         for (int lv = 0; lv < TREE_LEVELS; ++lv) {

@@ -28,7 +28,7 @@ constexpr int TFRAMES = TREE_LEVELS + 1;
 constexpr int TREE_LIST = 48;     // cached candidate positions per cell (adaptive pass)
 constexpr int TREE_LIST_FILL = 20;// the cached region grows until it holds this many sites
 constexpr int TREE_PROBES = 6;    // leaves probed along the ray before a region pass
-constexpr int TREE_BUDGET = 8192; // sub-buckets + evaluations a lane spends on one cell before
+constexpr int TREE_BUDGET = 1024; // sub-buckets + evaluations a lane spends on one cell before
                                   // handing it to the one-wave-per-cell pass
 
 struct TNode {
@@ -153,8 +153,7 @@ __device__ __forceinline__ Rect grow_crect(const Rect &A, const Rect &R) {
                 max(min(A.y0, R.y0), A.y0 - wy), min(max(A.y1, R.y1), A.y1 + wy)};
 }
 
-// Frame stacks of the depth-first leaf walk: a column per thread in LDS (one lane per cell),
-// or one copy per wave (all lanes of a wave walk the same cell and write the same values).
+// Frame stack of the depth-first leaf walk: a column per thread in LDS (one lane per cell).
 template <int BLOCK>
 struct LdsFrames {
     int (*f)[3][BLOCK];
@@ -167,19 +166,6 @@ struct LdsFrames {
         node = f[d][0][threadIdx.x];
         i = f[d][1][threadIdx.x];
         j = f[d][2][threadIdx.x];
-    }
-};
-struct WaveFrames {
-    int (*f)[3];
-    __device__ __forceinline__ void put(int d, int node, int i, int j) {
-        f[d][0] = node;
-        f[d][1] = i;
-        f[d][2] = j;
-    }
-    __device__ __forceinline__ void get(int d, int &node, int &i, int &j) const {
-        node = f[d][0];
-        i = f[d][1];
-        j = f[d][2];
     }
 };
 
