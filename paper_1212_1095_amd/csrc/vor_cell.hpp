@@ -244,11 +244,54 @@ struct GlobalRows {
 // Candidates of rectangle O \ I, one flat loop per lane (a lane pays only for its own
 // candidates); with the Coop policy lane i takes every 64th candidate of each row.  With
 // DETECT a row segment longer than SEG_HEAVY stops the walk and sets `heavy`.
+// With the Coop policy the rows are spread over lane groups: segment s of O \ I is the left
+// (s even) or right (s odd) part of row O.y0 + s/2 (a row that misses I is whole in its left
+// part); COOP_G lanes share a segment, so a pass costs one round of row loads and one of site
+// loads instead of one per row.  A round that holds a long segment (a crowded bucket) is
+// scanned segment by segment with all lanes instead.
+constexpr int COOP_G = 8;
+constexpr int COOP_LONG = 4 * COOP_G;
+__device__ __forceinline__ void coop_segment(const Cell &C, const int *__restrict__ bstart,
+                                             const Rect &O, const Rect &I, int s, int &a,
+                                             int &e) {
+    a = e = 0;
+    const int row = O.y0 + (s >> 1);
+    if (row > O.y1) return;
+    int xa = O.x0, xb = O.x1;
+    if (row >= I.y0 && row <= I.y1) {
+        if (s & 1) xa = max(O.x0, I.x1 + 1);
+        else xb = min(O.x1, I.x0 - 1);
+    } else if (s & 1) {
+        return;
+    }
+    if (xa > xb) return;
+    const int base = C.boff + row * C.gx;
+    a = bstart[base + xa];
+    e = bstart[base + xb + 1];
+}
+
 template <class P, bool DETECT>
 __device__ __forceinline__ void scan_rect_f32(const Cell &C, const float2 *__restrict__ sxy,
                                               const int *__restrict__ bstart, Rect O, Rect I,
                                               float dx, float dy, int ex1, int ex2, Best &b,
                                               Counters &K, bool &heavy) {
+    if constexpr (P::W > 1) {
+        const int grp = P::lane() / COOP_G, sub = P::lane() % COOP_G;
+        const int nseg = 2 * (O.y1 - O.y0 + 1);
+        for (int s0 = 0; s0 < nseg; s0 += P::W / COOP_G) {
+            int a, e;
+            coop_segment(C, bstart, O, I, s0 + grp, a, e);
+            if (__any(e - a > COOP_LONG)) {
+                for (int g = 0; g < P::W / COOP_G; ++g) {
+                    const int ga = __shfl(a, g * COOP_G, 64), ge = __shfl(e, g * COOP_G, 64);
+                    eval_range<P::W>(C, sxy, ga + P::lane(), ge, dx, dy, ex1, ex2, b, K);
+                }
+            } else {
+                eval_range<COOP_G>(C, sxy, a + sub, e, dx, dy, ex1, ex2, b, K);
+            }
+        }
+        return;
+    }
     RowWalk wk;
     wk.start(O, I);
     while (wk.next(C, bstart)) {
@@ -279,6 +322,29 @@ __device__ __forceinline__ void exact_rect(const Cell &C, const float2 *__restri
                                            Rect I, float Tlim, int ex1, int ex2, XBest &b,
                                            Counters &K) {
     const float lim = Tlim * CERT_UP;
+    if constexpr (P::W > 1) {
+        const int grp = P::lane() / COOP_G, sub = P::lane() % COOP_G;
+        const int nseg = 2 * (O.y1 - O.y0 + 1);
+        for (int s0 = 0; s0 < nseg; s0 += P::W / COOP_G) {
+            int a, e;
+            coop_segment(C, bstart, O, I, s0 + grp, a, e);
+            if (__any(e - a > COOP_LONG)) {
+                for (int g = 0; g < P::W / COOP_G; ++g) {
+                    const int ga = __shfl(a, g * COOP_G, 64), ge = __shfl(e, g * COOP_G, 64);
+                    for (int q = ga + P::lane(); q < ge; q += P::W) {
+                        if (q == ex1 || q == ex2) continue;
+                        exact_site<FILTER, P>(C, sxy[q], q, d, lim, b, K);
+                    }
+                }
+            } else {
+                for (int q = a + sub; q < e; q += COOP_G) {
+                    if (q == ex1 || q == ex2) continue;
+                    exact_site<FILTER, P>(C, sxy[q], q, d, lim, b, K);
+                }
+            }
+        }
+        return;
+    }
     RowWalk wk;
     wk.start(O, I);
     int pos = 0, end = 0;
@@ -336,7 +402,7 @@ struct GridScan {
                                             Counters &K) {
         Best b{FINF, FINF, NO_TAG};
         const Rect A = block_rect(C);
-        if (BR.nrows <= MAXROWS) {
+        if (P::W == 1 && BR.nrows <= MAXROWS) {
             for (int r = 0; r < BR.nrows; ++r) {
                 int pos, end;
                 BR.get(C, bstart, r, pos, end);
@@ -733,8 +799,8 @@ struct LdsStack {
     __device__ __forceinline__ int pop() { return s[--depth][threadIdx.x]; }
 };
 
-// Stack in global memory; with the Coop policy every lane writes the same value to the same
-// address.
+// Stack shared by the lanes of a wave (LDS or global memory); with the Coop policy every lane
+// writes the same value to the same address.
 struct GStack {
     int *s;
     int depth;

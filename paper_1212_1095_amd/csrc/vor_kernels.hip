@@ -453,7 +453,7 @@ __global__ void k_queue_all(int total, int *__restrict__ queue, int *__restrict_
 }
 
 // One cell by one wave (the Coop policy) with scanner Sc; the cell's stack and output live in
-// the worker's area of dcap entries each.
+// `area` (dcap entries each).
 template <int MODE, class Sc>
 __device__ __forceinline__ int coop_cell(const Cell &C, const float2 *__restrict__ sxy,
                                          const int *__restrict__ sid, Sc &sc, int *area, int dcap,
@@ -466,7 +466,9 @@ __device__ __forceinline__ int coop_cell(const Cell &C, const float2 *__restrict
 // Exact pass over a queue of cells: one wave per cell (the Coop policy), a persistent grid of
 // one-wave blocks.  The scans run over the uniform grid even where buckets were refined: with
 // 64 lanes a crowded bucket is read in coalesced rows, which beats walking its sub-buckets.
-template <int MODE>
+// LCAP > 0: the stack and output of a cell live in LDS (LCAP entries each, the usual pass);
+// LCAP == 0: in the block's area of wbuf (dcap entries each, the deep pass).
+template <int MODE, int LCAP>
 __global__ __launch_bounds__(64) void k_cells_exact(
     const SetDesc *__restrict__ sets, int nsets, const int *__restrict__ set_off,
     const float2 *__restrict__ sxy, const int *__restrict__ sid, const int *__restrict__ bstart,
@@ -476,12 +478,15 @@ __global__ __launch_bounds__(64) void k_cells_exact(
     int *__restrict__ qcount2, int *__restrict__ wbuf, int dcap,
     unsigned long long *__restrict__ stats, int *__restrict__ status) {
     __shared__ unsigned long long sh[SL_COUNT];
+    __shared__ int larea[LCAP > 0 ? 2 * LCAP : 1];
     if (*status & (ST_DOMAIN | ST_DUP)) return;
+    const int nq = *qcount;
+    if ((int)blockIdx.x >= nq) return;   // no cell for this worker
     if (threadIdx.x < SL_COUNT) sh[threadIdx.x] = 0;
     __syncthreads();
     const int lane = threadIdx.x;
-    const int nq = *qcount;
-    int *area = wbuf + (size_t)blockIdx.x * 2 * dcap;
+    int *area = LCAP > 0 ? larea : wbuf + (size_t)blockIdx.x * 2 * dcap;
+    if (LCAP > 0) dcap = LCAP;
     Counters K{0, 0, 0, 0, 0, 0};
     uint32_t edges = 0;
     for (int qi = blockIdx.x; qi < nq; qi += gridDim.x) {
@@ -783,11 +788,11 @@ static void launch_fast(const PipeArgs &a, hipStream_t st) {
 
 template <int MODE>
 static void launch_exact(const PipeArgs &a, hipStream_t st) {
-    k_cells_exact<MODE><<<a.exact_blocks, 64, 0, st>>>(
+    k_cells_exact<MODE, DCAP1><<<a.exact_blocks, 64, 0, st>>>(
         a.sets, a.nsets, a.set_off, a.sxy, a.sid, a.bstart, a.ocnt, a.olines, a.ovf, a.pool, a.poolcnt(), a.poolcap, a.queue, a.qcount(), a.queue2,
         a.qcount2(), a.wbuf, DCAP1, a.stats, a.status_rw());
     // deep cells: few workers with a large area each
-    k_cells_exact<MODE><<<DEEP_BLOCKS, 64, 0, st>>>(
+    k_cells_exact<MODE, 0><<<DEEP_BLOCKS, 64, 0, st>>>(
         a.sets, a.nsets, a.set_off, a.sxy, a.sid, a.bstart, a.ocnt, a.olines, a.ovf, a.pool, a.poolcnt(), a.poolcap, a.queue2, a.qcount2(), nullptr,
         nullptr,
         a.wbuf2, DCAP2, a.stats, a.status_rw());
