@@ -871,86 +871,114 @@ __device__ __forceinline__ int ray(const Cell &C, Sc &sc, const float2 *__restri
 }
 
 // ------------------------------------------------------------------------------ one cell
-// Returns the number of lines written to the sink (>= 3), or
+// The walk over a cell's subedges as a resumable state: cell_begin, then cell_step until it
+// returns non-zero.  Phases 0..2 shoot the projector's corner rays (7,-4), (0,1), (-7,-4)
+// (counter-clockwise, consecutive gaps < pi); every later step resolves the subedge on top of
+// the stack.
+struct CellWalk {
+    Line cur, B;
+    int m, first, last, nodes, phase;
+};
+
+// Returns 0, or -4 when the scanner met a heavy bucket (the cell belongs to the adaptive pass).
+template <class Stack, class Sc>
+__device__ __forceinline__ int cell_begin(const Cell &C, const float2 *__restrict__ sxy, Sc &sc,
+                                          Stack &st, CellWalk &w) {
+    w.cur = Line{};
+    w.B = Line{};
+    w.m = w.first = w.last = w.nodes = w.phase = 0;
+    st.depth = 0;
+    sc.load(C, sxy);
+    return sc.heavy ? -4 : 0;
+}
+
+// One step.  Returns 0 (more steps), 1 (done: w.m lines in the sink), or
 //   -1 undecided in MODE 0, -2 stack / output capacity, -3 node limit (never expected),
-//   -4 the scanner met a heavy bucket (the cell belongs to the adaptive pass).
+//   -4 the scanner met a heavy bucket.
+template <int MODE, class P, class Stack, class Sc>
+__device__ __forceinline__ int cell_step(const Cell &C, const float2 *__restrict__ sxy, Sc &sc,
+                                         Stack &st, int scap, Sink &sink, int ocap, Counters &K,
+                                         CellWalk &w) {
+    const int phase = w.phase++;
+    Dir d;
+    int64_t Den = 0;
+    int ex1 = INT32_MIN, ex2 = INT32_MIN;
+    bool leaf = false;
+    Line R{}, L3{};
+    if (phase < 3) {
+        d = make_dir(phase == 1 ? 0 : (phase == 0 ? 7 : -7), phase == 1 ? 1 : -4);
+    } else {
+        if (st.depth == 0) {
+            if (w.m > 1 && w.last == w.first) --w.m;
+            return 1;
+        }
+        if (++w.nodes > NODE_LIMIT_FACTOR * (scap + ocap) + 64) return -3;
+        K.nodes++;
+        R = make_line(C, sxy, st.top());
+        const Line &cur = w.cur;
+        if (cur.id == R.id) {
+            leaf = true;   // SameLines
+        } else {
+            Den = (int64_t)cur.nx * R.ny - (int64_t)cur.ny * R.nx;
+            if (Den == 0) {   // ParallelLines: direction of the lines, inside the wedge
+                d = make_dir(-(i128)cur.ny, (i128)cur.nx);
+            } else {          // OutsideWedge (Den < 0) or Vertex / OutsideCell (Den > 0)
+                const i128 Zx = (i128)cur.c * R.ny - (i128)R.c * cur.ny;
+                const i128 Zy = (i128)cur.nx * R.c - (i128)R.nx * cur.c;
+                d = make_dir(Zx, Zy);
+                ex1 = cur.id;
+                ex2 = R.id;
+            }
+        }
+    }
+    if (!leaf) {
+        const int r = ray<MODE, P, Sc>(C, sc, sxy, d, Den, ex1, ex2, L3, K);
+        if (r < 0) return r == -4 ? -4 : -1;
+        leaf = (r == 1);
+        // a shot ray (Lemma on shot rays) yields a corner; a ray that confirms a vertex is the
+        // in-cell test of the vertex
+        if (leaf) K.vtests++; else K.rays++;
+    }
+    if (phase < 3) {
+        if (phase == 0) {
+            w.cur = L3;
+            w.first = w.last = L3.id;
+            sink.put(w.m++, L3.id);
+        } else if (phase == 1) {
+            w.B = L3;
+        } else {
+            st.push(w.first);   // closes the cycle
+            st.push(L3.id);
+            st.push(w.B.id);
+        }
+        return 0;
+    }
+    if (leaf) {
+        const int id = st.pop();
+        w.cur = R;
+        if (id != w.last) {
+            if (w.m >= ocap) return -2;
+            sink.put(w.m++, id);
+            w.last = id;
+        }
+    } else {
+        if (st.depth >= scap) return -2;
+        st.push(L3.id);
+    }
+    return 0;
+}
+
+// A whole cell.  Returns the number of lines written to the sink (>= 3), or the negative codes
+// of cell_step.
 template <int MODE, class P, class Stack, class Sc>
 __device__ __forceinline__ int run_cell(const Cell &C, const float2 *__restrict__ sxy, Sc &sc,
                                         Stack &st, int scap, Sink &sink, int ocap, Counters &K) {
-    Line cur{}, B{}, L3{};
-    int m = 0, first = 0, last = 0;
-    const int node_limit = NODE_LIMIT_FACTOR * (scap + ocap) + 64;
-    int nodes = 0;
-    st.depth = 0;
-    sc.load(C, sxy);
-    if (sc.heavy) return -4;
-    // phases 0..2: the projector's corner rays (7,-4), (0,1), (-7,-4): counter-clockwise,
-    // consecutive gaps < pi.  Then the subedge loop.
-    for (int phase = 0;; ++phase) {
-        Dir d;
-        int64_t Den = 0;
-        int ex1 = INT32_MIN, ex2 = INT32_MIN;
-        bool leaf = false;
-        Line R{};
-        if (phase < 3) {
-            d = make_dir(phase == 1 ? 0 : (phase == 0 ? 7 : -7), phase == 1 ? 1 : -4);
-        } else {
-            if (st.depth == 0) break;
-            if (++nodes > node_limit) return -3;
-            K.nodes++;
-            R = make_line(C, sxy, st.top());
-            if (cur.id == R.id) {
-                leaf = true;   // SameLines
-            } else {
-                Den = (int64_t)cur.nx * R.ny - (int64_t)cur.ny * R.nx;
-                if (Den == 0) {   // ParallelLines: direction of the lines, inside the wedge
-                    d = make_dir(-(i128)cur.ny, (i128)cur.nx);
-                } else {          // OutsideWedge (Den < 0) or Vertex / OutsideCell (Den > 0)
-                    const i128 Zx = (i128)cur.c * R.ny - (i128)R.c * cur.ny;
-                    const i128 Zy = (i128)cur.nx * R.c - (i128)R.nx * cur.c;
-                    d = make_dir(Zx, Zy);
-                    ex1 = cur.id;
-                    ex2 = R.id;
-                }
-            }
-        }
-        if (!leaf) {
-            const int r = ray<MODE, P, Sc>(C, sc, sxy, d, Den, ex1, ex2, L3, K);
-            if (r < 0) return r == -4 ? -4 : -1;
-            leaf = (r == 1);
-            // a shot ray (Lemma on shot rays) yields a corner; a ray that confirms a vertex
-            // is the in-cell test of the vertex
-            if (leaf) K.vtests++; else K.rays++;
-        }
-        if (phase < 3) {
-            if (phase == 0) {
-                cur = L3;
-                first = last = L3.id;
-                sink.put(m++, L3.id);
-            } else if (phase == 1) {
-                B = L3;
-            } else {
-                st.push(first);   // closes the cycle
-                st.push(L3.id);
-                st.push(B.id);
-            }
-            continue;
-        }
-        if (leaf) {
-            const int id = st.pop();
-            cur = R;
-            if (id != last) {
-                if (m >= ocap) return -2;
-                sink.put(m++, id);
-                last = id;
-            }
-        } else {
-            if (st.depth >= scap) return -2;
-            st.push(L3.id);
-        }
+    CellWalk w;
+    if (cell_begin(C, sxy, sc, st, w) < 0) return -4;
+    for (;;) {
+        const int r = cell_step<MODE, P>(C, sxy, sc, st, scap, sink, ocap, K, w);
+        if (r != 0) return r > 0 ? w.m : r;
     }
-    if (m > 1 && last == first) --m;
-    return m;
 }
 
 }  // namespace vor
