@@ -224,10 +224,17 @@ def main():
     ctx = vor.Context(device=0, precision=vor.VOR_FP32_FILTERED,
                       flags=vor.VOR_RESULT_DEVICE | vor.VOR_TIME_KERNELS)
     tuning = list(vor.vor_get_tuning(ctx.h))
+    tuning_source = "library default"
+    from paper_1212_1095_amd import autotune
+    tuned = autotune.best_params(ps.n, args.dist)
+    if tuned is not None:
+        tuning = list(tuned)
+        tuning_source = "autotuned (" + os.path.basename(autotune.TABLE) + ")"
     for i, v in ((0, args.sites_per_bucket), (2, args.block_halfwidth), (3, args.leaf_halfwidth),
                  (4, None if args.path is None else (1 if args.path == "tree" else 0))):
         if v is not None:
             tuning[i] = v
+            tuning_source = "command line"
     ctx.tune(*tuning)
     log(f"tuning (sites/bucket, block, h, leaf h, path): {tuning}")
 
@@ -349,7 +356,8 @@ def main():
                   "adaptive_cells": st.adaptive_cells,
                   "tuning": {"sites_per_bucket": tuning[0], "block": tuning[1],
                              "block_halfwidth": tuning[2], "leaf_halfwidth": tuning[3],
-                             "path": "tree" if tuning[4] == 1 else "grid-first"},
+                             "path": "tree" if tuning[4] == 1 else "grid-first",
+                             "source": tuning_source},
                   "stage_ms": {"grid": round(last.grid_ms, 4), "cells": round(last.cells_ms, 4),
                                "adaptive": round(last.adaptive_ms, 4),
                                "exact": round(last.exact_ms, 4), "emit": round(last.emit_ms, 4)},

@@ -1,11 +1,12 @@
-"""Autotuner: picks the grid density, block half-width and workgroup size of the cell kernel
-for a workload shape by timing the C-ABI pipeline on the device (results are exact whatever
-the parameters; only the speed changes).
+"""Autotuner: picks the grid density, block half-width, workgroup size, leaf half-width and
+scan path for a workload shape by timing the C-ABI pipeline on the device (results are exact
+whatever the parameters; only the speed changes).
 
     python -m paper_1212_1095_amd.autotune --n 1048576 --box 16777216 [--out tuning.json]
 
-The table maps "log2(n)" (rounded) and a distribution tag to the best (sites_per_bucket,
-block, block_halfwidth).  ``best_params`` looks a shape up (nearest log2 n).
+The table maps a distribution tag and "log2(n)" (rounded) to the best (sites_per_bucket, block,
+block_halfwidth, leaf_halfwidth, scan_path).  ``best_params`` looks a shape up (nearest
+log2 n) and returns the arguments of ``Context.tune``.
 """
 from __future__ import annotations
 
@@ -19,13 +20,17 @@ import time
 HERE = os.path.dirname(os.path.abspath(__file__))
 TABLE = os.path.join(HERE, "tuning.json")
 
-DEFAULT_GRID = [(0.5, 1), (0.7, 1), (1.0, 1), (1.5, 1), (2.0, 1), (0.35, 2), (0.5, 2), (1.0, 2)]
+# (sites_per_bucket, block_halfwidth, leaf_halfwidth, scan_path)
+DEFAULT_GRID = [(0.5, 1, 0, 0), (0.7, 1, 0, 0), (1.0, 1, 0, 0), (1.5, 1, 0, 0), (2.0, 1, 0, 0),
+                (0.35, 2, 0, 0), (0.5, 2, 0, 0), (0.7, 2, 0, 0), (1.0, 2, 0, 0),
+                (1.0, 0, 1, 0), (1.0, 0, 0, 1), (2.0, 0, 0, 1)]
 DEFAULT_BLOCKS = (256,)
+KEYS = ("sites_per_bucket", "block", "block_halfwidth", "leaf_halfwidth", "scan_path")
 
 
-def time_config(ctx, xd, yd, n, box, rho, h, block, reps=5, warmup=2):
+def time_config(ctx, xd, yd, n, box, rho, h, block, ht=0, path=0, reps=5, warmup=2):
     import torch
-    ctx.tune(rho, block, h)
+    ctx.tune(rho, block, h, ht, path)
     for _ in range(warmup):
         ctx.compute((xd.data_ptr(), n), (yd.data_ptr(), n), box, device_ptrs=True)
     torch.cuda.synchronize()
@@ -45,11 +50,13 @@ def sweep(x, y, box, grid=DEFAULT_GRID, blocks=DEFAULT_BLOCKS, reps=5, log=print
     yd = torch.from_numpy(np.ascontiguousarray(y, dtype=np.int32)).cuda()
     rows = []
     with Context(flags=VOR_RESULT_DEVICE | VOR_TIME_KERNELS) as ctx:
-        for rho, h in grid:
+        for rho, h, ht, path in grid:
             for block in blocks:
-                ms, r = time_config(ctx, xd, yd, n, box, rho, h, block, reps)
-                row = {"sites_per_bucket": rho, "block_halfwidth": h, "block": block, "ms": ms,
-                       "cells_ms": r.cells_ms, "exact_ms": r.exact_ms,
+                ms, r = time_config(ctx, xd, yd, n, box, rho, h, block, ht, path, reps)
+                row = {"sites_per_bucket": rho, "block_halfwidth": h, "block": block,
+                       "leaf_halfwidth": ht, "scan_path": path, "ms": ms,
+                       "cells_ms": r.cells_ms, "adaptive_ms": r.adaptive_ms,
+                       "exact_ms": r.exact_ms,
                        "evals_per_cell": r.stats.evals / n, "shells_per_cell": r.stats.shells / n}
                 rows.append(row)
                 log(json.dumps(row))
@@ -65,13 +72,14 @@ def load_table(path=TABLE) -> dict:
 
 
 def best_params(n: int, dist: str = "uniform", path=TABLE):
-    """(sites_per_bucket, block, block_halfwidth) for the nearest tuned log2(n), or None."""
+    """(sites_per_bucket, block, block_halfwidth, leaf_halfwidth, scan_path) for the nearest
+    tuned log2(n), or None."""
     t = load_table(path).get(dist, {})
     if not t:
         return None
     key = min(t.keys(), key=lambda k: abs(int(k) - round(math.log2(max(n, 1)))))
     e = t[key]
-    return e["sites_per_bucket"], e["block"], e["block_halfwidth"]
+    return tuple(e.get(k, d) for k, d in zip(KEYS, (1.0, 256, 0, 0, 0)))
 
 
 def main():
@@ -94,7 +102,7 @@ def main():
     if a.out:
         t = load_table(a.out)
         t.setdefault(a.dist, {})[str(round(math.log2(a.n)))] = {
-            k: best[k] for k in ("sites_per_bucket", "block", "block_halfwidth", "ms")}
+            k: best[k] for k in KEYS + ("ms",)}
         with open(a.out, "w") as f:
             json.dump(t, f, indent=1, sort_keys=True)
 

@@ -52,3 +52,18 @@ def test_no_fallback_when_library_missing(tmp_path, monkeypatch):
     monkeypatch.setattr(b, "_lib", None)
     with pytest.raises(ImportError):
         b.lib()
+
+
+def test_autotune_table_lookup(tmp_path):
+    """The autotuner's table maps (distribution, nearest log2 n) to Context.tune arguments."""
+    import json
+    from paper_1212_1095_amd import autotune
+    table = {"uniform": {"10": {"sites_per_bucket": 2.0, "block": 256, "block_halfwidth": 0,
+                                "leaf_halfwidth": 0, "scan_path": 1, "ms": 0.3},
+                         "20": {"sites_per_bucket": 1.0, "block": 128, "block_halfwidth": 2,
+                                "ms": 2.0}}}
+    p = tmp_path / "t.json"
+    p.write_text(json.dumps(table))
+    assert autotune.best_params(1000, "uniform", path=str(p)) == (2.0, 256, 0, 0, 1)
+    assert autotune.best_params(900000, "uniform", path=str(p)) == (1.0, 128, 2, 0, 0)
+    assert autotune.best_params(1000, "clustered", path=str(p)) is None
