@@ -76,7 +76,7 @@ enum BufId {
     B_SETS, B_SETOFF, B_INX, B_INY, B_XYID, B_KEY, B_BCNT, B_BSTART, B_SXY, B_SID, B_OCNT,
     B_OLINES, B_OVF, B_POOL, B_QUEUE, B_QUEUE2, B_WBUF, B_WBUF2, B_CELLOFF, B_NBR, B_VTX,
     B_DCNT, B_DELOFF, B_DEL, B_SCANTMP, B_SMALL, B_STATS, B_ECELL, B_TCHILD, B_NODES, B_TXY,
-    B_TID, B_QUEUE3, B_TREF, B_COUNT
+    B_TID, B_QUEUE3, B_TREF, B_NLIST, B_COUNT
 };
 
 struct Workspace {
@@ -236,7 +236,7 @@ size_t footprint_bytes(uint64_t total, uint64_t gtot, bool vertices) {
     b += gtot * 16;                                                 // counts, starts, tree slots
     b += total * (8 + 4 + 4);                                       // refinement scratch, queue
     b += (3 * total + 1024) * 8;                                    // sub-bucket tables
-    b += (TREE_LEVELS * (total / (TREE_C1 + 1)) + 64) * sizeof(TNode);
+    b += (TREE_LEVELS * (total / (TREE_C1 + 1)) + 64) * (sizeof(TNode) + 4 * (TREE_LEVELS - 1));
     return b;
 }
 
@@ -287,7 +287,8 @@ int launch(vor_ctx *ctx, Workspace &ws, const std::vector<HostSet> &sets, bool v
         {B_INY, 4ull * T}, {B_XYID, 8ull * T}, {B_KEY, 4ull * T}, {B_BCNT, 4ull * gtot},
         {B_BSTART, 4ull * (gtot + 1 + tabcap)}, {B_TCHILD, 4ull * (gtot + 1 + tabcap)},
         {B_NODES, sizeof(TNode) * ncap}, {B_TXY, 8ull * T}, {B_TID, 4ull * T},
-        {B_QUEUE3, 4ull * T}, {B_TREF, 4ull * (gtot + 1)}, {B_SXY, 8ull * T}, {B_SID, 4ull * T},
+        {B_QUEUE3, 4ull * T}, {B_TREF, 4ull * (gtot + 1)},
+        {B_NLIST, 4ull * (TREE_LEVELS - 1) * ncap}, {B_SXY, 8ull * T}, {B_SID, 4ull * T},
         {B_OCNT, 4ull * T}, {B_OLINES, 4ull * KOUT * T}, {B_OVF, 4ull * T}, {B_POOL, 4ull * E},
         {B_QUEUE, 4ull * T}, {B_QUEUE2, 4ull * T},
         {B_WBUF, 4ull * 2 * DCAP1 * exact_blocks}, {B_WBUF2, 4ull * 2 * DCAP2 * DEEP_BLOCKS},
@@ -354,6 +355,7 @@ int launch(vor_ctx *ctx, Workspace &ws, const std::vector<HostSet> &sets, bool v
     a.tid = ws.b[B_TID].as<int>();
     a.queue3 = ws.b[B_QUEUE3].as<int>();
     a.tref = ws.b[B_TREF].as<int>();
+    a.nlist = ws.b[B_NLIST].as<int>();
     a.sxy = ws.b[B_SXY].as<float2>();
     a.sid = ws.b[B_SID].as<int>();
     a.ocnt = ws.b[B_OCNT].as<int>();

@@ -9,6 +9,7 @@ struct SetDesc;
 struct TNode;
 constexpr int SMALL_INTS = 16;   // status, queue counters, pool / tree counters, spare
 constexpr int DEEP_BLOCKS = 8;   // one-wave workers of the deep-cell pass
+constexpr int LVCNT0 = 8;        // small[LVCNT0 + l]: nodes listed for refinement level l (2..6)
 
 // Device pointers and sizes of one pipeline launch.
 struct PipeArgs {
@@ -60,10 +61,11 @@ struct PipeArgs {
     int *qcount() const { return small + 1; }
     int *qcount2() const { return small + 2; }
     int *poolcnt() const { return small + 3; }
-    int *nodecnt() const { return small + 4; }
+    int *nodecnt() const { return small + 4; }   // nodes below the roots
     int *tabcnt() const { return small + 5; }
-    int *level() const { return small + 6; }     // [lo, hi) of the nodes to refine next
+    int *rootcnt() const { return small + 6; }   // refined grid buckets (tree roots)
     int *qcount3() const { return small + 8; }
+    int *nlist;             // [TREE_LEVELS - 1][ncap] node ids of refinement levels 2..
 };
 
 // stages: 0 grid build and refinement, 1 filtered cell pass, 2 adaptive pass, 3 exact / deep

@@ -156,6 +156,7 @@ __global__ void k_tree_mark0(const SetDesc *__restrict__ sets, int nsets, long l
             t.cnt = cnt;
             t.pk = (int)b;
             t.ss = t.m = t.tab = 0;
+            t.lv = 1;
             nodes[id] = t;
         } else {
             id = -1;
@@ -165,32 +166,32 @@ __global__ void k_tree_mark0(const SetDesc *__restrict__ sets, int nsets, long l
     refined[b] = id >= 0 ? 1 : 0;
 }
 
-// [lo, hi) of the nodes the next refinement level processes.
-__global__ void k_tree_level(int *__restrict__ lvl, const int *__restrict__ nodecnt, int ncap) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        lvl[0] = lvl[1];
-        lvl[1] = min(*nodecnt, ncap);
-    }
-}
-
-// One block per node: counting sort of the node's sites into an m x m grid of sub-buckets
-// (through the scratch arrays), the node's sub-bucket starts, and nodes for crowded
-// sub-buckets (refined by the next level).
+// One refinement level per launch, one block per node: a counting sort of the node's sites into
+// an m x m grid of sub-buckets over their bounding square (through the scratch arrays), the
+// node's sub-bucket starts, and nodes for crowded sub-buckets, listed for the next level.
+// Level 1 refines the grid buckets marked by k_tree_mark0 (node ids 0..roots-1); level l > 1
+// takes its node ids from list l, filled by the launch of level l - 1.
 constexpr int REFINE_BLOCK = 256;
 constexpr int REFINE_MAXSUB = TREE_MMAX * TREE_MMAX;
 
 __global__ __launch_bounds__(REFINE_BLOCK) void k_tree_refine(
-    TNode *__restrict__ nodes, const int *__restrict__ lvl, int *__restrict__ nodecnt, int ncap,
-    int *__restrict__ tstart, int *__restrict__ tchild, int *__restrict__ tabcnt, long long tab0,
-    long long tabcap, float2 *__restrict__ sxy, int *__restrict__ sid, float2 *__restrict__ txy,
-    int *__restrict__ tid, int last_level, int *__restrict__ status) {
+    TNode *__restrict__ nodes, int level, const int *__restrict__ rootcnt,
+    int *__restrict__ childcnt, int *__restrict__ lvcnt, int *__restrict__ nlist, int lcap,
+    int ncap, int *__restrict__ tstart, int *__restrict__ tchild, int *__restrict__ tabcnt,
+    long long tab0, long long tabcap, float2 *__restrict__ sxy, int *__restrict__ sid,
+    float2 *__restrict__ txy, int *__restrict__ tid, int *__restrict__ status) {
     __shared__ int cnt[REFINE_MAXSUB];
     __shared__ int pre[REFINE_MAXSUB + 1];
     __shared__ int sh_tab, sh_part[REFINE_BLOCK];
     __shared__ int sh_box[4];
     if (*status) return;
-    const int lo = lvl[0], hi = lvl[1];
-    for (int id = lo + blockIdx.x; id < hi; id += gridDim.x) {
+    const int nroot = min(*rootcnt, ncap);
+    const int nlevel = level == 1 ? nroot : min(lvcnt[level], lcap);
+    const int *mine = nlist + (size_t)max(level - 2, 0) * lcap;
+    int *next = nlist + (size_t)(level - 1) * lcap;
+    for (int i = blockIdx.x; i < nlevel; i += gridDim.x) {
+        const int id = level == 1 ? i : mine[i];
+        if (id < 0) continue;   // uniform across the block
         TNode t = nodes[id];
         // bounding square of the node's sites
         if (threadIdx.x == 0) {
@@ -221,7 +222,7 @@ __global__ __launch_bounds__(REFINE_BLOCK) void k_tree_refine(
         if (threadIdx.x == 0) {
             const int tb = atomicAdd(tabcnt, mm + 1);
             sh_tab = ((long long)tb + mm + 1 > tabcap || t.size < 2) ? -1 : tb;
-            if (t.size < 2) atomicOr(status, ST_DUP);   // > TREE_C0 sites on one lattice point
+            if (t.size < 2) atomicOr(status, ST_DUP);   // many sites on one lattice point
         }
         for (int k = threadIdx.x; k < mm; k += REFINE_BLOCK) cnt[k] = 0;
         __syncthreads();
@@ -233,8 +234,9 @@ __global__ __launch_bounds__(REFINE_BLOCK) void k_tree_refine(
         }
         for (int p = t.a + threadIdx.x; p < t.a + t.cnt; p += REFINE_BLOCK) {
             const float2 q = sxy[p];
-            const int i = min(((int)q.x - t.ox) / ss, m - 1), j = min(((int)q.y - t.oy) / ss, m - 1);
-            atomicAdd(&cnt[j * m + i], 1);
+            const int i2 = min(((int)q.x - t.ox) / ss, m - 1);
+            const int j2 = min(((int)q.y - t.oy) / ss, m - 1);
+            atomicAdd(&cnt[j2 * m + i2], 1);
         }
         __syncthreads();
         // exclusive scan of cnt[0..mm) into pre: a chunk per thread, then the chunk sums
@@ -267,8 +269,9 @@ __global__ __launch_bounds__(REFINE_BLOCK) void k_tree_refine(
         __syncthreads();
         for (int p = t.a + threadIdx.x; p < t.a + t.cnt; p += REFINE_BLOCK) {
             const float2 q = sxy[p];
-            const int i = min(((int)q.x - t.ox) / ss, m - 1), j = min(((int)q.y - t.oy) / ss, m - 1);
-            const int dst = t.a + atomicAdd(&cnt[j * m + i], 1);
+            const int i2 = min(((int)q.x - t.ox) / ss, m - 1);
+            const int j2 = min(((int)q.y - t.oy) / ss, m - 1);
+            const int dst = t.a + atomicAdd(&cnt[j2 * m + i2], 1);
             txy[dst] = q;
             tid[dst] = sid[p];
         }
@@ -277,24 +280,29 @@ __global__ __launch_bounds__(REFINE_BLOCK) void k_tree_refine(
             sxy[p] = txy[p];
             sid[p] = tid[p];
         }
-        // children
+        // children: crowded sub-buckets below the last level become nodes of the next list
         for (int k = threadIdx.x; k < mm; k += REFINE_BLOCK) {
             const int c = pre[k + 1] - pre[k];
             int cid = -1;
-            if (c > TREE_C1 && !last_level) {
-                cid = atomicAdd(nodecnt, 1);
-                if (cid < ncap) {
-                    TNode u;
-                    u.ox = t.ox + (k % m) * ss;
-                    u.oy = t.oy + (k / m) * ss;
-                    u.size = ss;
-                    u.a = t.a + pre[k];
-                    u.cnt = c;
-                    u.pk = (int)(base + k);
-                    u.ss = u.m = u.tab = 0;
-                    nodes[cid] = u;
-                } else {
-                    cid = -1;
+            if (c > TREE_C1 && level < TREE_LEVELS) {
+                const int slot = atomicAdd(&lvcnt[level + 1], 1);
+                if (slot < lcap) {
+                    cid = nroot + atomicAdd(childcnt, 1);
+                    if (cid < ncap) {
+                        TNode u;
+                        u.ox = t.ox + (k % m) * ss;
+                        u.oy = t.oy + (k / m) * ss;
+                        u.size = ss;
+                        u.a = t.a + pre[k];
+                        u.cnt = c;
+                        u.pk = (int)(base + k);
+                        u.ss = u.m = u.tab = 0;
+                        u.lv = level + 1;
+                        nodes[cid] = u;
+                    } else {
+                        cid = -1;
+                    }
+                    next[slot] = cid;   // -1: skipped by the next level
                 }
             }
             tchild[base + k] = cid;
@@ -815,16 +823,14 @@ void launch_stage(const PipeArgs &a, hipStream_t st, int stage) {
                                                  a.bstart, a.bcnt, a.sxy, a.sid);
         k_tree_mark0<<<nblk(a.gtot + 1, 256), 256, 0, st>>>(a.sets, a.nsets, a.gtot, a.bstart,
                                                             a.tchild, a.bcnt, a.nodes, a.ncap,
-                                                            a.nodecnt(), a.status());
+                                                            a.rootcnt(), a.status());
         launch_scan(a.bcnt, a.gtot, a.tref, a.scan_tmp, a.status(), 1, st);
         const unsigned rb = (unsigned)std::max(1, std::min(2048, a.ncap));
-        for (int lv = 0; lv < TREE_LEVELS; ++lv) {
-            k_tree_level<<<1, 64, 0, st>>>(a.level(), a.nodecnt(), a.ncap);
+        for (int lv = 1; lv <= TREE_LEVELS; ++lv)
             k_tree_refine<<<rb, REFINE_BLOCK, 0, st>>>(
-                a.nodes, a.level(), a.nodecnt(), a.ncap, a.bstart, a.tchild, a.tabcnt(),
-                a.gtot + 1, a.tabcap, a.sxy, a.sid, a.txy, a.tid, lv == TREE_LEVELS - 1 ? 1 : 0,
+                a.nodes, lv, a.rootcnt(), a.nodecnt(), a.small + LVCNT0, a.nlist, a.ncap, a.ncap,
+                a.bstart, a.tchild, a.tabcnt(), a.gtot + 1, a.tabcap, a.sxy, a.sid, a.txy, a.tid,
                 a.status_rw());
-        }
         k_dups<<<nblk(T, 256), 256, 0, st>>>(a.sets, a.nsets, a.set_off, T, a.sxy, a.bstart,
                                               a.tchild, a.nodes, a.status_rw());
     } else if (stage == 1) {

@@ -38,6 +38,7 @@ struct TNode {
     int pk;       // table slot of the parent that points to this node
     int ss, m;    // sub-bucket side, sub-buckets per axis (set by the refinement)
     int tab;      // first of the m*m + 1 sub-bucket starts in the table
+    int lv;       // refinement level (1 for a refined grid bucket)
 };
 
 // Table of bucket starts: the grid's gtot + 1 starts first, then the nodes' sub-bucket starts;
