@@ -180,6 +180,28 @@ typedef struct {
 int vor_set_tuning(vor_ctx *ctx, const vor_tuning *t);
 int vor_get_tuning(vor_ctx *ctx, vor_tuning *t);
 
+/* Diagnostic (not on the hot path): the FP32 filter keys that the cell passes compute for one
+ * line and one ray direction each, so that their bounds can be checked in exact arithmetic
+ * (the filter sits in front of the exact comparisons of eq. Tdef, Theorem 2.2; buckets and
+ * filtered candidate scans of Method 11.5).  Frame: p-relative and doubled, a line is
+ * N.w <= c with N = (nx[i], ny[i]).
+ *   kind[i]  0: site candidate, N = delta = a - p, c = |delta|^2 (c[i] ignored);
+ *            1: general line with c = c[i], 0 < c <= 2^50 (box sides are such lines)
+ *   nx, ny   |.| <= 2^24, not both zero
+ *   dir      [4n] ray direction d as two signed 128-bit integers, each given as
+ *            (high 64 bits, low 64 bits): x_hi, x_lo, y_hi, y_lo; |component| < 2^100
+ *            (|high| < 2^36), d != 0
+ *   out      [8n] floats per instance: key_lo, key_hi, key_lo * (1 - 2^-19),
+ *            key_hi * (1 + 2^-19), upper bound of the exact endpoint parameter (as used after an
+ *            exact decision; +inf when N.d <= 0), d_s.x, d_s.y, 0.  Keys are in units of
+ *            d_s = d 2^-sigma: the exact key is c 2^sigma / (N.d) when N.d > 0.
+ *   sigma    [n] the scaling exponent
+ * All arrays are host memory owned by the caller; n == 0 is a no-op.  Returns VOR_E_INVAL for
+ * a null pointer or an argument out of range, VOR_E_NOMEM / VOR_E_DEVICE for HIP failures. */
+int vor_filter_keys(int32_t device, int64_t n, const int32_t *kind, const int32_t *nx,
+                    const int32_t *ny, const int64_t *c, const int64_t *dir, float *out,
+                    int32_t *sigma);
+
 /* Version string of the library build (never NULL). */
 const char *vor_version(void);
 

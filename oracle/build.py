@@ -6,15 +6,22 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "vor_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
+FILTER_SRC = os.path.join(HERE, "filter_exact.c")
+FILTER_LIB = os.path.join(HERE, "libfilterexact.so")
 
 
-def build(verbose: bool = False) -> str:
+def _gcc(src: str, lib: str, verbose: bool, extra=()) -> None:
     cmd = ["gcc", "-O2", "-std=gnu11", "-Wall", "-Wextra", "-shared", "-fPIC", "-pthread",
-           "-o", LIB + ".tmp", SRC]
+           "-o", lib + ".tmp", src] + list(extra)
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(LIB + ".tmp", LIB)
+    os.replace(lib + ".tmp", lib)
+
+
+def build(verbose: bool = False) -> str:
+    _gcc(SRC, LIB, verbose)
+    _gcc(FILTER_SRC, FILTER_LIB, verbose, ["-fopenmp", "-lm"])
     return LIB
 
 

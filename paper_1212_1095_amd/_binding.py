@@ -91,9 +91,13 @@ def lib():
         L.vor_set_tuning.argtypes = [C.c_void_p, P(vor_tuning)]
         L.vor_get_tuning.argtypes = [C.c_void_p, P(vor_tuning)]
         L.vor_version.argtypes = []
+        L.vor_filter_keys.argtypes = [C.c_int32, C.c_int64, P(C.c_int32), P(C.c_int32),
+                                      P(C.c_int32), P(C.c_int64), P(C.c_int64), P(C.c_float),
+                                      P(C.c_int32)]
         L.vor_version.restype = C.c_char_p
         for f in ("vor_create", "vor_destroy", "vor_compute", "vor_compute_batch", "vor_submit",
-                  "vor_poll", "vor_ticket_times", "vor_set_tuning", "vor_get_tuning"):
+                  "vor_poll", "vor_ticket_times", "vor_set_tuning", "vor_get_tuning",
+                  "vor_filter_keys"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -301,6 +305,52 @@ def vor_get_tuning(ctx):
     _check(lib().vor_get_tuning(ctx, C.byref(t)), "vor_get_tuning")
     return (float(t.sites_per_bucket), int(t.block), int(t.block_halfwidth),
             int(t.leaf_halfwidth), int(t.scan_path))
+
+
+def vor_filter_keys(kind, nx, ny, c, dx, dy, device: int = 0):
+    """FP32 filter keys of single (line, ray) instances on the device (diagnostic entry).
+
+    kind/nx/ny/c: per-instance arrays (see include/vor.h); dx, dy: Python ints, the exact ray
+    direction (|.| < 2^100).  Returns (out [n, 8] float32, sigma [n] int32)."""
+    n = len(kind)
+    if not len(dx) == len(dy) == n:
+        raise ValueError("vor_filter_keys: per-instance arrays of different lengths")
+    M = (1 << 64) - 1
+
+    def split(v):
+        v = int(v)
+        hi = v >> 64                      # floor: the low word is the unsigned remainder
+        lo = v & M
+        return hi, lo - (1 << 64) if lo >= 1 << 63 else lo
+
+    d = np.zeros((n, 4), np.int64)
+    for i in range(n):
+        d[i, 0], d[i, 1] = split(dx[i])
+        d[i, 2], d[i, 3] = split(dy[i])
+    return vor_filter_keys_words(kind, nx, ny, c, d, device)
+
+
+def vor_filter_keys_words(kind, nx, ny, c, d, device: int = 0):
+    """Same as vor_filter_keys with the directions given as int64 words [n, 4]
+    (x_hi, x_lo, y_hi, y_lo), the layout of the C entry point."""
+    kind = np.ascontiguousarray(kind, np.int32)
+    nx = np.ascontiguousarray(nx, np.int32)
+    ny = np.ascontiguousarray(ny, np.int32)
+    c = np.ascontiguousarray(c, np.int64)
+    d = np.ascontiguousarray(d, np.int64).reshape(-1, 4)
+    n = kind.shape[0]
+    if not nx.shape == ny.shape == c.shape == (n,) or d.shape[0] != n:
+        raise ValueError("vor_filter_keys: per-instance arrays of different lengths")
+    out = np.zeros((n, 8), np.float32)
+    sigma = np.zeros(n, np.int32)
+    P = C.POINTER
+    _check(lib().vor_filter_keys(int(device), n, kind.ctypes.data_as(P(C.c_int32)),
+                                 nx.ctypes.data_as(P(C.c_int32)),
+                                 ny.ctypes.data_as(P(C.c_int32)),
+                                 c.ctypes.data_as(P(C.c_int64)), d.ctypes.data_as(P(C.c_int64)),
+                                 out.ctypes.data_as(P(C.c_float)),
+                                 sigma.ctypes.data_as(P(C.c_int32))), "vor_filter_keys")
+    return out, sigma
 
 
 class Context:
