@@ -75,7 +75,7 @@ struct HostBuf {   // pinned staging
 enum BufId {
     B_SETS, B_SETOFF, B_INX, B_INY, B_XYID, B_KEY, B_BCNT, B_BSTART, B_SXY, B_SID, B_OCNT,
     B_OLINES, B_OVF, B_POOL, B_QUEUE, B_QUEUE2, B_WBUF, B_WBUF2, B_CELLOFF, B_NBR, B_VTX,
-    B_DCNT, B_DELOFF, B_DEL, B_SCANTMP, B_SMALL, B_STATS, B_ECELL, B_TCHILD, B_NODES, B_TXY,
+    B_DCNT, B_DELOFF, B_DEL, B_SCANTMP, B_SMALL, B_STATS, B_TCHILD, B_NODES, B_TXY,
     B_TID, B_QUEUE3, B_TREF, B_NLIST, B_COUNT
 };
 
@@ -230,7 +230,7 @@ size_t footprint_bytes(uint64_t total, uint64_t gtot, bool vertices) {
     size_t b = 0;
     b += total * (4 + 4 + 8 + 4 + 8 + 4 + 4 + 4 + 4 + 4 + 4 + 4);   // inputs, grid, queues, counts
     b += total * 4ull * KOUT;                                       // filtered-pass lines
-    b += E * 4 * 3;                                                 // pool, nbr, owners
+    b += E * 4 * 2;                                                 // pool, nbr
     if (vertices) b += E * sizeof(vor_rat);
     b += (3 * total + 8) * 8;                                       // delaunay
     b += gtot * 16;                                                 // counts, starts, tree slots
@@ -295,7 +295,7 @@ int launch(vor_ctx *ctx, Workspace &ws, const std::vector<HostSet> &sets, bool v
         {B_CELLOFF, 4ull * (T + 1)}, {B_NBR, 4ull * E},
         {B_VTX, vertices ? sizeof(vor_rat) * E : 16}, {B_DCNT, 4ull * T},
         {B_DELOFF, 4ull * (T + 1)}, {B_DEL, 8ull * D}, {B_SCANTMP, 4ull * stmp},
-        {B_SMALL, 4ull * SMALL_INTS}, {B_STATS, 8ull * SL_COUNT}, {B_ECELL, 4ull * E}};
+        {B_SMALL, 4ull * SMALL_INTS}, {B_STATS, 8ull * SL_COUNT}};
     bool grew = false;
     for (auto &q : need) {
         const size_t before = ws.b[q.id].cap;
@@ -370,7 +370,6 @@ int launch(vor_ctx *ctx, Workspace &ws, const std::vector<HostSet> &sets, bool v
     a.exact_blocks = exact_blocks;
     a.cell_off = ws.b[B_CELLOFF].as<int>();
     a.nbr = ws.b[B_NBR].as<int>();
-    a.ecell = ws.b[B_ECELL].as<int>();
     a.nbr_cap = E;
     a.vtx = ws.b[B_VTX].p;
     a.dcnt = ws.b[B_DCNT].as<int>();

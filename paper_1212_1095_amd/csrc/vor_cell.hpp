@@ -810,10 +810,23 @@ struct GStack {
 };
 
 // Output sink: stores the line's label (local site index or side code).
+// Output of a cell walk: the lines as site ids (side codes unchanged), plus the count of
+// neighbours with a larger id than the cell's own (k), i.e. the cell's Delaunay edges (i, j),
+// i < j (Section 7).
 struct Sink {
     int *dst;
     const int *sid;
-    __device__ __forceinline__ void put(int m, int id) { dst[m] = id >= 0 ? sid[id] : id; }
+    int k;
+    int up = 0;
+    int lastup = 0;
+    __device__ __forceinline__ void put(int m, int id) {
+        const int v = id >= 0 ? sid[id] : id;
+        dst[m] = v;
+        lastup = v > k;
+        up += lastup;
+    }
+    // the last line closed the cycle (it is the first line again): not a new neighbour
+    __device__ __forceinline__ void drop_last() { up -= lastup; }
 };
 
 // ------------------------------------------------------------------------------ ray shots
@@ -909,7 +922,10 @@ __device__ __forceinline__ int cell_step(const Cell &C, const float2 *__restrict
         d = make_dir(phase == 1 ? 0 : (phase == 0 ? 7 : -7), phase == 1 ? 1 : -4);
     } else {
         if (st.depth == 0) {
-            if (w.m > 1 && w.last == w.first) --w.m;
+            if (w.m > 1 && w.last == w.first) {
+                --w.m;
+                sink.drop_last();
+            }
             return 1;
         }
         if (++w.nodes > NODE_LIMIT_FACTOR * (scap + ocap) + 64) return -3;

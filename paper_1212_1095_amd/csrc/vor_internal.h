@@ -41,7 +41,6 @@ struct PipeArgs {
     int exact_blocks;
     int *cell_off;          // [total + 1]
     int *nbr;
-    int *ecell;             // owner cell of each CSR entry [nbr_cap]
     long long nbr_cap;
     void *vtx;              // vor_rat [nbr_cap]
     int *dcnt, *del_off;    // [total], [total + 1]

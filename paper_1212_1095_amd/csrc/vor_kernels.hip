@@ -12,9 +12,9 @@
 //   adaptive  those cells again, scanning the refined buckets by coordinate rectangles
 //   exact     queued cells again with exact fallback (or every cell, exact-only precision)
 //   deep      cells deeper than the exact pass's per-worker capacity
-//   scan      line counts -> CSR offsets
-//   fill      canonical rotation, neighbour ids, pair-form vertices (Section 6)
-//   scan/del  Delaunay edges (i, j), i < j, sorted (Section 7)
+//   scans     line counts -> CSR offsets, Delaunay counts (from the cell passes) -> offsets
+//   emit      canonical rotation, neighbour ids, pair-form vertices (Section 6) and Delaunay
+//             edges (i, j), i < j, sorted (Section 7), one block per 256 consecutive cells
 //
 // Every kernel reads the device status word first and returns when an input error is set, so
 // the whole sequence can be launched (or replayed as a HIP graph) without host round trips.
@@ -365,8 +365,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5, 8))) v
     const SetDesc *__restrict__ sets, int nsets, const int *__restrict__ set_off,
     const float2 *__restrict__ sxy, const int *__restrict__ sid, const int *__restrict__ bstart,
     int total, int *__restrict__ ocnt, int *__restrict__ olines, int *__restrict__ ovf,
-    int *__restrict__ queue, int *__restrict__ qcount, int *__restrict__ queue3,
-    int *__restrict__ qcount3, unsigned long long *__restrict__ stats,
+    int *__restrict__ dcnt, int *__restrict__ queue, int *__restrict__ qcount,
+    int *__restrict__ queue3, int *__restrict__ qcount3, unsigned long long *__restrict__ stats,
     const int *__restrict__ status) {
     __shared__ int stk[SCAP][BLOCK];
     __shared__ int rlo[MAXROWS][BLOCK], rhi[MAXROWS][BLOCK];
@@ -380,14 +380,16 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5, 8))) v
     if (pos < total) {
         const SetDesc S = sets[find_set(set_off, nsets, pos)];
         const Cell C = make_cell(S, sxy[pos]);
-        const int g = S.site_off + sid[pos];
+        const int k = sid[pos];
+        const int g = S.site_off + k;
         LdsStack<BLOCK> st{stk, 0};
         GridScan<Solo, LdsRows<BLOCK>, true> sc{LdsRows<BLOCK>{rlo, rhi, 0}, bstart, false};
-        Sink sink{olines + (size_t)g * KOUT, sid};
+        Sink sink{olines + (size_t)g * KOUT, sid, k};
         const int r = run_cell<0, Solo>(C, sxy, sc, st, SCAP, sink, KOUT, K);
         ovf[g] = -1;
         if (r >= 0) {
             ocnt[g] = r;
+            dcnt[g] = sink.up;
             edges = (uint32_t)r;
         } else {
             ocnt[g] = -1;
@@ -411,8 +413,8 @@ __global__ __launch_bounds__(BLOCK) void k_cells_tree(
     const float2 *__restrict__ sxy, const int *__restrict__ sid, const int *__restrict__ tstart,
     const int *__restrict__ tchild, const TNode *__restrict__ nodes, const int *__restrict__ tref,
     int *__restrict__ ocnt,
-    int *__restrict__ olines, int *__restrict__ ovf, const int *__restrict__ queue3,
-    const int *__restrict__ qcount3,
+    int *__restrict__ olines, int *__restrict__ ovf, int *__restrict__ dcnt,
+    const int *__restrict__ queue3, const int *__restrict__ qcount3,
     int *__restrict__ queue, int *__restrict__ qcount, unsigned long long *__restrict__ stats,
     const int *__restrict__ status) {
     __shared__ int stk[SCAP][BLOCK];
@@ -430,18 +432,20 @@ __global__ __launch_bounds__(BLOCK) void k_cells_tree(
         const int pos = queue3[qi];
         const SetDesc S = sets[find_set(set_off, nsets, pos)];
         const Cell C = make_cell(S, sxy[pos]);
-        const int g = S.site_off + sid[pos];
+        const int k = sid[pos];
+        const int g = S.site_off + k;
         LdsStack<BLOCK> st{stk, 0};
         TreeScan<Solo, LdsFrames<BLOCK>, LdsList<BLOCK, TREE_LIST>> sc{
             Tree{tstart, tchild, nodes, tref}, LdsFrames<BLOCK>{fr},
             LdsList<BLOCK, TREE_LIST>{lst},
             Rect{}, false, Rect{}, 0, false};
-        Sink sink{olines + (size_t)g * KOUT, sid};
+        Sink sink{olines + (size_t)g * KOUT, sid, k};
         const int r = run_cell<0, Solo>(C, sxy, sc, st, SCAP, sink, KOUT, K);
         ++handled;
         if (r >= 0) {
             ovf[g] = -1;
             ocnt[g] = r;
+            dcnt[g] = sink.up;
             edges += (uint32_t)r;
         } else {
             queue[atomicAdd(qcount, 1)] = pos;
@@ -464,11 +468,13 @@ __global__ void k_queue_all(int total, int *__restrict__ queue, int *__restrict_
 // `area` (dcap entries each).
 template <int MODE, class Sc>
 __device__ __forceinline__ int coop_cell(const Cell &C, const float2 *__restrict__ sxy,
-                                         const int *__restrict__ sid, Sc &sc, int *area, int dcap,
-                                         Counters &K) {
+                                         const int *__restrict__ sid, int k, Sc &sc, int *area,
+                                         int dcap, Counters &K, int &up) {
     GStack st{area, 0};
-    Sink sink{area + dcap, sid};
-    return run_cell<MODE, Coop>(C, sxy, sc, st, dcap, sink, dcap, K);
+    Sink sink{area + dcap, sid, k};
+    const int r = run_cell<MODE, Coop>(C, sxy, sc, st, dcap, sink, dcap, K);
+    up = sink.up;
+    return r;
 }
 
 // Exact pass over a queue of cells: one wave per cell (the Coop policy), a persistent grid of
@@ -480,7 +486,7 @@ template <int MODE, int LCAP>
 __global__ __launch_bounds__(64) void k_cells_exact(
     const SetDesc *__restrict__ sets, int nsets, const int *__restrict__ set_off,
     const float2 *__restrict__ sxy, const int *__restrict__ sid, const int *__restrict__ bstart,
-    int *__restrict__ ocnt, int *__restrict__ olines,
+    int *__restrict__ ocnt, int *__restrict__ olines, int *__restrict__ dcnt,
     int *__restrict__ ovf, int *__restrict__ pool, int *__restrict__ poolcnt, long long poolcap,
     const int *__restrict__ queue, const int *__restrict__ qcount, int *__restrict__ queue2,
     int *__restrict__ qcount2, int *__restrict__ wbuf, int dcap,
@@ -501,9 +507,11 @@ __global__ __launch_bounds__(64) void k_cells_exact(
         const int pos = queue[qi];
         const SetDesc S = sets[find_set(set_off, nsets, pos)];
         const Cell C = make_cell(S, sxy[pos]);
-        const int g = S.site_off + sid[pos];
+        const int k = sid[pos];
+        const int g = S.site_off + k;
         GridScan<Coop, GlobalRows, false> sc{GlobalRows{0}, bstart, false};
-        const int r = coop_cell<MODE>(C, sxy, sid, sc, area, dcap, K);
+        int up = 0;
+        const int r = coop_cell<MODE>(C, sxy, sid, k, sc, area, dcap, K, up);
         if (r == -2) {
             if (lane == 0) {
                 if (queue2) queue2[atomicAdd(qcount2, 1)] = pos;
@@ -531,6 +539,7 @@ __global__ __launch_bounds__(64) void k_cells_exact(
         if (lane == 0) {
             ovf[g] = off;
             ocnt[g] = r;
+            dcnt[g] = up;
         }
     }
     // every lane ran the same control flow: count it once; evaluations are split across lanes
@@ -628,15 +637,14 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_apply(const int *__restrict
     }
 }
 
-// ------------------------------------------------------------------------------ CSR fill
-__device__ __forceinline__ void abs_line(const SetDesc &S, const int2 *__restrict__ xyid, int k,
-                                         int j, long long &nx, long long &ny, long long &c) {
-    // absolute coordinates: x = rel + x0
-    const long long px = (long long)xyid[S.site_off + k].x + S.x0;
-    const long long py = (long long)xyid[S.site_off + k].y + S.y0;
+// ------------------------------------------------------------------------------ output
+// Absolute line N.x <= c of neighbour j of the cell whose site is at relative p (site lines:
+// N = 2 (q - p), c = |q|^2 - |p|^2 with q the neighbour's site; sides: unit outward normal).
+__device__ __forceinline__ void abs_line(const SetDesc &S, int2 p, int j, int2 q, long long &nx,
+                                         long long &ny, long long &c) {
+    const long long px = (long long)p.x + S.x0, py = (long long)p.y + S.y0;
     if (j >= 0) {
-        const long long qx = (long long)xyid[S.site_off + j].x + S.x0;
-        const long long qy = (long long)xyid[S.site_off + j].y + S.y0;
+        const long long qx = (long long)q.x + S.x0, qy = (long long)q.y + S.y0;
         nx = 2 * (qx - px);
         ny = 2 * (qy - py);
         c = (qx * qx + qy * qy) - (px * px + py * py);
@@ -659,96 +667,186 @@ struct Rat {
     int64_t d;
 };
 
-// Per cell: canonical rotation, neighbour ids, the owner of every CSR entry, Delaunay count.
-__global__ void k_fill(const SetDesc *__restrict__ sets, int nsets, const int *__restrict__ set_off,
-                       int total, const int *__restrict__ ocnt, const int *__restrict__ olines,
-                       const int *__restrict__ ovf, const int *__restrict__ pool,
-                       const int *__restrict__ cell_off, long long cap, int *__restrict__ nbr,
-                       int *__restrict__ ecell, int *__restrict__ dcnt, int *__restrict__ status) {
-    if (*status) return;
-    const int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= total) return;
-    const int k = g - set_off[find_set(set_off, nsets, g)];
-    const int m = ocnt[g];
-    const long long base = cell_off[g];
-    if (m < 3 || base + m > cap) {
-        atomicOr(status, ST_INTERNAL);
-        return;
-    }
-    const int *src = ovf[g] >= 0 ? pool + ovf[g] : olines + (size_t)g * KOUT;
-    int r = 0;
-    for (int t = 1; t < m; ++t)
-        if ((uint32_t)src[t] < (uint32_t)src[r]) r = t;
-    int up = 0;
+// Vertex of lines 1 and 2 in pair form (X/D, Y/D), Cramer's rule.
+__device__ __forceinline__ Rat pair_vertex(const SetDesc &S, int2 p, int a, int2 qa, int b,
+                                           int2 qb) {
+    long long n1x, n1y, c1, n2x, n2y, c2;
+    abs_line(S, p, a, qa, n1x, n1y, c1);
+    abs_line(S, p, b, qb, n2x, n2y, c2);
+    const i128 X = (i128)c1 * n2y - (i128)c2 * n1y;
+    const i128 Y = (i128)n1x * c2 - (i128)n2x * c1;
+    Rat v;
+    v.x_lo = (uint64_t)X;
+    v.x_hi = (int64_t)(X >> 64);
+    v.y_lo = (uint64_t)Y;
+    v.y_hi = (int64_t)(Y >> 64);
+    v.d = n1x * n2y - n1y * n2x;
+    return v;
+}
+
+constexpr int EMIT_BLOCK = 256;   // cells per block (consecutive ids)
+constexpr int EMIT_ECAP = 2048;   // CSR entries staged per block (mean about 6 per cell)
+
+// Cell by cell (blocks whose entries exceed the LDS capacity: cells with very many edges).
+// Returns false, writing nothing, when the neighbours > k are not the dn the cell pass counted.
+template <bool VERT>
+__device__ bool emit_cell(const SetDesc &S, int so, int k, int2 p, const int *__restrict__ src,
+                          int m, int dn, long long base, long long dbase,
+                          const int2 *__restrict__ xyid, int *__restrict__ nbr,
+                          Rat *__restrict__ vtx, unsigned *__restrict__ del) {
+    int r = 0, up = 0;
     for (int t = 0; t < m; ++t) {
-        const int a = src[(r + t) % m];
-        nbr[base + t] = a;
-        ecell[base + t] = g;
-        up += a > k;
+        r = (uint32_t)src[t] < (uint32_t)src[r] ? t : r;
+        up += src[t] > k;
     }
-    dcnt[g] = up;
+    if (up != dn) return false;
+    for (int t = 0; t < m; ++t) nbr[base + t] = src[(r + t) % m];
+    if (VERT)
+        for (int t = 0; t < m; ++t) {
+            const int a = src[(r + t) % m], b = src[(r + t + 1) % m];
+            const int2 qa = a >= 0 ? xyid[so + a] : make_int2(0, 0);
+            const int2 qb = b >= 0 ? xyid[so + b] : make_int2(0, 0);
+            vtx[base + t] = pair_vertex(S, p, a, qa, b, qb);
+        }
+    for (int t = 0; t < m; ++t) {   // Delaunay pairs: rank of each neighbour > k
+        const int j = src[t];
+        if (j <= k) continue;
+        int rank = 0;
+        for (int u = 0; u < m; ++u) rank += src[u] > k && src[u] < j;
+        del[2 * (dbase + rank)] = (unsigned)k;
+        del[2 * (dbase + rank) + 1] = (unsigned)j;
+    }
+    return true;
 }
 
-// Per CSR entry (consecutive threads write consecutive 40-byte vertices): vertex i of cell k is
-// line(nbr[i]) ∩ line(nbr[i+1 cyclic]) in pair form, Cramer's rule on the absolute lines.
-__global__ void k_vertices(const SetDesc *__restrict__ sets, int nsets,
-                           const int *__restrict__ set_off, int total,
-                           const int *__restrict__ cell_off, const int *__restrict__ nbr,
-                           const int *__restrict__ ecell, const int2 *__restrict__ xyid,
-                           Rat *__restrict__ vtx, const int *__restrict__ status) {
-    if (*status) return;
-    const long long E = cell_off[total];
-    const long long stride = (long long)gridDim.x * blockDim.x;
-    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < E; e += stride) {
-        const int g = ecell[e];
-        const SetDesc S = sets[find_set(set_off, nsets, g)];
-        const int k = g - S.site_off;
-        const int lo = cell_off[g], hi = cell_off[g + 1];
-        const int a = nbr[e];
-        const int b = nbr[e + 1 == hi ? lo : e + 1];
-        long long n1x, n1y, c1, n2x, n2y, c2;
-        abs_line(S, xyid, k, a, n1x, n1y, c1);
-        abs_line(S, xyid, k, b, n2x, n2y, c2);
-        const long long D = n1x * n2y - n1y * n2x;
-        const i128 X = (i128)c1 * n2y - (i128)c2 * n1y;
-        const i128 Y = (i128)n1x * c2 - (i128)n2x * c1;
-        Rat v;
-        v.x_lo = (uint64_t)X;
-        v.x_hi = (int64_t)(X >> 64);
-        v.y_lo = (uint64_t)Y;
-        v.y_hi = (int64_t)(Y >> 64);
-        v.d = D;
-        vtx[e] = v;
+// Output of 256 consecutive cells: the canonical rotation of each cell's lines (the entry
+// smallest as uint32 first), the neighbour ids, the pair-form vertices (Section 6) and the
+// Delaunay pairs (k, j), k < j, ascending (Section 7).  The block's lines are read entry by
+// entry (consecutive threads, consecutive entries) into LDS; the rotation and the Delaunay
+// order are found there; each entry then writes its CSR slot, its vertex and its Delaunay pair.
+// A block whose entries exceed the LDS capacity works cell by cell instead.
+template <bool VERT>
+__global__ __launch_bounds__(EMIT_BLOCK) void k_emit(
+    const SetDesc *__restrict__ sets, int nsets, const int *__restrict__ set_off, int total,
+    const int *__restrict__ ocnt, const int *__restrict__ olines, const int *__restrict__ ovf,
+    const int *__restrict__ pool, const int *__restrict__ dcnt, const int *__restrict__ cell_off,
+    long long cap, const int *__restrict__ del_off, long long del_cap,
+    const int2 *__restrict__ xyid, int *__restrict__ nbr, Rat *__restrict__ vtx,
+    unsigned *__restrict__ del, int *__restrict__ status) {
+    __shared__ int lin[EMIT_ECAP];
+    __shared__ unsigned char own[EMIT_ECAP];
+    __shared__ int2 qc[VERT ? EMIT_ECAP : 1];
+    __shared__ int clo[EMIT_BLOCK + 1];
+    __shared__ const int *crow[EMIT_BLOCK];
+    __shared__ int cdl[EMIT_BLOCK];
+    __shared__ int crot[EMIT_BLOCK];
+    __shared__ int cset[EMIT_BLOCK];
+    __shared__ int2 pc[EMIT_BLOCK];
+    __shared__ int bad, stop;
+    const int tid = threadIdx.x;
+    const int g0 = blockIdx.x * EMIT_BLOCK;
+    const int nc = min(EMIT_BLOCK, total - g0);
+    const int g = g0 + tid;
+    const long long E0 = cell_off[g0], E1 = cell_off[g0 + nc];
+    const long long D0 = del_off[g0], D1 = del_off[g0 + nc];
+    const bool staged = E1 - E0 >= 0 && E1 - E0 <= EMIT_ECAP && D1 >= D0;
+    const int ne = staged ? (int)(E1 - E0) : 0;
+    if (tid == 0) {
+        stop = *status;   // one read, so that every wave of the block takes the same branch
+        bad = 0;
+        clo[nc] = ne;
     }
-}
-
-__global__ void k_delaunay(const SetDesc *__restrict__ sets, int nsets,
-                           const int *__restrict__ set_off, int total,
-                           const int *__restrict__ cell_off, const int *__restrict__ nbr,
-                           const int *__restrict__ del_off, unsigned *__restrict__ del,
-                           long long del_cap, int *__restrict__ status) {
-    if (*status) return;
-    const int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= total) return;
-    if ((long long)del_off[g + 1] > del_cap) {
-        atomicOr(status, ST_INTERNAL);
+    __syncthreads();
+    if (stop) return;
+    // per cell: offsets, checks, where its lines are
+    int s = 0, k = 0, m = 0, dn = 0;
+    long long base = 0, dbase = 0;
+    const int *src = nullptr;
+    int2 p = make_int2(0, 0);
+    if (tid < nc) {
+        s = find_set(set_off, nsets, g);
+        k = g - set_off[s];
+        m = ocnt[g];
+        base = cell_off[g];
+        dn = dcnt[g];
+        dbase = del_off[g];
+        const int of = ovf[g];
+        if (m < 3 || base + m > cap || cell_off[g + 1] != base + m || dn < 0 ||
+            dbase + dn > del_cap || del_off[g + 1] != dbase + dn || (of < 0 && m > KOUT) ||
+            (staged && (base < E0 || base + m > E1))) {
+            bad = 1;
+            m = 0;
+        } else {
+            src = of >= 0 ? pool + of : olines + (size_t)g * KOUT;
+            p = xyid[g];
+            if (staged) {
+                const int lo = (int)(base - E0);
+                clo[tid] = lo;
+                crow[tid] = src;
+                cdl[tid] = (int)(dbase - D0);
+                cset[tid] = s;
+                pc[tid] = p;
+                for (int t = 0; t < m; ++t) own[lo + t] = (unsigned char)tid;
+            }
+        }
+    }
+    __syncthreads();
+    if (bad) {
+        if (tid == 0) atomicOr(status, ST_INTERNAL);
         return;
     }
-    const int k = g - set_off[find_set(set_off, nsets, g)];
-    const int lo = cell_off[g], hi = cell_off[g + 1];
-    long long o = del_off[g];
-    int prev = k;
-    for (;;) {   // ascending neighbours > k (selection; cells are small)
-        int nxt = INT32_MAX;
-        for (int t = lo; t < hi; ++t) {
-            const int a = nbr[t];
-            if (a > prev && a < nxt) nxt = a;
+    if (!staged) {
+        if (tid < nc &&
+            !emit_cell<VERT>(sets[s], set_off[s], k, p, src, m, dn, base, dbase, xyid, nbr, vtx,
+                             del))
+            atomicOr(status, ST_INTERNAL);
+        return;
+    }
+    // per entry: the line, and the coordinates of its site
+    for (int e = tid; e < ne; e += EMIT_BLOCK) {
+        const int o = own[e];
+        const int j = crow[o][e - clo[o]];
+        lin[e] = j;
+        if (VERT) qc[e] = j >= 0 ? xyid[set_off[cset[o]] + j] : make_int2(0, 0);
+    }
+    __syncthreads();
+    // per cell: rotation, and the count of neighbours > k against the cell pass's count
+    if (tid < nc) {
+        const int lo = clo[tid];
+        int r = 0, up = 0;
+        for (int t = 0; t < m; ++t) {
+            const int a = lin[lo + t];
+            r = (uint32_t)a < (uint32_t)lin[lo + r] ? t : r;
+            up += a > k;
         }
-        if (nxt == INT32_MAX) break;
-        del[2 * o] = (unsigned)k;
-        del[2 * o + 1] = (unsigned)nxt;
-        ++o;
-        prev = nxt;
+        crot[tid] = r;
+        if (up != dn) bad = 1;
+    }
+    __syncthreads();
+    if (bad) {
+        if (tid == 0) atomicOr(status, ST_INTERNAL);
+        return;
+    }
+    // per entry (found order u): CSR slot (u - r) mod m, the vertex with the next line, and the
+    // Delaunay pair at the rank of j among the cell's neighbours > k
+    uint2 *__restrict__ del2 = reinterpret_cast<uint2 *>(del);
+    for (int e = tid; e < ne; e += EMIT_BLOCK) {
+        const int o = own[e];
+        const int lo = clo[o], mo = clo[o + 1] - lo, u = e - lo;
+        int t = u - crot[o];
+        t += t < 0 ? mo : 0;
+        const int j = lin[e];
+        nbr[E0 + lo + t] = j;
+        if (VERT) {
+            const int e2 = u + 1 == mo ? lo : e + 1;
+            vtx[E0 + lo + t] = pair_vertex(sets[cset[o]], pc[o], j, qc[e], lin[e2], qc[e2]);
+        }
+        const int ko = g0 + o - set_off[cset[o]];
+        if (j > ko) {
+            int rank = 0;
+            for (int v = lo; v < lo + mo; ++v) rank += lin[v] > ko && lin[v] < j;
+            del2[D0 + cdl[o] + rank] = make_uint2((unsigned)ko, (unsigned)j);
+        }
     }
 }
 
@@ -789,19 +887,21 @@ template <int BLOCK>
 static void launch_fast(const PipeArgs &a, hipStream_t st) {
     const unsigned nb = (nblk(a.total, BLOCK) + 7) & ~7u;
     k_cells_fast<BLOCK><<<nb, BLOCK, 0, st>>>(a.sets, a.nsets, a.set_off, a.sxy, a.sid, a.bstart,
-                                             a.total, a.ocnt, a.olines, a.ovf, a.queue,
-                                             a.qcount(), a.queue3, a.qcount3(), a.stats,
-                                             a.status());
+                                             a.total, a.ocnt, a.olines, a.ovf, a.dcnt,
+                                             a.queue, a.qcount(), a.queue3, a.qcount3(),
+                                             a.stats, a.status());
 }
 
 template <int MODE>
 static void launch_exact(const PipeArgs &a, hipStream_t st) {
     k_cells_exact<MODE, DCAP1><<<a.exact_blocks, 64, 0, st>>>(
-        a.sets, a.nsets, a.set_off, a.sxy, a.sid, a.bstart, a.ocnt, a.olines, a.ovf, a.pool, a.poolcnt(), a.poolcap, a.queue, a.qcount(), a.queue2,
+        a.sets, a.nsets, a.set_off, a.sxy, a.sid, a.bstart, a.ocnt, a.olines, a.dcnt, a.ovf,
+        a.pool, a.poolcnt(), a.poolcap, a.queue, a.qcount(), a.queue2,
         a.qcount2(), a.wbuf, DCAP1, a.stats, a.status_rw());
     // deep cells: few workers with a large area each
     k_cells_exact<MODE, 0><<<DEEP_BLOCKS, 64, 0, st>>>(
-        a.sets, a.nsets, a.set_off, a.sxy, a.sid, a.bstart, a.ocnt, a.olines, a.ovf, a.pool, a.poolcnt(), a.poolcap, a.queue2, a.qcount2(), nullptr,
+        a.sets, a.nsets, a.set_off, a.sxy, a.sid, a.bstart, a.ocnt, a.olines, a.dcnt, a.ovf,
+        a.pool, a.poolcnt(), a.poolcap, a.queue2, a.qcount2(), nullptr,
         nullptr,
         a.wbuf2, DCAP2, a.stats, a.status_rw());
 }
@@ -852,28 +952,26 @@ void launch_stage(const PipeArgs &a, hipStream_t st, int stage) {
                 1, std::min<long long>(nblk(T, TREE_PASS_BLOCK), 2048));
             k_cells_tree<TREE_PASS_BLOCK><<<nb, TREE_PASS_BLOCK, 0, st>>>(
                 a.sets, a.nsets, a.set_off, a.sxy, a.sid, a.bstart, a.tchild, a.nodes, a.tref,
-                a.ocnt, a.olines, a.ovf, a.queue3, a.qcount3(), a.queue, a.qcount(), a.stats,
-                a.status());
+                a.ocnt, a.olines, a.ovf, a.dcnt, a.queue3, a.qcount3(), a.queue, a.qcount(),
+                a.stats, a.status());
         }
     } else if (stage == 3) {
         if (a.exact_only) launch_exact<2>(a, st);
         else launch_exact<1>(a, st);
     } else {
-        // CSR, vertices, Delaunay edges
+        // CSR offsets and Delaunay offsets, then neighbours, vertices and Delaunay pairs
         launch_scan(a.ocnt, T, a.cell_off, a.scan_tmp, a.status(), 1, st);
-        k_fill<<<nblk(T, 256), 256, 0, st>>>(a.sets, a.nsets, a.set_off, T, a.ocnt, a.olines,
-                                              a.ovf, a.pool, a.cell_off, a.nbr_cap, a.nbr,
-                                              a.ecell, a.dcnt, a.status_rw());
-        if (a.with_vertices) {
-            const long long cap = a.nbr_cap;
-            const unsigned nb = (unsigned)std::min<long long>(nblk(cap, 256), 8192);
-            k_vertices<<<nb, 256, 0, st>>>(a.sets, a.nsets, a.set_off, T, a.cell_off, a.nbr,
-                                           a.ecell, a.xyid, (Rat *)a.vtx, a.status());
-        }
         launch_scan(a.dcnt, T, a.del_off, a.scan_tmp, a.status(), 1, st);
-        k_delaunay<<<nblk(T, 256), 256, 0, st>>>(a.sets, a.nsets, a.set_off, T, a.cell_off,
-                                                  a.nbr, a.del_off, a.del, a.del_cap,
-                                                  a.status_rw());
+        if (a.with_vertices)
+            k_emit<true><<<nblk(T, EMIT_BLOCK), EMIT_BLOCK, 0, st>>>(
+                a.sets, a.nsets, a.set_off, T, a.ocnt, a.olines, a.ovf, a.pool, a.dcnt,
+                a.cell_off, a.nbr_cap, a.del_off, a.del_cap, a.xyid, a.nbr, (Rat *)a.vtx, a.del,
+                a.status_rw());
+        else
+            k_emit<false><<<nblk(T, EMIT_BLOCK), EMIT_BLOCK, 0, st>>>(
+                a.sets, a.nsets, a.set_off, T, a.ocnt, a.olines, a.ovf, a.pool, a.dcnt,
+                a.cell_off, a.nbr_cap, a.del_off, a.del_cap, a.xyid, a.nbr, nullptr, a.del,
+                a.status_rw());
         if (a.check_symmetry)
             k_symmetry<<<nblk(T, 256), 256, 0, st>>>(a.sets, a.nsets, a.set_off, T, a.cell_off,
                                                       a.nbr, a.stats, a.status());

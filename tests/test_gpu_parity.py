@@ -77,6 +77,25 @@ def test_twelve_cocircular(ctx):
     assert r.dele.shape[0] == 12
 
 
+@pytest.mark.parametrize("ring", [40, 300, 3000])
+def test_hub_cell_with_many_edges(ctx, ring):
+    """A site at the centre of `ring` sites on a circle: its cell has one edge per ring site.
+    40 edges exceed the filtered pass's 24 line slots (the cell moves to the exact pass and its
+    lines to the overflow pool), 300 exceed the exact pass's 128 (deep pass), 3000 exceed the
+    2048 entries that the output kernel stages per block of 256 cells."""
+    R, c = 1 << 20, 1 << 21
+    ang = 2 * np.pi * (np.arange(ring) + 0.25) / ring
+    x = np.concatenate([[c], np.rint(c + R * np.cos(ang))]).astype(np.int32)
+    y = np.concatenate([[c], np.rint(c + R * np.sin(ang))]).astype(np.int32)
+    order = np.random.default_rng(ring).permutation(ring + 1)   # the hub at a random id
+    ps = sitegen.PointSet(x[order], y[order], (0, 0, 1 << 22, 1 << 22))
+    r = run(ctx, ps, f"hub with {ring} ring sites")
+    hub = int(np.flatnonzero(order == 0)[0])
+    assert len(r.lines(hub)) == ring
+    assert_matches_oracle(r, ps)
+    assert symmetric(r)
+
+
 @pytest.mark.parametrize("k", [1, 2, 7, 16])
 def test_perfect_lattice(ctx, k):
     h = 64
