@@ -96,6 +96,26 @@ def test_hub_cell_with_many_edges(ctx, ring):
     assert symmetric(r)
 
 
+@pytest.mark.parametrize("name", ["jittered lattice", "dense small box", "perfect lattice"])
+def test_near_ties_in_the_filtered_pass(ctx, name):
+    """Sets above the small-set threshold (the one-lane-per-cell pass runs) full of near-ties
+    and exact ties: the FP32 filter leaves rays undecided and those cells reach the exact pass."""
+    if name == "jittered lattice":
+        ps = sitegen.lattice(30000, 176 * 1024, seed=44)   # the lattice fills the box
+    elif name == "dense small box":
+        ps = sitegen.uniform(30000, 1 << 9, seed=45)
+    else:
+        k, h = 180, 256
+        ii, jj = np.meshgrid(np.arange(k), np.arange(k), indexing="xy")
+        ps = sitegen.PointSet((h // 2 + h * ii.ravel()).astype(np.int32),
+                              (h // 2 + h * jj.ravel()).astype(np.int32), (0, 0, k * h, k * h))
+    r = run(ctx, ps, f"{name} n={ps.n}")
+    assert_matches_oracle(r, ps)
+    assert symmetric(r)
+    if ctx.mode == "filtered":
+        assert r.stats.deferred_cells > 0
+
+
 @pytest.mark.parametrize("k", [1, 2, 7, 16])
 def test_perfect_lattice(ctx, k):
     h = 64
