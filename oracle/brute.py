@@ -13,21 +13,29 @@ from __future__ import annotations
 from fractions import Fraction as F
 from itertools import combinations
 
+from . import region as _region
 
-def _candidates(x, y, box):
-    x0, y0, x1, y1 = box
-    pts = {(F(x0), F(y0)), (F(x1), F(y0)), (F(x1), F(y1)), (F(x0), F(y1))}
+
+def _meet(l1, l2):
+    """Intersection of two lines N.v = c, or None when parallel."""
+    (ax, ay, ac), (bx, by, bc) = l1, l2
+    d = ax * by - ay * bx
+    if d == 0:
+        return None
+    return (F(ac * by - bc * ay, d), F(ax * bc - bx * ac, d))
+
+
+def _candidates(x, y, sides, corners):
+    pts = {(F(a), F(b)) for a, b in corners}
     n = len(x)
-    # bisector of (i, j) meets the four side lines
+    # bisector of (i, j) meets every side line
     for i, j in combinations(range(n), 2):
-        nx, ny = 2 * (x[j] - x[i]), 2 * (y[j] - y[i])
-        c = (x[j] ** 2 + y[j] ** 2) - (x[i] ** 2 + y[i] ** 2)
-        for yy in (y0, y1):
-            if nx != 0:
-                pts.add((F(c - ny * yy, nx), F(yy)))
-        for xx in (x0, x1):
-            if ny != 0:
-                pts.add((F(xx), F(c - nx * xx, ny)))
+        bis = (2 * (x[j] - x[i]), 2 * (y[j] - y[i]),
+               (x[j] ** 2 + y[j] ** 2) - (x[i] ** 2 + y[i] ** 2))
+        for sl in sides:
+            p = _meet(bis, sl)
+            if p is not None:
+                pts.add(p)
     # circumcentres of non-collinear triples
     for i, j, k in combinations(range(n), 3):
         ax, ay, bx, by, cx, cy = x[i], y[i], x[j], y[j], x[k], y[k]
@@ -38,7 +46,7 @@ def _candidates(x, y, box):
         ux = F(a2 * (by - cy) + b2 * (cy - ay) + c2 * (ay - by), d)
         uy = F(a2 * (cx - bx) + b2 * (ax - cx) + c2 * (bx - ax), d)
         pts.add((ux, uy))
-    return [p for p in pts if x0 <= p[0] <= x1 and y0 <= p[1] <= y1]
+    return [p for p in pts if _region.contains(sides, p[0], p[1])]
 
 
 def _hull(points):
@@ -62,13 +70,14 @@ def _hull(points):
     return lower[:-1] + upper[:-1]
 
 
-def diagram(x, y, box):
-    """List of CCW label lists (not rotated) per site, plus the hull vertices per site."""
+def diagram(x, y, box, region=None):
+    """List of CCW label lists (not rotated) per site, plus the hull vertices per site.  X is the
+    box, or the convex polygon region = (vx, vy) when given."""
     x = [int(v) for v in x]
     y = [int(v) for v in y]
-    x0, y0, x1, y1 = box
+    sides = _region.side_lines(box, region)
     n = len(x)
-    cand = _candidates(x, y, box)
+    cand = _candidates(x, y, sides, _region.vertices(box, region))
     near = []
     for p in cand:
         d = [(p[0] - x[i]) ** 2 + (p[1] - y[i]) ** 2 for i in range(n)]
@@ -81,14 +90,9 @@ def diagram(x, y, box):
         labels = []
         for a, b in zip(h, h[1:] + h[:1]):
             lab = []
-            if a[1] == y0 and b[1] == y0:
-                lab.append(-1)
-            if a[0] == x1 and b[0] == x1:
-                lab.append(-2)
-            if a[1] == y1 and b[1] == y1:
-                lab.append(-3)
-            if a[0] == x0 and b[0] == x0:
-                lab.append(-4)
+            for e, (nx, ny, c) in enumerate(sides):
+                if nx * a[0] + ny * a[1] == c and nx * b[0] + ny * b[1] == c:
+                    lab.append(-(e + 1))
             for j in range(n):
                 if j == k:
                     continue

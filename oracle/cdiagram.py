@@ -2,7 +2,7 @@
 
 Implements the plain definition (Section 2, Definition of the Voronoi diagram): each cell is
 X intersected with the n-1 bisector half-planes.  Output conventions follow Section 6 (lines
-named by neighbour index, box sides -1..-4) and Section 7 (Delaunay edges = neighbours via an
+named by neighbour index, box sides -1..-4, sides of a convex polygon X -1..-K) and Section 7 (Delaunay edges = neighbours via an
 edge, restricted to X).
 """
 from __future__ import annotations
@@ -39,6 +39,17 @@ def lib():
                                           [C.c_int32, i32p, i32p, i32p,
                                            C.POINTER(C.c_uint64), C.POINTER(C.c_uint64),
                                            C.POINTER(C.c_int64)])
+        L.vor_oracle_validate_poly.restype = C.c_int
+        L.vor_oracle_validate_poly.argtypes = [C.c_int32, i32p, i32p, C.c_int32, i32p, i32p]
+        L.vor_oracle_cells_poly.restype = C.c_int64
+        L.vor_oracle_cells_poly.argtypes = ([C.c_int32, i32p, i32p, C.c_int32, i32p, i32p] +
+                                            [C.c_int32, i32p, C.c_int32, i32p, C.c_int64, i32p,
+                                             C.POINTER(C.c_int64)])
+        L.vor_oracle_vertices_poly.restype = C.c_int
+        L.vor_oracle_vertices_poly.argtypes = ([C.c_int32, i32p, i32p, C.c_int32, i32p, i32p] +
+                                               [C.c_int32, i32p, i32p, i32p,
+                                                C.POINTER(C.c_uint64), C.POINTER(C.c_uint64),
+                                                C.POINTER(C.c_int64)])
         L.vor_oracle_default_threads.restype = C.c_int32
         L.vor_oracle_default_threads.argtypes = []
         _lib = L
@@ -53,9 +64,20 @@ def default_threads() -> int:
     return int(lib().vor_oracle_default_threads())
 
 
-def validate(x, y, box) -> int:
+def _region_args(region):
+    vx = np.ascontiguousarray(region[0], dtype=np.int32)
+    vy = np.ascontiguousarray(region[1], dtype=np.int32)
+    return vx, vy, (vx.shape[0], _p(vx, C.c_int32), _p(vy, C.c_int32))
+
+
+def validate(x, y, box, region=None) -> int:
+    """0, or the oracle's error code; X is the box, or the convex polygon region = (vx, vy)."""
     x = np.ascontiguousarray(x, dtype=np.int32)
     y = np.ascontiguousarray(y, dtype=np.int32)
+    if region is not None:
+        vx, vy, ra = _region_args(region)
+        return int(lib().vor_oracle_validate_poly(x.shape[0], _p(x, C.c_int32),
+                                                  _p(y, C.c_int32), *ra))
     return int(lib().vor_oracle_validate(x.shape[0], _p(x, C.c_int32), _p(y, C.c_int32), *box))
 
 
@@ -73,7 +95,10 @@ class Cells:
         return self.nbr[self.off[i]:self.off[i + 1]].tolist()
 
 
-def cells(x, y, box, which=None, threads: int | None = None, vertices: bool = True) -> Cells:
+def cells(x, y, box, which=None, threads: int | None = None, vertices: bool = True,
+          region=None) -> Cells:
+    """Cells of the listed sites (all by default).  X is the box, or, when region = (vx, vy) is
+    given, that convex polygon (counter-clockwise; sides named -1, -2, ...)."""
     x = np.ascontiguousarray(x, dtype=np.int32)
     y = np.ascontiguousarray(y, dtype=np.int32)
     n = x.shape[0]
@@ -86,12 +111,20 @@ def cells(x, y, box, which=None, threads: int | None = None, vertices: bool = Tr
         threads = default_threads()
     cap = max(16, 12 * m)
     needed = C.c_int64(0)
-    for _ in range(3):
+    for attempt in range(3):
         buf = np.zeros(cap, dtype=np.int32)
-        r = lib().vor_oracle_cells(n, _p(x, C.c_int32), _p(y, C.c_int32), *box, m,
-                                   _p(which, C.c_int32), int(threads), _p(counts, C.c_int32),
-                                   cap, _p(buf, C.c_int32), C.byref(needed))
-        if r == -4:
+        if region is not None:
+            vx, vy, ra = _region_args(region)
+            r = lib().vor_oracle_cells_poly(n, _p(x, C.c_int32), _p(y, C.c_int32), *ra, m,
+                                            _p(which, C.c_int32), int(threads),
+                                            _p(counts, C.c_int32), cap, _p(buf, C.c_int32),
+                                            C.byref(needed))
+        else:
+            r = lib().vor_oracle_cells(n, _p(x, C.c_int32), _p(y, C.c_int32), *box, m,
+                                       _p(which, C.c_int32), int(threads),
+                                       _p(counts, C.c_int32), cap, _p(buf, C.c_int32),
+                                       C.byref(needed))
+        if r == -4 and attempt < 2 and int(needed.value) + 16 > cap:
             cap = int(needed.value) + 16
             continue
         if r < 0:
@@ -107,10 +140,14 @@ def cells(x, y, box, which=None, threads: int | None = None, vertices: bool = Tr
         X2 = np.zeros(2 * max(tot, 1), dtype=np.uint64)
         Y2 = np.zeros(2 * max(tot, 1), dtype=np.uint64)
         D = np.zeros(max(tot, 1), dtype=np.int64)
-        r = lib().vor_oracle_vertices(n, _p(x, C.c_int32), _p(y, C.c_int32), *box, m,
-                                      _p(which, C.c_int32), _p(counts, C.c_int32),
-                                      _p(nbr, C.c_int32), _p(X2, C.c_uint64),
-                                      _p(Y2, C.c_uint64), _p(D, C.c_int64))
+        tail = (m, _p(which, C.c_int32), _p(counts, C.c_int32), _p(nbr, C.c_int32),
+                _p(X2, C.c_uint64), _p(Y2, C.c_uint64), _p(D, C.c_int64))
+        if region is not None:
+            vx, vy, ra = _region_args(region)
+            r = lib().vor_oracle_vertices_poly(n, _p(x, C.c_int32), _p(y, C.c_int32), *ra,
+                                               *tail)
+        else:
+            r = lib().vor_oracle_vertices(n, _p(x, C.c_int32), _p(y, C.c_int32), *box, *tail)
         if r != 0:
             raise ValueError("oracle vertex error")
         out.vx = limbs_to_int(X2[:2 * tot])

@@ -1,4 +1,5 @@
-"""Invariant checkers for a Voronoi diagram restricted to a box -- TEST INFRASTRUCTURE ONLY.
+"""Invariant checkers for a Voronoi diagram restricted to a box or a convex polygon X -- TEST
+INFRASTRUCTURE ONLY.
 
 Every output of the oracle and of the GPU path can be run through these.  They check what the
 mathematics fixes, independent of how the diagram was computed:
@@ -16,21 +17,21 @@ from __future__ import annotations
 from fractions import Fraction as F
 from math import gcd
 
+from . import region as _region
 
-def line(x, y, box, k, j):
+
+def line(x, y, box, k, j, region=None):
     """(Nx, Ny, c) of the line with label j in the cell of k, absolute coordinates."""
-    x0, y0, x1, y1 = box
     if j >= 0:
         return (2 * (int(x[j]) - int(x[k])), 2 * (int(y[j]) - int(y[k])),
                 (int(x[j]) ** 2 + int(y[j]) ** 2) - (int(x[k]) ** 2 + int(y[k]) ** 2))
-    return {-1: (0, -1, -int(y0)), -2: (1, 0, int(x1)), -3: (0, 1, int(y1)),
-            -4: (-1, 0, -int(x0))}[int(j)]
+    return _region.side_lines(box, region)[-int(j) - 1]
 
 
-def pair_form(x, y, box, k, a, b):
+def pair_form(x, y, box, k, a, b, region=None):
     """Intersection of lines a and b of cell k by Cramer's rule: (X, Y, D), point = (X/D, Y/D)."""
-    n1x, n1y, c1 = line(x, y, box, k, a)
-    n2x, n2y, c2 = line(x, y, box, k, b)
+    n1x, n1y, c1 = line(x, y, box, k, a, region)
+    n2x, n2y, c2 = line(x, y, box, k, b, region)
     D = n1x * n2y - n1y * n2x
     X = c1 * n2y - c2 * n1y
     Y = n1x * c2 - n2x * c1
@@ -55,10 +56,10 @@ def check_symmetry(cells):
     return True
 
 
-def check_cell_vertices(x, y, box, cells, every_site=True):
+def check_cell_vertices(x, y, box, cells, every_site=True, region=None):
     """Convexity, equidistance and emptiness of every vertex; returns the reduced vertices."""
     n = len(x)
-    x0, y0, x1, y1 = box
+    sides = _region.side_lines(box, region)
     out = []
     for k, ids in enumerate(cells):
         m = len(ids)
@@ -67,10 +68,10 @@ def check_cell_vertices(x, y, box, cells, every_site=True):
         vs = []
         for t in range(m):
             a, b = ids[t], ids[(t + 1) % m]
-            X, Y, D = pair_form(x, y, box, k, a, b)
+            X, Y, D = pair_form(x, y, box, k, a, b, region)
             assert D > 0, f"cell {k}: lines {a},{b} do not turn CCW"
             vx, vy = F(X, D), F(Y, D)
-            assert x0 <= vx <= x1 and y0 <= vy <= y1
+            assert _region.contains(sides, vx, vy)
             dk = (vx - int(x[k])) ** 2 + (vy - int(y[k])) ** 2
             for j in (a, b):
                 if j >= 0:
@@ -84,14 +85,13 @@ def check_cell_vertices(x, y, box, cells, every_site=True):
     return out
 
 
-def check_area(x, y, box, cells):
-    x0, y0, x1, y1 = box
+def check_area(x, y, box, cells, region=None):
     total = F(0)
     for k, ids in enumerate(cells):
         m = len(ids)
         pts = []
         for t in range(m):
-            X, Y, D = pair_form(x, y, box, k, ids[t], ids[(t + 1) % m])
+            X, Y, D = pair_form(x, y, box, k, ids[t], ids[(t + 1) % m], region)
             pts.append((F(X, D), F(Y, D)))
         a = F(0)
         for t in range(m):
@@ -99,7 +99,7 @@ def check_area(x, y, box, cells):
             a += ax * by - ay * bx
         assert a > 0, f"cell {k} has non-positive area"
         total += a / 2
-    assert total == (x1 - x0) * (y1 - y0), f"areas sum to {total}"
+    assert total == _region.area(box, region), f"areas sum to {total}"
     return True
 
 
@@ -134,10 +134,10 @@ def check_delaunay_count(cells, reduced_vertices):
     return True
 
 
-def check_all(x, y, box, cells, every_site=True):
+def check_all(x, y, box, cells, every_site=True, region=None):
     check_symmetry(cells)
-    rv = check_cell_vertices(x, y, box, cells, every_site)
-    check_area(x, y, box, cells)
+    rv = check_cell_vertices(x, y, box, cells, every_site, region)
+    check_area(x, y, box, cells, region)
     check_euler(cells, rv)
     check_delaunay_count(cells, rv)
     return True

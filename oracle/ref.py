@@ -10,28 +10,26 @@ from __future__ import annotations
 
 from fractions import Fraction as F
 
-
-def _line(x, y, box, k, j):
-    """(Nx, Ny, c) of the closed half-plane N.v <= c bounding the cell of site k."""
-    x0, y0, x1, y1 = box
-    if j >= 0:
-        return (2 * (x[j] - x[k]), 2 * (y[j] - y[k]),
-                (x[j] ** 2 + y[j] ** 2) - (x[k] ** 2 + y[k] ** 2))
-    return {-1: (0, -1, -y0), -2: (1, 0, x1), -3: (0, 1, y1), -4: (-1, 0, -x0)}[j]
+from . import region as _region
 
 
-def cell(x, y, box, k):
-    """Counter-clockwise list of line labels of the cell of site k (not rotated)."""
+def _line(x, y, k, j):
+    """(Nx, Ny, c) of the closed bisector half-plane N.v <= c bounding the cell of site k."""
+    return (2 * (x[j] - x[k]), 2 * (y[j] - y[k]),
+            (x[j] ** 2 + y[j] ** 2) - (x[k] ** 2 + y[k] ** 2))
+
+
+def cell(x, y, box, k, region=None):
+    """Counter-clockwise list of line labels of the cell of site k (not rotated).  X is the box,
+    or the convex polygon region = (vx, vy) when given."""
     x = [int(v) for v in x]
     y = [int(v) for v in y]
-    x0, y0, x1, y1 = box
-    # vertices CCW from the bottom-left corner; label = line of the edge leaving the vertex
-    poly = [((F(x0), F(y0)), -1), ((F(x1), F(y0)), -2), ((F(x1), F(y1)), -3),
-            ((F(x0), F(y1)), -4)]
+    # vertices of X counter-clockwise; label = line of the edge leaving the vertex
+    poly = [((F(a), F(b)), -(e + 1)) for e, (a, b) in enumerate(_region.vertices(box, region))]
     for j in range(len(x)):
         if j == k:
             continue
-        nx, ny, c = _line(x, y, box, k, j)
+        nx, ny, c = _line(x, y, k, j)
         f = [c - (nx * v[0] + ny * v[1]) for v, _ in poly]
         if all(fv >= 0 for fv in f):
             continue
@@ -58,6 +56,6 @@ def rotate_canonical(ids):
     return ids[i:] + ids[:i]
 
 
-def diagram(x, y, box):
+def diagram(x, y, box, region=None):
     """All cells, canonically rotated: list of label lists."""
-    return [rotate_canonical(cell(x, y, box, k)[0]) for k in range(len(x))]
+    return [rotate_canonical(cell(x, y, box, k, region)[0]) for k in range(len(x))]

@@ -15,4 +15,7 @@ from .generators import (  # noqa: F401
     batch_sets,
     request_stream,
     small_integer_set,
+    convex_polygon,
+    inside_polygon,
+    in_polygon,
 )

@@ -25,6 +25,7 @@ class PointSet:
     kind: str = "uniform"
     seed: int = 0
     meta: dict = field(default_factory=dict)
+    region: tuple | None = None   # (vx, vy) int32: X is this convex polygon (box = its bbox)
 
     @property
     def n(self) -> int:
@@ -175,3 +176,88 @@ def small_integer_set(n: int, coord_max: int, seed: int, box_pad: int = 1) -> Po
 
     x, y = _redraw_until_distinct(x, y, draw, lo, coord_max)
     return PointSet(x.astype(np.int32), y.astype(np.int32), (0, 0, B, B), "small", seed)
+
+
+def convex_polygon(K: int, B: int = 1 << 20, seed: int = 7, origin: int = 0) -> tuple:
+    """A strictly convex polygon with at most K integer vertices, counter-clockwise, inside
+    [origin, origin + B]^2: K sorted random angles on an ellipse of random axes, rounded, then
+    the convex hull with collinear points dropped.  Returns (vx, vy) int32 arrays."""
+    rng = _rng(seed)
+    ang = np.sort(rng.uniform(0.0, 2.0 * np.pi, size=K))
+    ax, ay = rng.uniform(0.3, 0.5, size=2) * B
+    cx, cy = origin + B / 2, origin + B / 2
+    px = np.rint(cx + ax * np.cos(ang)).astype(np.int64)
+    py = np.rint(cy + ay * np.sin(ang)).astype(np.int64)
+    pts = sorted(set(zip(px.tolist(), py.tolist())))
+
+    def cross(o, a, b):
+        return (a[0] - o[0]) * (b[1] - o[1]) - (a[1] - o[1]) * (b[0] - o[0])
+
+    lower, upper = [], []
+    for p in pts:
+        while len(lower) >= 2 and cross(lower[-2], lower[-1], p) <= 0:
+            lower.pop()
+        lower.append(p)
+    for p in reversed(pts):
+        while len(upper) >= 2 and cross(upper[-2], upper[-1], p) <= 0:
+            upper.pop()
+        upper.append(p)
+    hull = lower[:-1] + upper[:-1]
+    if len(hull) < 3:
+        raise ValueError("degenerate polygon")
+    return (np.array([p[0] for p in hull], np.int32), np.array([p[1] for p in hull], np.int32))
+
+
+def inside_polygon(region, px: np.ndarray, py: np.ndarray) -> np.ndarray:
+    """Strictly inside the counter-clockwise convex polygon: strictly left of every edge."""
+    vx = np.asarray(region[0], np.int64)
+    vy = np.asarray(region[1], np.int64)
+    ok = np.ones(px.shape[0], dtype=bool)
+    for e in range(vx.shape[0]):
+        f = (e + 1) % vx.shape[0]
+        ok &= (vx[f] - vx[e]) * (py - vy[e]) - (vy[f] - vy[e]) * (px - vx[e]) > 0
+    return ok
+
+
+def in_polygon(n: int, region, seed: int = 1, kind: str = "uniform") -> PointSet:
+    """n distinct sites strictly inside the convex polygon region = (vx, vy): uniform over the
+    polygon, or clustered (90% from 8 Gaussians with centres inside, sigma 1/64 of the extent,
+    10% uniform).  The box is the polygon's bounding box."""
+    rng = _rng(seed)
+    vx = np.asarray(region[0], np.int64)
+    vy = np.asarray(region[1], np.int64)
+    x0, x1, y0, y1 = int(vx.min()), int(vx.max()), int(vy.min()), int(vy.max())
+    ext = max(x1 - x0, y1 - y0)
+    centres = []
+    while kind == "clustered" and len(centres) < 8:
+        c = rng.integers([x0, y0], [x1 + 1, y1 + 1], size=(1, 2))
+        if inside_polygon(region, c[:, 0], c[:, 1])[0]:
+            centres.append(c[0])
+
+    def draw(m):
+        if kind == "clustered":
+            u = rng.random(m) < 0.1
+            k = rng.integers(0, len(centres), size=m)
+            g = np.array(centres)[k] + rng.normal(0.0, ext / 64.0, size=(m, 2))
+            b = rng.integers([x0, y0], [x1 + 1, y1 + 1], size=(m, 2))
+            p = np.where(u[:, None], b, np.rint(g)).astype(np.int64)
+        else:
+            p = rng.integers([x0, y0], [x1 + 1, y1 + 1], size=(m, 2))
+        return p[:, 0], p[:, 1]
+
+    xs = np.zeros(0, np.int64)
+    ys = np.zeros(0, np.int64)
+    for _ in range(1000):
+        if xs.shape[0] >= n:
+            break
+        px, py = draw(2 * (n - xs.shape[0]) + 16)
+        keep = inside_polygon(region, px, py)
+        xs = np.concatenate([xs, px[keep]])
+        ys = np.concatenate([ys, py[keep]])
+        first = _first_occurrence_mask(xs, ys)
+        xs, ys = xs[first], ys[first]
+    if xs.shape[0] < n:
+        raise ValueError("the polygon holds fewer distinct interior points than requested")
+    xs, ys = xs[:n], ys[:n]
+    return PointSet(xs.astype(np.int32), ys.astype(np.int32), (x0, y0, x1, y1), kind, seed,
+                    region=(vx.astype(np.int32), vy.astype(np.int32)))
