@@ -12,7 +12,8 @@
  * thread-safe; vor_compute and vor_compute_batch serialise per context.
  *
  * Coordinates: int32, |coordinate| <= 2^30, box extent x1-x0 and y1-y0 at most 2^24.
- * Sites must lie strictly inside X (x0 < x < x1, y0 < y < y1) and be pairwise distinct
+ * X is the box, or a convex polygon given with the set (Remark 11.1 on a general convex X).
+ * Sites must lie strictly inside X (x0 < x < x1, y0 < y < y1 for the box) and be pairwise distinct
  * (problem statement in Section 2; a duplicate is an error, never silently dropped, since
  * dropping it would renumber the sites).
  */
@@ -41,6 +42,11 @@ extern "C" {
 #define VOR_SIDE_RIGHT (-2)    /* x = x1 */
 #define VOR_SIDE_TOP (-3)      /* y = y1 */
 #define VOR_SIDE_LEFT (-4)     /* x = x0 */
+/* Convex polygon X with vertices v_0..v_{K-1} (counter-clockwise): side e runs from v_e to
+ * v_{e+1 mod K} and is named -(e+1); its line is N.x <= N.v_e with N = (dy, -dx) / gcd(|dx|, |dy|)
+ * for (dx, dy) = v_{e+1} - v_e (the primitive outward normal).  The box is the polygon
+ * (x0,y0), (x1,y0), (x1,y1), (x0,y1): the codes above with the same lines. */
+#define VOR_MAX_SIDES 256
 
 /* ---- flags ------------------------------------------------------------------------------ */
 #define VOR_SET_DEVICE 0x1u       /* vor_set.x / .y are device pointers (HBM-resident input)  */
@@ -57,13 +63,19 @@ typedef struct {
 } vor_box;
 
 /* One point set in structure-of-arrays form.  Borrowed for the duration of vor_compute*,
- * copied by vor_submit. */
+ * copied by vor_submit.  With nregion = 0, X is `box`.  With 3 <= nregion <= VOR_MAX_SIDES, X is
+ * the convex polygon (region_x[i], region_y[i]) (host memory, counter-clockwise, strictly convex:
+ * every turn strictly left, the boundary going round once; VOR_E_INVAL otherwise) and `box` is
+ * ignored (the polygon's bounding box, extent at most 2^24, takes its place). */
 typedef struct {
     uint32_t n;
     const int32_t *x;
     const int32_t *y;
     vor_box box;
     uint32_t flags;               /* VOR_SET_DEVICE */
+    uint32_t nregion;             /* 0, or the number of vertices of a convex polygon X */
+    const int32_t *region_x;      /* [nregion] */
+    const int32_t *region_y;      /* [nregion] */
 } vor_set;
 
 typedef enum {
@@ -113,7 +125,8 @@ typedef struct {
     uint32_t n;
     const uint32_t *cell_off;  /* [n+1] CSR offsets into nbr / vtx                            */
     const int32_t *nbr;        /* [cell_off[n]] per cell, CCW, lines that carry an edge of
-                                  positive length: site index 0..n-1 or a VOR_SIDE_* code;
+                                  positive length: site index 0..n-1 or a side code (box:
+                                  VOR_SIDE_*, polygon: -(e+1));
                                   rotated so the entry smallest as uint32 comes first         */
     const vor_rat *vtx;        /* [cell_off[n]] vtx[i] = line(nbr[i]) ∩ line(nbr[i+1 cyclic]);
                                   NULL with VOR_NO_VERTICES                                   */

@@ -26,7 +26,8 @@ class vor_box(C.Structure):
 
 class vor_set(C.Structure):
     _fields_ = [("n", C.c_uint32), ("x", C.c_void_p), ("y", C.c_void_p), ("box", vor_box),
-                ("flags", C.c_uint32)]
+                ("flags", C.c_uint32), ("nregion", C.c_uint32), ("region_x", C.c_void_p),
+                ("region_y", C.c_void_p)]
 
 
 class vor_opts(C.Structure):
@@ -135,16 +136,24 @@ def vor_destroy(ctx) -> None:
     _check(lib().vor_destroy(ctx), "vor_destroy")
 
 
-def _make_set(x, y, box, device_ptrs=False):
-    """x, y: int32 numpy arrays (host) or (ptr, ptr) device addresses with device_ptrs=True."""
+def _make_set(x, y, box, device_ptrs=False, region=None):
+    """x, y: int32 numpy arrays (host) or (ptr, ptr) device addresses with device_ptrs=True.
+    region: None (X = box) or (vx, vy), the vertices of a convex polygon X, counter-clockwise."""
+    rn, rx, ry, rkeep = 0, None, None, None
+    if region is not None:
+        vx = np.ascontiguousarray(region[0], dtype=np.int32)
+        vy = np.ascontiguousarray(region[1], dtype=np.int32)
+        if vx.shape != vy.shape or vx.ndim != 1:
+            raise ValueError("region: vx and vy must be 1-D arrays of the same length")
+        rn, rx, ry, rkeep = vx.shape[0], vx.ctypes.data, vy.ctypes.data, (vx, vy)
     if device_ptrs:
         xp, yp, n = x[0], y[0], x[1]
-        return vor_set(n, xp, yp, vor_box(*box), VOR_SET_DEVICE), None
+        return vor_set(n, xp, yp, vor_box(*box), VOR_SET_DEVICE, rn, rx, ry), rkeep
     x = np.ascontiguousarray(x, dtype=np.int32)
     y = np.ascontiguousarray(y, dtype=np.int32)
-    keep = (x, y)
+    keep = (x, y, rkeep)
     return vor_set(x.shape[0], x.ctypes.data, y.ctypes.data, vor_box(*[int(v) for v in box]),
-                   0), keep
+                   0, rn, rx, ry), keep
 
 
 @dataclass
@@ -231,10 +240,12 @@ def vor_result_free(rp) -> None:
     lib().vor_result_free(rp)
 
 
-def vor_compute(ctx, x, y, box, device_ptrs=False, keep_raw=False, device_result=False):
+def vor_compute(ctx, x, y, box, device_ptrs=False, keep_raw=False, device_result=False,
+                region=None):
     """x, y: int32 host arrays, or (device address, n) pairs with device_ptrs=True.
-    device_result must match the context's VOR_RESULT_DEVICE flag."""
-    s, keep = _make_set(x, y, box, device_ptrs)
+    device_result must match the context's VOR_RESULT_DEVICE flag.  region: (vx, vy) of a
+    convex polygon X (counter-clockwise), or None for X = box."""
+    s, keep = _make_set(x, y, box, device_ptrs, region)
     rp = C.POINTER(vor_result)()
     _check(lib().vor_compute(ctx, C.byref(s), C.byref(rp)), "vor_compute")
     if keep_raw:
@@ -246,12 +257,13 @@ def vor_compute(ctx, x, y, box, device_ptrs=False, keep_raw=False, device_result
 
 
 def vor_compute_batch(ctx, sets):
-    """sets: list of (x, y, box).  Returns (status, [Result])."""
+    """sets: list of (x, y, box) or (x, y, box, region).  Returns (status, [Result])."""
     k = len(sets)
     arr = (vor_set * k)()
     keep = []
-    for i, (x, y, box) in enumerate(sets):
-        s, kp = _make_set(x, y, box)
+    for i, t in enumerate(sets):
+        x, y, box = t[:3]
+        s, kp = _make_set(x, y, box, region=t[3] if len(t) > 3 else None)
         arr[i] = s
         keep.append(kp)
     outs = (C.POINTER(vor_result) * k)()
@@ -268,8 +280,8 @@ def vor_compute_batch(ctx, sets):
     return rc, res
 
 
-def vor_submit(ctx, x, y, box) -> int:
-    s, keep = _make_set(x, y, box)
+def vor_submit(ctx, x, y, box, region=None) -> int:
+    s, keep = _make_set(x, y, box, region=region)
     t = C.c_uint64()
     _check(lib().vor_submit(ctx, C.byref(s), C.byref(t)), "vor_submit")
     return int(t.value)
@@ -368,8 +380,8 @@ class Context:
     def compute_batch(self, sets):
         return vor_compute_batch(self.h, sets)
 
-    def submit(self, x, y, box):
-        return vor_submit(self.h, x, y, box)
+    def submit(self, x, y, box, region=None):
+        return vor_submit(self.h, x, y, box, region)
 
     def poll(self, ticket):
         return vor_poll(self.h, ticket)

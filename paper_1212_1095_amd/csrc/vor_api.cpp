@@ -13,6 +13,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <numeric>
 #include <thread>
 #include <vector>
 
@@ -76,12 +77,13 @@ enum BufId {
     B_SETS, B_SETOFF, B_INX, B_INY, B_XYID, B_KEY, B_BCNT, B_BSTART, B_SXY, B_SID, B_OCNT,
     B_OLINES, B_OVF, B_POOL, B_QUEUE, B_QUEUE2, B_WBUF, B_WBUF2, B_CELLOFF, B_NBR, B_VTX,
     B_DCNT, B_DELOFF, B_DEL, B_SCANTMP, B_SMALL, B_STATS, B_TCHILD, B_NODES, B_TXY,
-    B_TID, B_QUEUE3, B_TREF, B_NLIST, B_COUNT
+    B_TID, B_QUEUE3, B_TREF, B_NLIST, B_SIDES, B_COUNT
 };
 
 struct Workspace {
     DevBuf b[B_COUNT];
     HostBuf h_in, h_small;
+    std::vector<SideRel> sides_h;   // side table of the sets being launched
     hipStream_t stream = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     hipEvent_t ek[NSTAGES + 1] = {};
@@ -128,13 +130,69 @@ struct Workspace {
 struct HostSet {   // validated description of one input set
     uint32_t n;
     const int32_t *x, *y;
-    vor_box box;
+    vor_box box;           // X, or the bounding box of a polygon X
     bool device;
+    uint32_t nreg = 0;     // vertices of a convex polygon X (0: X is the box)
+    const int32_t *rx = nullptr, *ry = nullptr;
 };
 
-int check_set(const vor_set *s) {
+// Convex polygon X (Remark 11.1): 3..VOR_MAX_SIDES vertices, counter-clockwise, every turn
+// strictly left and the edge directions going round once (they switch between the upper and
+// the lower half-plane exactly twice).  Writes its bounding box.
+int check_region(uint32_t K, const int32_t *vx, const int32_t *vy, vor_box &bb) {
+    if (K < 3 || K > VOR_MAX_SIDES || !vx || !vy) return VOR_E_INVAL;
+    const long long lim = 1LL << 30;
+    long long mnx = vx[0], mxx = vx[0], mny = vy[0], mxy = vy[0];
+    for (uint32_t e = 0; e < K; ++e) {
+        if (vx[e] < -lim || vx[e] > lim || vy[e] < -lim || vy[e] > lim) return VOR_E_DOMAIN;
+        mnx = std::min<long long>(mnx, vx[e]);
+        mxx = std::max<long long>(mxx, vx[e]);
+        mny = std::min<long long>(mny, vy[e]);
+        mxy = std::max<long long>(mxy, vy[e]);
+    }
+    if (mxx - mnx > (1LL << 24) || mxy - mny > (1LL << 24)) return VOR_E_DOMAIN;
+    int changes = 0;
+    for (uint32_t e = 0; e < K; ++e) {
+        const uint32_t f = (e + 1) % K, g = (e + 2) % K;
+        const long long ax = (long long)vx[f] - vx[e], ay = (long long)vy[f] - vy[e];
+        const long long bx = (long long)vx[g] - vx[f], by = (long long)vy[g] - vy[f];
+        if (ax * by - ay * bx <= 0) return VOR_E_INVAL;
+        const bool ua = ay > 0 || (ay == 0 && ax > 0), ub = by > 0 || (by == 0 && bx > 0);
+        changes += ua != ub;
+    }
+    if (changes != 2) return VOR_E_INVAL;
+    bb = vor_box{(int32_t)mnx, (int32_t)mny, (int32_t)mxx, (int32_t)mxy};
+    return VOR_OK;
+}
+
+// Side lines of a checked polygon, relative to its bounding-box origin (x0, y0): side e is
+// N.x <= c with the primitive outward normal N = (dy, -dx) / gcd.
+void region_sides(uint32_t K, const int32_t *vx, const int32_t *vy, int32_t x0, int32_t y0,
+                  std::vector<SideRel> &out) {
+    for (uint32_t e = 0; e < K; ++e) {
+        const long long ax = (long long)vx[e] - x0, ay = (long long)vy[e] - y0;
+        const long long bx = (long long)vx[(e + 1) % K] - x0, by = (long long)vy[(e + 1) % K] - y0;
+        long long dx = bx - ax, dy = by - ay, g = std::gcd(dx < 0 ? -dx : dx, dy < 0 ? -dy : dy);
+        SideRel s;
+        s.nx = (int32_t)(dy / g);
+        s.ny = (int32_t)(-dx / g);
+        s.c = (int64_t)s.nx * ax + (int64_t)s.ny * ay;
+        out.push_back(s);
+    }
+}
+
+// Validates a set and returns the HostSet the pipeline runs (device: inputs in HBM).
+int check_set(const vor_set *s, HostSet &h) {
     if (!s || s->n == 0 || !s->x || !s->y) return VOR_E_INVAL;
-    const vor_box &b = s->box;
+    h = HostSet{s->n, s->x, s->y, s->box, (s->flags & VOR_SET_DEVICE) != 0};
+    if (s->nregion) {
+        const int rc = check_region(s->nregion, s->region_x, s->region_y, h.box);
+        if (rc != VOR_OK) return rc;
+        h.nreg = s->nregion;
+        h.rx = s->region_x;
+        h.ry = s->region_y;
+    }
+    const vor_box &b = h.box;
     if (!(b.x0 < b.x1 && b.y0 < b.y1)) return VOR_E_INVAL;
     const long long lim = 1LL << 30;
     if (b.x0 < -lim || b.y0 < -lim || b.x1 > lim || b.y1 > lim) return VOR_E_DOMAIN;
@@ -196,6 +254,7 @@ struct Request {
     uint64_t ticket;
     std::vector<int32_t> x, y;
     vor_box box;
+    std::vector<int32_t> rx, ry;   // polygon X (empty: the box)
     double t_submit = 0, t_admit = 0, t_done = 0;
     int status = VOR_PENDING;
     vor_result *result = nullptr;
@@ -249,6 +308,7 @@ int launch(vor_ctx *ctx, Workspace &ws, const std::vector<HostSet> &sets, bool v
     const int K = (int)sets.size();
     descs.resize(K);
     set_off.assign(K + 1, 0);
+    ws.sides_h.clear();
     long long total = 0, gtot = 0;
     for (int i = 0; i < K; ++i) {
         const HostSet &s = sets[i];
@@ -262,6 +322,9 @@ int launch(vor_ctx *ctx, Workspace &ws, const std::vector<HostSet> &sets, bool v
         choose_grid(s.box, s.n, ctx->tune.sites_per_bucket, ctx->tune.block_halfwidth, d);
         d.ht = ctx->tune.leaf_halfwidth;
         d.bucket_off = (int32_t)gtot;
+        d.ns = (int32_t)s.nreg;
+        d.side_off = (int32_t)ws.sides_h.size();
+        if (s.nreg) region_sides(s.nreg, s.rx, s.ry, s.box.x0, s.box.y0, ws.sides_h);
         set_off[i] = (int)total;
         total += s.n;
         gtot += (long long)d.gx * d.gy;
@@ -295,7 +358,8 @@ int launch(vor_ctx *ctx, Workspace &ws, const std::vector<HostSet> &sets, bool v
         {B_CELLOFF, 4ull * (T + 1)}, {B_NBR, 4ull * E},
         {B_VTX, vertices ? sizeof(vor_rat) * E : 16}, {B_DCNT, 4ull * T},
         {B_DELOFF, 4ull * (T + 1)}, {B_DEL, 8ull * D}, {B_SCANTMP, 4ull * stmp},
-        {B_SMALL, 4ull * SMALL_INTS}, {B_STATS, 8ull * SL_COUNT}};
+        {B_SMALL, 4ull * SMALL_INTS}, {B_STATS, 8ull * SL_COUNT},
+        {B_SIDES, sizeof(SideRel) * std::max<size_t>(1, ws.sides_h.size())}};
     bool grew = false;
     for (auto &q : need) {
         const size_t before = ws.b[q.id].cap;
@@ -330,6 +394,9 @@ int launch(vor_ctx *ctx, Workspace &ws, const std::vector<HostSet> &sets, bool v
     }
     e = hipMemcpyAsync(ws.b[B_SETS].p, descs.data(), sizeof(SetDesc) * K, hipMemcpyHostToDevice,
                        ws.stream);
+    if (e == hipSuccess && !ws.sides_h.empty())
+        e = hipMemcpyAsync(ws.b[B_SIDES].p, ws.sides_h.data(), sizeof(SideRel) * ws.sides_h.size(),
+                           hipMemcpyHostToDevice, ws.stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(ws.b[B_SETOFF].p, set_off.data(), 4ull * (K + 1),
                            hipMemcpyHostToDevice, ws.stream);
@@ -338,6 +405,8 @@ int launch(vor_ctx *ctx, Workspace &ws, const std::vector<HostSet> &sets, bool v
     std::memset(&a, 0, sizeof(a));
     a.sets = ws.b[B_SETS].as<SetDesc>();
     a.nsets = K;
+    a.sides = ws.b[B_SIDES].as<SideRel>();
+    a.any_poly = !ws.sides_h.empty();
     a.set_off = ws.b[B_SETOFF].as<int>();
     a.total = (int)T;
     a.gtot = gtot;
@@ -676,7 +745,13 @@ void request_loop(vor_ctx *ctx) {
             const double t = now_s();
             for (auto &r : take) {
                 r->t_admit = t;
-                sets.push_back(HostSet{(uint32_t)r->x.size(), r->x.data(), r->y.data(), r->box, false});
+                HostSet h{(uint32_t)r->x.size(), r->x.data(), r->y.data(), r->box, false};
+                if (!r->rx.empty()) {
+                    h.nreg = (uint32_t)r->rx.size();
+                    h.rx = r->rx.data();
+                    h.ry = r->ry.data();
+                }
+                sets.push_back(h);
             }
             fl[w].reqs = take;
             int rc = launch(ctx, ctx->rws[w], sets, vertices, exact_only, false, ctx->use_graph,
@@ -801,12 +876,12 @@ int vor_get_tuning(vor_ctx *ctx, vor_tuning *t) {
 int vor_compute(vor_ctx *ctx, const vor_set *set, vor_result **out) {
     if (!ctx || !out) return VOR_E_INVAL;
     *out = nullptr;
-    int rc = check_set(set);
+    HostSet h;
+    int rc = check_set(set, h);
     if (rc != VOR_OK) return rc;
     std::lock_guard<std::mutex> lk(ctx->mu);
     if (hipSetDevice(ctx->device) != hipSuccess) return VOR_E_DEVICE;
-    std::vector<HostSet> sets{HostSet{set->n, set->x, set->y, set->box,
-                                      (set->flags & VOR_SET_DEVICE) != 0}};
+    std::vector<HostSet> sets{h};
     std::vector<vor_result *> outs;
     rc = run_sync(ctx, ctx->ws, sets, outs, (ctx->opts.flags & VOR_RESULT_DEVICE) != 0);
     if (rc == VOR_OK) *out = outs[0];
@@ -819,10 +894,11 @@ int vor_compute_batch(vor_ctx *ctx, const vor_set *sets, uint32_t k, vor_result 
     std::vector<HostSet> hs;
     long long total = 0;
     for (uint32_t i = 0; i < k; ++i) {
-        int rc = check_set(&sets[i]);
+        HostSet h;
+        int rc = check_set(&sets[i], h);
         if (rc != VOR_OK) return rc;
         if (sets[i].flags & VOR_SET_DEVICE) return VOR_E_INVAL;   // batches take host inputs
-        hs.push_back(HostSet{sets[i].n, sets[i].x, sets[i].y, sets[i].box, false});
+        hs.push_back(h);
         total += sets[i].n;
     }
     if (total >= (1LL << 30)) return VOR_E_NOMEM;
@@ -856,16 +932,21 @@ int vor_compute_batch(vor_ctx *ctx, const vor_set *sets, uint32_t k, vor_result 
 
 int vor_submit(vor_ctx *ctx, const vor_set *set, uint64_t *ticket) {
     if (!ctx || !ticket) return VOR_E_INVAL;
-    int rc = check_set(set);
+    HostSet h;
+    int rc = check_set(set, h);
     if (rc != VOR_OK) return rc;
     if (set->flags & VOR_SET_DEVICE) return VOR_E_INVAL;
     auto r = std::make_shared<Request>();
     r->x.assign(set->x, set->x + set->n);
     r->y.assign(set->y, set->y + set->n);
-    r->box = set->box;
+    r->box = h.box;
+    if (h.nreg) {
+        r->rx.assign(h.rx, h.rx + h.nreg);
+        r->ry.assign(h.ry, h.ry + h.nreg);
+    }
     r->t_submit = now_s();
     SetDesc d{};
-    choose_grid(set->box, set->n, ctx->tune.sites_per_bucket, ctx->tune.block_halfwidth, d);
+    choose_grid(h.box, set->n, ctx->tune.sites_per_bucket, ctx->tune.block_halfwidth, d);
     r->footprint = footprint_bytes(set->n, (uint64_t)d.gx * d.gy,
                                    !(ctx->opts.flags & VOR_NO_VERTICES));
     {

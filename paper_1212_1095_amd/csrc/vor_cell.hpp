@@ -152,9 +152,19 @@ __device__ __forceinline__ float upper_of(const Cell &C, const float2 *__restric
     return key_hi_line((float)L.c, (float)L.nx, (float)L.ny, dx, dy);
 }
 
-// Box sides the ray can leave through: at most one horizontal and one vertical side.
+// Sides the ray can leave through: for the box at most one horizontal and one vertical side;
+// for a polygon every side (those with N.d <= 0 get +inf).
 __device__ __forceinline__ void consider_sides(const Cell &C, float dx, float dy, int ex1, int ex2,
                                                Best &b) {
+    if (C.ns > 0) {
+        for (int code = -1; code >= -C.ns; --code) {
+            const Line L = side_line(C, code);
+            float k = key_lo_line((float)L.c, (float)L.nx, (float)L.ny, dx, dy);
+            k = (code == ex1 || code == ex2) ? FINF : k;
+            consider(k, code, b);
+        }
+        return;
+    }
     const int sv = dy > 0.0f ? -3 : -1, sh = dx > 0.0f ? -2 : -4;
     const Line Lv = side_line(C, sv), Lh = side_line(C, sh);
     float kv = key_lo_line((float)Lv.c, (float)Lv.nx, (float)Lv.ny, dx, dy);
@@ -365,7 +375,8 @@ __device__ __forceinline__ void exact_rect(const Cell &C, const float2 *__restri
 __device__ __forceinline__ void exact_sides(const Cell &C, const Dir &d, float Tlim, bool filter,
                                             int ex1, int ex2, XBest &b) {
     const float lim = Tlim * CERT_UP;
-    for (int code = -1; code >= -4; --code) {
+    const int ns = C.ns > 0 ? C.ns : 4;
+    for (int code = -1; code >= -ns; --code) {
         if (code == ex1 || code == ex2) continue;
         const Line L = side_line(C, code);
         if (filter &&

@@ -52,6 +52,15 @@ struct SetDesc {
     int32_t bucket_off;  // first global bucket of the set
     int32_t h;           // block half-width in buckets (shells 0..h scanned first)
     int32_t ht;          // leaf sides around p's leaf scanned first (coordinate scans)
+    int32_t ns;          // 0: X is the box [0, W] x [0, H]; else the sides of a convex polygon X
+    int32_t side_off;    // its first entry in the side table
+};
+
+// Side e of a convex polygon X (code -(e+1)): N.x <= c with the primitive outward normal N,
+// x relative to the set's box origin (Remark 11.1: any convex polygon X).
+struct SideRel {
+    int32_t nx, ny;
+    int64_t c;
 };
 
 // ------------------------------------------------------------------------------ FP32 filter
@@ -159,11 +168,23 @@ struct Cell {       // per-cell constants
     int px, py;
     int bx, by;     // p's bucket
     int W, H;       // box extent (relative box [0, W] x [0, H])
+    int ns;         // 0: X is the box; else X is the convex polygon of `sides`
+    const SideRel *sides;
 };
 
-// Box side code -> line (N.w <= 2 dist).  k = -code - 1: 0 bottom, 1 right, 2 top, 3 left.
-// Written with arithmetic selects so that no lookup table is materialised.
+// Side code -> line in p's doubled frame: N.w <= 2 (c - N.p).  Box sides (k = -code - 1: 0
+// bottom, 1 right, 2 top, 3 left) are written with arithmetic selects so that no lookup table
+// is materialised; polygon sides come from the side table.
 __device__ __forceinline__ Line side_line(const Cell &C, int code) {
+    if (C.ns > 0) {
+        const SideRel s = C.sides[-code - 1];
+        Line L;
+        L.id = code;
+        L.nx = s.nx;
+        L.ny = s.ny;
+        L.c = 2 * (s.c - (int64_t)s.nx * C.px - (int64_t)s.ny * C.py);
+        return L;
+    }
     const int k = -code - 1;
     const bool vert = (k & 1) == 0;            // bottom / top: normal along y
     const bool far = ((k + 1) >> 1) & 1;       // right / top: outward normal positive

@@ -6,6 +6,7 @@
 namespace vor {
 
 struct SetDesc;
+struct SideRel;
 struct TNode;
 constexpr int SMALL_INTS = 16;   // status, queue counters, pool / tree counters, spare
 constexpr int DEEP_BLOCKS = 8;   // one-wave workers of the deep-cell pass
@@ -15,6 +16,8 @@ constexpr int LVCNT0 = 8;        // small[LVCNT0 + l]: nodes listed for refineme
 struct PipeArgs {
     const SetDesc *sets;
     int nsets;
+    const SideRel *sides;   // sides of the polygon regions (at least one entry)
+    bool any_poly;          // some set of the launch has a polygon X
     const int *set_off;     // [nsets + 1] first global site of each set
     int total;              // sites in all sets
     long long gtot;         // buckets in all sets

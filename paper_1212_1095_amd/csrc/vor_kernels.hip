@@ -51,14 +51,19 @@ __global__ void k_clear(int *__restrict__ p, long long n, int *__restrict__ smal
 }
 
 __global__ void k_prep(const SetDesc *__restrict__ sets, int nsets, const int *__restrict__ set_off,
-                       const int *__restrict__ in_x, const int *__restrict__ in_y, int total,
-                       int2 *__restrict__ xyid, int *__restrict__ key, int *__restrict__ bcnt,
-                       int *__restrict__ status) {
+                       const SideRel *__restrict__ sides, const int *__restrict__ in_x,
+                       const int *__restrict__ in_y, int total, int2 *__restrict__ xyid,
+                       int *__restrict__ key, int *__restrict__ bcnt, int *__restrict__ status) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= total) return;
     const SetDesc S = sets[find_set(set_off, nsets, i)];
     long long rx = (long long)in_x[i] - S.x0, ry = (long long)in_y[i] - S.y0;
-    if (!(rx > 0 && rx < S.W && ry > 0 && ry < S.H)) {
+    bool inside = rx > 0 && rx < S.W && ry > 0 && ry < S.H;
+    for (int e = 0; e < S.ns && inside; ++e) {   // strictly inside every side of a polygon X
+        const SideRel s = sides[S.side_off + e];
+        inside = (int64_t)s.nx * rx + (int64_t)s.ny * ry < s.c;
+    }
+    if (!inside) {
         atomicOr(status, ST_DOMAIN);
         rx = rx < 1 ? 1 : (rx > S.W - 1 ? S.W - 1 : rx);
         ry = ry < 1 ? 1 : (ry > S.H - 1 ? S.H - 1 : ry);
@@ -319,7 +324,10 @@ __global__ __launch_bounds__(REFINE_BLOCK) void k_tree_refine(
     }
 }
 
-__device__ __forceinline__ Cell make_cell(const SetDesc &S, float2 p) {
+// POLY = false: every set of the launch has the box as X (the side code folds to the box's).
+template <bool POLY = true>
+__device__ __forceinline__ Cell make_cell(const SetDesc &S, float2 p,
+                                          const SideRel *__restrict__ sides) {
     Cell C;
     C.gx = S.gx;
     C.gy = S.gy;
@@ -335,6 +343,8 @@ __device__ __forceinline__ Cell make_cell(const SetDesc &S, float2 p) {
     C.by = min(C.py / S.s, S.gy - 1);
     C.W = S.W;
     C.H = S.H;
+    C.ns = POLY ? S.ns : 0;
+    C.sides = POLY ? sides + S.side_off : nullptr;
     return C;
 }
 
@@ -360,9 +370,10 @@ __device__ __forceinline__ void reduce_stats(const Counters &K, uint32_t edges, 
 // Filtered pass: one thread per cell, cells in bucket order, stack in LDS.  Cells whose scans
 // meet a crowded bucket go to the adaptive pass (queue3), undecided cells to the exact pass.
 // Five waves per SIMD (the register budget that this asks for beats the few spills it costs).
-template <int BLOCK>
+template <int BLOCK, bool POLY>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_cells_fast(
     const SetDesc *__restrict__ sets, int nsets, const int *__restrict__ set_off,
+    const SideRel *__restrict__ sides,
     const float2 *__restrict__ sxy, const int *__restrict__ sid, const int *__restrict__ bstart,
     int total, int *__restrict__ ocnt, int *__restrict__ olines, int *__restrict__ ovf,
     int *__restrict__ dcnt, int *__restrict__ queue, int *__restrict__ qcount,
@@ -379,7 +390,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5, 8))) v
     uint32_t edges = 0, deferred = 0;
     if (pos < total) {
         const SetDesc S = sets[find_set(set_off, nsets, pos)];
-        const Cell C = make_cell(S, sxy[pos]);
+        const Cell C = make_cell<POLY>(S, sxy[pos], sides);
         const int k = sid[pos];
         const int g = S.site_off + k;
         LdsStack<BLOCK> st{stk, 0};
@@ -410,6 +421,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5, 8))) v
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_cells_tree(
     const SetDesc *__restrict__ sets, int nsets, const int *__restrict__ set_off,
+    const SideRel *__restrict__ sides,
     const float2 *__restrict__ sxy, const int *__restrict__ sid, const int *__restrict__ tstart,
     const int *__restrict__ tchild, const TNode *__restrict__ nodes, const int *__restrict__ tref,
     int *__restrict__ ocnt,
@@ -431,7 +443,7 @@ __global__ __launch_bounds__(BLOCK) void k_cells_tree(
     for (int qi = blockIdx.x * BLOCK + threadIdx.x; qi < nq; qi += gridDim.x * BLOCK) {
         const int pos = queue3[qi];
         const SetDesc S = sets[find_set(set_off, nsets, pos)];
-        const Cell C = make_cell(S, sxy[pos]);
+        const Cell C = make_cell(S, sxy[pos], sides);
         const int k = sid[pos];
         const int g = S.site_off + k;
         LdsStack<BLOCK> st{stk, 0};
@@ -485,6 +497,7 @@ __device__ __forceinline__ int coop_cell(const Cell &C, const float2 *__restrict
 template <int MODE, int LCAP>
 __global__ __launch_bounds__(64) void k_cells_exact(
     const SetDesc *__restrict__ sets, int nsets, const int *__restrict__ set_off,
+    const SideRel *__restrict__ sides,
     const float2 *__restrict__ sxy, const int *__restrict__ sid, const int *__restrict__ bstart,
     int *__restrict__ ocnt, int *__restrict__ olines, int *__restrict__ dcnt,
     int *__restrict__ ovf, int *__restrict__ pool, int *__restrict__ poolcnt, long long poolcap,
@@ -506,7 +519,7 @@ __global__ __launch_bounds__(64) void k_cells_exact(
     for (int qi = blockIdx.x; qi < nq; qi += gridDim.x) {
         const int pos = queue[qi];
         const SetDesc S = sets[find_set(set_off, nsets, pos)];
-        const Cell C = make_cell(S, sxy[pos]);
+        const Cell C = make_cell(S, sxy[pos], sides);
         const int k = sid[pos];
         const int g = S.site_off + k;
         GridScan<Coop, GlobalRows, false> sc{GlobalRows{0}, bstart, false};
@@ -639,11 +652,18 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_apply(const int *__restrict
 
 // ------------------------------------------------------------------------------ output
 // Absolute line N.x <= c of neighbour j of the cell whose site is at relative p (site lines:
-// N = 2 (q - p), c = |q|^2 - |p|^2 with q the neighbour's site; sides: unit outward normal).
-__device__ __forceinline__ void abs_line(const SetDesc &S, int2 p, int j, int2 q, long long &nx,
-                                         long long &ny, long long &c) {
+// N = 2 (q - p), c = |q|^2 - |p|^2 with q the neighbour's site; sides: primitive outward normal,
+// unit for the box).
+__device__ __forceinline__ void abs_line(const SetDesc &S, const SideRel *__restrict__ sides,
+                                         int2 p, int j, int2 q, long long &nx, long long &ny,
+                                         long long &c) {
     const long long px = (long long)p.x + S.x0, py = (long long)p.y + S.y0;
-    if (j >= 0) {
+    if (j < 0 && S.ns > 0) {
+        const SideRel s = sides[S.side_off - j - 1];
+        nx = s.nx;
+        ny = s.ny;
+        c = s.c + (long long)s.nx * S.x0 + (long long)s.ny * S.y0;
+    } else if (j >= 0) {
         const long long qx = (long long)q.x + S.x0, qy = (long long)q.y + S.y0;
         nx = 2 * (qx - px);
         ny = 2 * (qy - py);
@@ -668,11 +688,11 @@ struct Rat {
 };
 
 // Vertex of lines 1 and 2 in pair form (X/D, Y/D), Cramer's rule.
-__device__ __forceinline__ Rat pair_vertex(const SetDesc &S, int2 p, int a, int2 qa, int b,
-                                           int2 qb) {
+__device__ __forceinline__ Rat pair_vertex(const SetDesc &S, const SideRel *__restrict__ sides,
+                                           int2 p, int a, int2 qa, int b, int2 qb) {
     long long n1x, n1y, c1, n2x, n2y, c2;
-    abs_line(S, p, a, qa, n1x, n1y, c1);
-    abs_line(S, p, b, qb, n2x, n2y, c2);
+    abs_line(S, sides, p, a, qa, n1x, n1y, c1);
+    abs_line(S, sides, p, b, qb, n2x, n2y, c2);
     const i128 X = (i128)c1 * n2y - (i128)c2 * n1y;
     const i128 Y = (i128)n1x * c2 - (i128)n2x * c1;
     Rat v;
@@ -690,7 +710,8 @@ constexpr int EMIT_ECAP = 2048;   // CSR entries staged per block (mean about 6 
 // Cell by cell (blocks whose entries exceed the LDS capacity: cells with very many edges).
 // Returns false, writing nothing, when the neighbours > k are not the dn the cell pass counted.
 template <bool VERT>
-__device__ bool emit_cell(const SetDesc &S, int so, int k, int2 p, const int *__restrict__ src,
+__device__ bool emit_cell(const SetDesc &S, const SideRel *__restrict__ sides, int so, int k,
+                          int2 p, const int *__restrict__ src,
                           int m, int dn, long long base, long long dbase,
                           const int2 *__restrict__ xyid, int *__restrict__ nbr,
                           Rat *__restrict__ vtx, unsigned *__restrict__ del) {
@@ -706,7 +727,7 @@ __device__ bool emit_cell(const SetDesc &S, int so, int k, int2 p, const int *__
             const int a = src[(r + t) % m], b = src[(r + t + 1) % m];
             const int2 qa = a >= 0 ? xyid[so + a] : make_int2(0, 0);
             const int2 qb = b >= 0 ? xyid[so + b] : make_int2(0, 0);
-            vtx[base + t] = pair_vertex(S, p, a, qa, b, qb);
+            vtx[base + t] = pair_vertex(S, sides, p, a, qa, b, qb);
         }
     for (int t = 0; t < m; ++t) {   // Delaunay pairs: rank of each neighbour > k
         const int j = src[t];
@@ -727,7 +748,8 @@ __device__ bool emit_cell(const SetDesc &S, int so, int k, int2 p, const int *__
 // A block whose entries exceed the LDS capacity works cell by cell instead.
 template <bool VERT>
 __global__ __launch_bounds__(EMIT_BLOCK) void k_emit(
-    const SetDesc *__restrict__ sets, int nsets, const int *__restrict__ set_off, int total,
+    const SetDesc *__restrict__ sets, int nsets, const int *__restrict__ set_off,
+    const SideRel *__restrict__ sides, int total,
     const int *__restrict__ ocnt, const int *__restrict__ olines, const int *__restrict__ ovf,
     const int *__restrict__ pool, const int *__restrict__ dcnt, const int *__restrict__ cell_off,
     long long cap, const int *__restrict__ del_off, long long del_cap,
@@ -797,8 +819,8 @@ __global__ __launch_bounds__(EMIT_BLOCK) void k_emit(
     }
     if (!staged) {
         if (tid < nc &&
-            !emit_cell<VERT>(sets[s], set_off[s], k, p, src, m, dn, base, dbase, xyid, nbr, vtx,
-                             del))
+            !emit_cell<VERT>(sets[s], sides, set_off[s], k, p, src, m, dn, base, dbase, xyid, nbr,
+                             vtx, del))
             atomicOr(status, ST_INTERNAL);
         return;
     }
@@ -839,7 +861,7 @@ __global__ __launch_bounds__(EMIT_BLOCK) void k_emit(
         nbr[E0 + lo + t] = j;
         if (VERT) {
             const int e2 = u + 1 == mo ? lo : e + 1;
-            vtx[E0 + lo + t] = pair_vertex(sets[cset[o]], pc[o], j, qc[e], lin[e2], qc[e2]);
+            vtx[E0 + lo + t] = pair_vertex(sets[cset[o]], sides, pc[o], j, qc[e], lin[e2], qc[e2]);
         }
         const int ko = g0 + o - set_off[cset[o]];
         if (j > ko) {
@@ -886,21 +908,27 @@ long long scan_tmp_ints(long long n) { return (long long)nblk(n, SCAN_TILE) + 1;
 template <int BLOCK>
 static void launch_fast(const PipeArgs &a, hipStream_t st) {
     const unsigned nb = (nblk(a.total, BLOCK) + 7) & ~7u;
-    k_cells_fast<BLOCK><<<nb, BLOCK, 0, st>>>(a.sets, a.nsets, a.set_off, a.sxy, a.sid, a.bstart,
-                                             a.total, a.ocnt, a.olines, a.ovf, a.dcnt,
-                                             a.queue, a.qcount(), a.queue3, a.qcount3(),
-                                             a.stats, a.status());
+    if (a.any_poly)
+        k_cells_fast<BLOCK, true><<<nb, BLOCK, 0, st>>>(
+            a.sets, a.nsets, a.set_off, a.sides, a.sxy, a.sid, a.bstart, a.total, a.ocnt,
+            a.olines, a.ovf, a.dcnt, a.queue, a.qcount(), a.queue3, a.qcount3(), a.stats,
+            a.status());
+    else
+        k_cells_fast<BLOCK, false><<<nb, BLOCK, 0, st>>>(
+            a.sets, a.nsets, a.set_off, a.sides, a.sxy, a.sid, a.bstart, a.total, a.ocnt,
+            a.olines, a.ovf, a.dcnt, a.queue, a.qcount(), a.queue3, a.qcount3(), a.stats,
+            a.status());
 }
 
 template <int MODE>
 static void launch_exact(const PipeArgs &a, hipStream_t st) {
     k_cells_exact<MODE, DCAP1><<<a.exact_blocks, 64, 0, st>>>(
-        a.sets, a.nsets, a.set_off, a.sxy, a.sid, a.bstart, a.ocnt, a.olines, a.dcnt, a.ovf,
+        a.sets, a.nsets, a.set_off, a.sides, a.sxy, a.sid, a.bstart, a.ocnt, a.olines, a.dcnt, a.ovf,
         a.pool, a.poolcnt(), a.poolcap, a.queue, a.qcount(), a.queue2,
         a.qcount2(), a.wbuf, DCAP1, a.stats, a.status_rw());
     // deep cells: few workers with a large area each
     k_cells_exact<MODE, 0><<<DEEP_BLOCKS, 64, 0, st>>>(
-        a.sets, a.nsets, a.set_off, a.sxy, a.sid, a.bstart, a.ocnt, a.olines, a.dcnt, a.ovf,
+        a.sets, a.nsets, a.set_off, a.sides, a.sxy, a.sid, a.bstart, a.ocnt, a.olines, a.dcnt, a.ovf,
         a.pool, a.poolcnt(), a.poolcap, a.queue2, a.qcount2(), nullptr,
         nullptr,
         a.wbuf2, DCAP2, a.stats, a.status_rw());
@@ -916,8 +944,8 @@ void launch_stage(const PipeArgs &a, hipStream_t st, int stage) {
         const long long big = n > 64 ? n : 64;
         k_clear<<<nblk(big, 256), 256, 0, st>>>(a.bcnt, n, a.small, SMALL_INTS, a.stats);
         // grid build (Method 11.5), then adaptive refinement of crowded buckets
-        k_prep<<<nblk(T, 256), 256, 0, st>>>(a.sets, a.nsets, a.set_off, a.in_x, a.in_y, T,
-                                              a.xyid, a.key, a.bcnt, a.status());
+        k_prep<<<nblk(T, 256), 256, 0, st>>>(a.sets, a.nsets, a.set_off, a.sides, a.in_x,
+                                              a.in_y, T, a.xyid, a.key, a.bcnt, a.status());
         launch_scan(a.bcnt, a.gtot, a.bstart, a.scan_tmp, a.status(), 0, st);
         k_scatter<<<nblk(T, 256), 256, 0, st>>>(a.sets, a.nsets, a.set_off, T, a.xyid, a.key,
                                                  a.bstart, a.bcnt, a.sxy, a.sid);
@@ -951,7 +979,7 @@ void launch_stage(const PipeArgs &a, hipStream_t st, int stage) {
             const unsigned nb = (unsigned)std::max<long long>(
                 1, std::min<long long>(nblk(T, TREE_PASS_BLOCK), 2048));
             k_cells_tree<TREE_PASS_BLOCK><<<nb, TREE_PASS_BLOCK, 0, st>>>(
-                a.sets, a.nsets, a.set_off, a.sxy, a.sid, a.bstart, a.tchild, a.nodes, a.tref,
+                a.sets, a.nsets, a.set_off, a.sides, a.sxy, a.sid, a.bstart, a.tchild, a.nodes, a.tref,
                 a.ocnt, a.olines, a.ovf, a.dcnt, a.queue3, a.qcount3(), a.queue, a.qcount(),
                 a.stats, a.status());
         }
@@ -964,12 +992,12 @@ void launch_stage(const PipeArgs &a, hipStream_t st, int stage) {
         launch_scan(a.dcnt, T, a.del_off, a.scan_tmp, a.status(), 1, st);
         if (a.with_vertices)
             k_emit<true><<<nblk(T, EMIT_BLOCK), EMIT_BLOCK, 0, st>>>(
-                a.sets, a.nsets, a.set_off, T, a.ocnt, a.olines, a.ovf, a.pool, a.dcnt,
+                a.sets, a.nsets, a.set_off, a.sides, T, a.ocnt, a.olines, a.ovf, a.pool, a.dcnt,
                 a.cell_off, a.nbr_cap, a.del_off, a.del_cap, a.xyid, a.nbr, (Rat *)a.vtx, a.del,
                 a.status_rw());
         else
             k_emit<false><<<nblk(T, EMIT_BLOCK), EMIT_BLOCK, 0, st>>>(
-                a.sets, a.nsets, a.set_off, T, a.ocnt, a.olines, a.ovf, a.pool, a.dcnt,
+                a.sets, a.nsets, a.set_off, a.sides, T, a.ocnt, a.olines, a.ovf, a.pool, a.dcnt,
                 a.cell_off, a.nbr_cap, a.del_off, a.del_cap, a.xyid, a.nbr, nullptr, a.del,
                 a.status_rw());
         if (a.check_symmetry)

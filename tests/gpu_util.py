@@ -14,7 +14,7 @@ def say(*a):
 def assert_matches_oracle(r, ps, which=None, vertices=True):
     """Element-by-element equality of neighbour lists (and pair-form vertices) with the oracle,
     for all cells or for the listed cells."""
-    oc = cdiagram.cells(ps.x, ps.y, ps.box, which=which)
+    oc = cdiagram.cells(ps.x, ps.y, ps.box, which=which, region=getattr(ps, "region", None))
     if which is None:
         assert r.cell_off.shape[0] == ps.n + 1
         assert np.array_equal(r.cell_off.astype(np.int64), oc.off), "cell offsets"
