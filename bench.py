@@ -64,8 +64,13 @@ def measured_traffic(kernel, tag):
     return int(rec["bytes_per_launch"])
 
 
-def make_workload(n, B, seed, dist="uniform"):
+def make_workload(n, B, seed, dist="uniform", sides=0):
+    """The box [0, B]^2, or (sides > 0) a random convex polygon with at most that many vertices
+    inside it, with n sites of the distribution strictly inside."""
     import sitegen
+    if sides > 0:
+        reg = sitegen.convex_polygon(sides, B, seed=seed)
+        return sitegen.in_polygon(n, reg, seed=seed, kind=dist)
     gen = {"uniform": sitegen.uniform, "clustered": sitegen.clustered,
            "lattice": sitegen.lattice}[dist]
     return gen(n, B, seed=seed)
@@ -147,13 +152,15 @@ def cpu_baseline(ps, res, budget_s=12.0, threads=None):
     rng = np.random.default_rng(12345)
     probe = np.sort(rng.choice(ps.n, size=min(ps.n, 8 * threads), replace=False)).astype(np.int32)
     t0 = time.perf_counter()
-    cdiagram.cells(ps.x, ps.y, ps.box, which=probe, threads=threads, vertices=False)
+    cdiagram.cells(ps.x, ps.y, ps.box, which=probe, threads=threads, vertices=False,
+                   region=ps.region)
     t_probe = time.perf_counter() - t0
     per_cell = t_probe / probe.shape[0]
     m = int(min(ps.n, max(probe.shape[0], budget_s / max(per_cell, 1e-9))))
     which = np.sort(rng.choice(ps.n, size=m, replace=False)).astype(np.int32)
     t0 = time.perf_counter()
-    oc = cdiagram.cells(ps.x, ps.y, ps.box, which=which, threads=threads, vertices=True)
+    oc = cdiagram.cells(ps.x, ps.y, ps.box, which=which, threads=threads, vertices=True,
+                        region=ps.region)
     dt = time.perf_counter() - t0
     # bit-exact check of the sampled cells (neighbour lists and pair-form vertices)
     bad = 0
@@ -181,6 +188,8 @@ def main():
     ap.add_argument("--box", type=int, default=1 << 24)
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--dist", default="uniform", choices=["uniform", "clustered", "lattice"])
+    ap.add_argument("--region-sides", type=int, default=0, metavar="K",
+                    help="X a random convex polygon with at most K sides (0: the box)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--extras", action="store_true", help="also time exact-only mode")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
@@ -215,7 +224,7 @@ def main():
 
     assert torch.cuda.is_available(), "bench needs a GPU"
     dev = torch.device("cuda:0")
-    ps = make_workload(args.n, args.box, args.seed, args.dist)
+    ps = make_workload(args.n, args.box, args.seed, args.dist, args.region_sides)
     log(f"workload: n={ps.n} box={ps.box} seed={args.seed}")
     xd = torch.from_numpy(ps.x).to(dev)
     yd = torch.from_numpy(ps.y).to(dev)
@@ -240,7 +249,7 @@ def main():
 
     def step():
         return ctx.compute((xd.data_ptr(), ps.n), (yd.data_ptr(), ps.n), ps.box,
-                           device_ptrs=True)
+                           device_ptrs=True, region=ps.region)
 
     for _ in range(args.warmup):
         step()
@@ -268,7 +277,7 @@ def main():
     if not args.no_cpu:
         with vor.Context(device=0) as hctx:
             hctx.tune(*tuning)
-            res = hctx.compute(ps.x, ps.y, ps.box)
+            res = hctx.compute(ps.x, ps.y, ps.box, region=ps.region)
 
     # roofline of the dominant kernel: algorithmic flops per launch / mean launch duration.
     # The filtered grid pass and the adaptive (coordinate-rectangle) pass each run as one
@@ -283,7 +292,7 @@ def main():
         kname = "vor::k_cells_fast<256>"
     achieved = evals * FLOPS_PER_EVAL / kern_s / 1e12
     traffic = (measured_traffic(kname, f"{args.dist}_n{ps.n}")
-               if (args.box, args.seed) == (1 << 24, 2) else None)
+               if (args.box, args.seed, args.region_sides) == (1 << 24, 2, 0) else None)
     roofline = {"bound": "alu", "achieved": round(achieved, 4), "peak": PEAK_FP32_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 6),
                 "traffic": traffic, "traffic_unit": "bytes per launch",
@@ -340,9 +349,14 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+i128",
         "data": "synthetic",
-        "config": {"workload": f"single set, n={ps.n} {args.dist} sites in [1,{args.box})^2, "
-                               f"X=[0,{args.box}]^2, seed {args.seed}, FP32 filter + exact "
-                               f"fallback, vertices and Delaunay edges",
+        "config": {"workload": (f"single set, n={ps.n} {args.dist} sites in [1,{args.box})^2, "
+                                f"X=[0,{args.box}]^2, seed {args.seed}, FP32 filter + exact "
+                                f"fallback, vertices and Delaunay edges"
+                                if ps.region is None else
+                                f"single set, n={ps.n} {args.dist} sites in a convex polygon X "
+                                f"with {len(ps.region[0])} sides inside [0,{args.box}]^2, seed "
+                                f"{args.seed}, FP32 filter + exact fallback, vertices and "
+                                f"Delaunay edges"),
                    "n": ps.n, "box": args.box, "mode": "plain (single set)"},
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -134,7 +134,17 @@ struct HostSet {   // validated description of one input set
     bool device;
     uint32_t nreg = 0;     // vertices of a convex polygon X (0: X is the box)
     const int32_t *rx = nullptr, *ry = nullptr;
+    double area = 0;       // area of X
 };
+
+double region_area(uint32_t K, const int32_t *vx, const int32_t *vy) {
+    __int128 s = 0;
+    for (uint32_t e = 0; e < K; ++e) {
+        const uint32_t f = (e + 1) % K;
+        s += (__int128)vx[e] * vy[f] - (__int128)vy[e] * vx[f];
+    }
+    return (double)s / 2.0;
+}
 
 // Convex polygon X (Remark 11.1): 3..VOR_MAX_SIDES vertices, counter-clockwise, every turn
 // strictly left and the edge directions going round once (they switch between the upper and
@@ -177,6 +187,8 @@ void region_sides(uint32_t K, const int32_t *vx, const int32_t *vy, int32_t x0, 
         s.nx = (int32_t)(dy / g);
         s.ny = (int32_t)(-dx / g);
         s.c = (int64_t)s.nx * ax + (int64_t)s.ny * ay;
+        s.vx = (int32_t)ax;
+        s.vy = (int32_t)ay;
         out.push_back(s);
     }
 }
@@ -191,6 +203,7 @@ int check_set(const vor_set *s, HostSet &h) {
         h.nreg = s->nregion;
         h.rx = s->region_x;
         h.ry = s->region_y;
+        h.area = region_area(h.nreg, h.rx, h.ry);
     }
     const vor_box &b = h.box;
     if (!(b.x0 < b.x1 && b.y0 < b.y1)) return VOR_E_INVAL;
@@ -203,14 +216,18 @@ int check_set(const vor_set *s, HostSet &h) {
 }
 
 // Uniform grid of Method 11.5 with about `rho` sites per square bucket.
-void choose_grid(const vor_box &b, uint32_t n, float rho, int hw, SetDesc &d) {
+// `area`: the area of X (W H for the box; less for a polygon X, whose sites crowd a part of
+// the bounding box: the buckets are sized for the sites' density in X).
+void choose_grid(const vor_box &b, uint32_t n, float rho, int hw, SetDesc &d, double area = 0) {
     const double W = (double)b.x1 - b.x0, H = (double)b.y1 - b.y0;
-    double s = std::sqrt(W * H * (double)rho / (double)n);
+    if (!(area > 0) || area > W * H) area = W * H;
+    double s = std::sqrt(area * (double)rho / (double)n);
     long long si = (long long)std::ceil(s);
     if (si < 1) si = 1;
     long long gx = (long long)std::ceil(W / (double)si), gy = (long long)std::ceil(H / (double)si);
-    // keep the grid at most ~4 buckets per site
-    while (gx * gy > 4LL * n + 16) {
+    // keep the grid at most ~4 buckets per site of X's area (16 at most in all)
+    const long long per = (long long)std::min(16.0, std::ceil(4.0 * W * H / area));
+    while (gx * gy > per * (long long)n + 16) {
         si *= 2;
         gx = (long long)std::ceil(W / (double)si);
         gy = (long long)std::ceil(H / (double)si);
@@ -319,7 +336,8 @@ int launch(vor_ctx *ctx, Workspace &ws, const std::vector<HostSet> &sets, bool v
         d.y0 = s.box.y0;
         d.n = (int32_t)s.n;
         d.site_off = (int32_t)total;
-        choose_grid(s.box, s.n, ctx->tune.sites_per_bucket, ctx->tune.block_halfwidth, d);
+        choose_grid(s.box, s.n, ctx->tune.sites_per_bucket, ctx->tune.block_halfwidth, d,
+                    s.area);
         d.ht = ctx->tune.leaf_halfwidth;
         d.bucket_off = (int32_t)gtot;
         d.ns = (int32_t)s.nreg;
@@ -750,6 +768,7 @@ void request_loop(vor_ctx *ctx) {
                     h.nreg = (uint32_t)r->rx.size();
                     h.rx = r->rx.data();
                     h.ry = r->ry.data();
+                    h.area = region_area(h.nreg, h.rx, h.ry);
                 }
                 sets.push_back(h);
             }
@@ -946,7 +965,7 @@ int vor_submit(vor_ctx *ctx, const vor_set *set, uint64_t *ticket) {
     }
     r->t_submit = now_s();
     SetDesc d{};
-    choose_grid(h.box, set->n, ctx->tune.sites_per_bucket, ctx->tune.block_halfwidth, d);
+    choose_grid(h.box, set->n, ctx->tune.sites_per_bucket, ctx->tune.block_halfwidth, d, h.area);
     r->footprint = footprint_bytes(set->n, (uint64_t)d.gx * d.gy,
                                    !(ctx->opts.flags & VOR_NO_VERTICES));
     {

@@ -152,11 +152,56 @@ __device__ __forceinline__ float upper_of(const Cell &C, const float2 *__restric
     return key_hi_line((float)L.c, (float)L.nx, (float)L.ny, dx, dy);
 }
 
+// The side of a convex polygon X through which the ray p + t d leaves, by binary search over
+// the vertex directions w_e = v_e - p (counter-clockwise around p, p inside): the side e with
+// w_e <= d < w_{e+1} in angle measured from w_0.  FP32 cross products with w exact (|w| <=
+// 2^24) and d_s rounded: the computed cross differs from the exact one by at most 3.05u S,
+// S = |w_x d_y| + |w_y d_x|; any decision closer than 8u S returns -1 (the caller takes every
+// side).  A robust answer is exact: that side is hit first, and strictly before the others.
+__device__ __forceinline__ int exit_side(const Cell &C, float dx, float dy) {
+    const float tol = 8.0f * 5.9604644775390625e-8f;
+    const SideRel s0 = C.sides[0];
+    const int64_t w0x = (int64_t)s0.vx - C.px, w0y = (int64_t)s0.vy - C.py;
+    // half-plane of d relative to w_0: 0 for angles in [0, pi), 1 for [pi, 2 pi)
+    const float a0 = (float)w0x * dy, b0 = (float)w0y * dx;
+    const float c0 = a0 - b0;
+    if (!(fabsf(c0) > tol * (fabsf(a0) + fabsf(b0)))) return -1;
+    const int hd = c0 > 0.0f ? 0 : 1;
+    int lo = 1, hi = C.ns;   // smallest k in [1, ns] with angle(d) < angle(w_k); ns: none
+    while (lo < hi) {
+        const int k = (lo + hi) >> 1;
+        const SideRel s = C.sides[k];
+        const int64_t wx = (int64_t)s.vx - C.px, wy = (int64_t)s.vy - C.py;
+        const int64_t cw = w0x * wy - w0y * wx;   // exact
+        const int hw = (cw > 0 || (cw == 0 && w0x * wx + w0y * wy > 0)) ? 0 : 1;
+        bool before;
+        if (hd != hw) {
+            before = hd < hw;
+        } else {
+            const float a = dx * (float)wy, bb = dy * (float)wx;
+            const float cr = a - bb;   // cross(d, w_k)
+            if (!(fabsf(cr) > tol * (fabsf(a) + fabsf(bb)))) return -1;
+            before = cr > 0.0f;
+        }
+        if (before) hi = k; else lo = k + 1;
+    }
+    return lo - 1;
+}
+
 // Sides the ray can leave through: for the box at most one horizontal and one vertical side;
-// for a polygon every side (those with N.d <= 0 get +inf).
+// for a polygon the exit side (every side with N.d > 0 when the search is not robust).
 __device__ __forceinline__ void consider_sides(const Cell &C, float dx, float dy, int ex1, int ex2,
                                                Best &b) {
     if (C.ns > 0) {
+        const int e = exit_side(C, dx, dy);
+        if (e >= 0) {
+            const int code = -e - 1;
+            const Line L = side_line(C, code);
+            float k = key_lo_line((float)L.c, (float)L.nx, (float)L.ny, dx, dy);
+            k = (code == ex1 || code == ex2) ? FINF : k;
+            consider(k, code, b);
+            return;
+        }
         for (int code = -1; code >= -C.ns; --code) {
             const Line L = side_line(C, code);
             float k = key_lo_line((float)L.c, (float)L.nx, (float)L.ny, dx, dy);

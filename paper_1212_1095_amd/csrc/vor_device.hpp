@@ -57,10 +57,12 @@ struct SetDesc {
 };
 
 // Side e of a convex polygon X (code -(e+1)): N.x <= c with the primitive outward normal N,
-// x relative to the set's box origin (Remark 11.1: any convex polygon X).
+// x relative to the set's box origin (Remark 11.1: any convex polygon X); side e starts at
+// vertex (vx, vy).
 struct SideRel {
     int32_t nx, ny;
     int64_t c;
+    int32_t vx, vy;
 };
 
 // ------------------------------------------------------------------------------ FP32 filter
