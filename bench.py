@@ -190,6 +190,8 @@ def main():
     ap.add_argument("--dist", default="uniform", choices=["uniform", "clustered", "lattice"])
     ap.add_argument("--region-sides", type=int, default=0, metavar="K",
                     help="X a random convex polygon with at most K sides (0: the box)")
+    ap.add_argument("--lloyd", type=int, default=0, metavar="K",
+                    help="also time K Lloyd steps on the workload (vor_lloyd)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--extras", action="store_true", help="also time exact-only mode")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
@@ -313,6 +315,19 @@ def main():
             log("ERROR: sampled cells differ from the oracle")
 
     extra = {}
+    if args.lloyd > 0:
+        with vor.Context(device=0) as lctx:
+            lctx.tune(*tuning)
+            lctx.lloyd(ps.x, ps.y, ps.box, 1, region=ps.region)   # warm-up, graph capture
+            t0 = time.perf_counter()
+            _, _, mv = lctx.lloyd(ps.x, ps.y, ps.box, args.lloyd, region=ps.region)
+            lw = (time.perf_counter() - t0) / args.lloyd
+        extra["lloyd"] = {"steps": args.lloyd, "ms_per_step": round(1000 * lw, 3),
+                          "cells_per_s": round(ps.n / lw, 1), "moved": mv,
+                          "note": "host sites in and out once per call; every step runs the "
+                                  "whole pipeline with vertices, the centroid and collision "
+                                  "kernels, and one host round trip"}
+        log(f"lloyd: {extra['lloyd']}")
     if args.extras:
         with vor.Context(device=0, precision=vor.VOR_EXACT_ONLY,
                          flags=vor.VOR_RESULT_DEVICE | vor.VOR_TIME_KERNELS) as ectx:

@@ -193,6 +193,22 @@ typedef struct {
 int vor_set_tuning(vor_ctx *ctx, const vor_tuning *t);
 int vor_get_tuning(vor_ctx *ctx, vor_tuning *t);
 
+/* Lloyd iterations on the integer grid (centroidal Voronoi relaxation, the kind of repeated
+ * diagram computation the paper's introduction motivates the method with).  Each of `iters`
+ * steps computes the diagram of the current sites (X and validation as vor_compute) and moves
+ * every site to the rounded centroid of its cell:
+ *   the cell's vertices relative to its site p in IEEE double, u_t = fl(X_t - p D_t) / fl(D_t)
+ *   (exact integer, correctly rounded conversion); c_t = u_t.x u_{t+1}.y - u_{t+1}.x u_t.y;
+ *   A2 = sum c_t, S = sum (u_t + u_{t+1}) c_t in the stored order from t = 0 (every operation
+ *   rounded once); proposal = p + rint(S / (3 A2)) (half to even), or p when that point is not
+ *   strictly inside X; then, while a position is proposed by more than one site, every such
+ *   site whose proposal is not its current position keeps its current position.
+ * set: host arrays only (VOR_SET_DEVICE: VOR_E_INVAL).  out_x, out_y: [n] host arrays, the sites
+ * after the last step (same ids).  moved: NULL or [iters] host array, the number of sites that
+ * moved in each step.  Errors as vor_compute. */
+int vor_lloyd(vor_ctx *ctx, const vor_set *set, uint32_t iters, int32_t *out_x, int32_t *out_y,
+              uint32_t *moved);
+
 /* Diagnostic (not on the hot path): the FP32 filter keys that the cell passes compute for one
  * line and one ray direction each, so that their bounds can be checked in exact arithmetic
  * (the filter sits in front of the exact comparisons of eq. Tdef, Theorem 2.2; buckets and

@@ -92,13 +92,15 @@ def lib():
         L.vor_set_tuning.argtypes = [C.c_void_p, P(vor_tuning)]
         L.vor_get_tuning.argtypes = [C.c_void_p, P(vor_tuning)]
         L.vor_version.argtypes = []
+        L.vor_lloyd.argtypes = [C.c_void_p, P(vor_set), C.c_uint32, P(C.c_int32),
+                                P(C.c_int32), P(C.c_uint32)]
         L.vor_filter_keys.argtypes = [C.c_int32, C.c_int64, P(C.c_int32), P(C.c_int32),
                                       P(C.c_int32), P(C.c_int64), P(C.c_int64), P(C.c_float),
                                       P(C.c_int32)]
         L.vor_version.restype = C.c_char_p
         for f in ("vor_create", "vor_destroy", "vor_compute", "vor_compute_batch", "vor_submit",
                   "vor_poll", "vor_ticket_times", "vor_set_tuning", "vor_get_tuning",
-                  "vor_filter_keys"):
+                  "vor_filter_keys", "vor_lloyd"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -319,6 +321,21 @@ def vor_get_tuning(ctx):
             int(t.leaf_halfwidth), int(t.scan_path))
 
 
+def vor_lloyd(ctx, x, y, box, iters: int, region=None):
+    """`iters` Lloyd steps on the device (see include/vor.h for the exact step).  Returns
+    (x, y, moved): the final sites (int32 [n]) and the number of sites moved per step."""
+    s, keep = _make_set(x, y, box, region=region)
+    n = int(s.n)
+    ox = np.zeros(n, np.int32)
+    oy = np.zeros(n, np.int32)
+    mv = np.zeros(max(int(iters), 1), np.uint32)
+    P = C.POINTER
+    _check(lib().vor_lloyd(ctx, C.byref(s), int(iters), ox.ctypes.data_as(P(C.c_int32)),
+                           oy.ctypes.data_as(P(C.c_int32)), mv.ctypes.data_as(P(C.c_uint32))),
+           "vor_lloyd")
+    return ox, oy, mv[:int(iters)].tolist()
+
+
 def vor_filter_keys(kind, nx, ny, c, dx, dy, device: int = 0):
     """FP32 filter keys of single (line, ray) instances on the device (diagnostic entry).
 
@@ -379,6 +396,9 @@ class Context:
 
     def compute_batch(self, sets):
         return vor_compute_batch(self.h, sets)
+
+    def lloyd(self, x, y, box, iters, region=None):
+        return vor_lloyd(self.h, x, y, box, iters, region)
 
     def submit(self, x, y, box, region=None):
         return vor_submit(self.h, x, y, box, region)

@@ -84,6 +84,8 @@ struct Workspace {
     DevBuf b[B_COUNT];
     HostBuf h_in, h_small;
     std::vector<SideRel> sides_h;   // side table of the sets being launched
+    DevBuf lcx, lcy, lqx, lqy, lkeys, lcnt, lflag;   // Lloyd iterations
+    HostBuf h_lloyd;
     hipStream_t stream = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     hipEvent_t ek[NSTAGES + 1] = {};
@@ -946,6 +948,74 @@ int vor_compute_batch(vor_ctx *ctx, const vor_set *sets, uint32_t k, vor_result 
         return first_err;
     }
     for (uint32_t i = 0; i < k; ++i) outs[i] = res[i];
+    return VOR_OK;
+}
+
+int vor_lloyd(vor_ctx *ctx, const vor_set *set, uint32_t iters, int32_t *out_x, int32_t *out_y,
+              uint32_t *moved) {
+    if (!ctx || !out_x || !out_y) return VOR_E_INVAL;
+    HostSet h;
+    int rc = check_set(set, h);
+    if (rc != VOR_OK) return rc;
+    if (h.device) return VOR_E_INVAL;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (hipSetDevice(ctx->device) != hipSuccess) return VOR_E_DEVICE;
+    Workspace &ws = ctx->ws;
+    const int n = (int)h.n;
+    unsigned cap = 1024;
+    while (cap < 2u * (unsigned)n) cap <<= 1;
+    if (ws.lcx.ensure(4ull * n) != hipSuccess || ws.lcy.ensure(4ull * n) != hipSuccess ||
+        ws.lqx.ensure(4ull * n) != hipSuccess || ws.lqy.ensure(4ull * n) != hipSuccess ||
+        ws.lkeys.ensure(8ull * cap) != hipSuccess || ws.lcnt.ensure(4ull * cap) != hipSuccess ||
+        ws.lflag.ensure(16) != hipSuccess || ws.h_lloyd.ensure(16) != hipSuccess) {
+        (void)hipGetLastError();
+        return VOR_E_NOMEM;
+    }
+    int *cx = ws.lcx.as<int>(), *cy = ws.lcy.as<int>(), *qx = ws.lqx.as<int>(),
+        *qy = ws.lqy.as<int>(), *flag = ws.lflag.as<int>(), *hf = (int *)ws.h_lloyd.p;
+    hipStream_t st = ws.stream;
+    if (hipMemcpyAsync(cx, h.x, 4ull * n, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(cy, h.y, 4ull * n, hipMemcpyHostToDevice, st) != hipSuccess)
+        return VOR_E_DEVICE;
+    HostSet hd = h;
+    hd.x = cx;
+    hd.y = cy;
+    hd.device = true;
+    const std::vector<HostSet> sets{hd};
+    const bool exact_only = ctx->opts.precision == VOR_EXACT_ONLY;
+    for (uint32_t it = 0; it < iters; ++it) {
+        PipeArgs a;
+        std::vector<SetDesc> descs;
+        std::vector<int> set_off;
+        rc = launch(ctx, ws, sets, true, exact_only, false, ctx->use_graph, a, descs, set_off);
+        if (rc != VOR_OK) {
+            (void)hipStreamSynchronize(st);
+            return rc;
+        }
+        if (hipStreamSynchronize(st) != hipSuccess) return VOR_E_DEVICE;
+        rc = map_status(read_summary(ws).status);
+        if (rc != VOR_OK) return rc;
+        lloyd_propose(a, cx, cy, qx, qy, st);
+        for (int round = 0; round <= n; ++round) {
+            lloyd_round(n, qx, qy, cx, cy, ws.lkeys.as<unsigned long long>(), ws.lcnt.as<int>(),
+                        cap, flag, st);
+            if (hipMemcpyAsync(hf, flag, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+                hipStreamSynchronize(st) != hipSuccess)
+                return VOR_E_DEVICE;
+            if (!*hf) break;
+        }
+        lloyd_moved(n, qx, qy, cx, cy, flag + 1, st);
+        if (hipMemcpyAsync(hf + 1, flag + 1, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipMemcpyAsync(cx, qx, 4ull * n, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+            hipMemcpyAsync(cy, qy, 4ull * n, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            return VOR_E_DEVICE;
+        if (moved) moved[it] = (uint32_t)hf[1];
+    }
+    if (hipMemcpyAsync(out_x, cx, 4ull * n, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipMemcpyAsync(out_y, cy, 4ull * n, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return VOR_E_DEVICE;
     return VOR_OK;
 }
 

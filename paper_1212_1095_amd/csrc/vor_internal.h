@@ -75,6 +75,14 @@ struct PipeArgs {
 constexpr int NSTAGES = 5;
 void launch_stage(const PipeArgs &a, hipStream_t st, int stage);
 void launch_pipeline(const PipeArgs &a, hipStream_t st);
+// Lloyd steps (vor_lloyd.hip): proposals from the cells of the last pipeline run, one
+// collision round (flag set when a site went back), the count of sites that moved.
+void lloyd_propose(const PipeArgs &a, const int *cx, const int *cy, int *qx, int *qy,
+                   hipStream_t st);
+void lloyd_round(int n, int *qx, int *qy, const int *cx, const int *cy,
+                 unsigned long long *keys, int *cnt, unsigned cap, int *flag, hipStream_t st);
+void lloyd_moved(int n, const int *qx, const int *qy, const int *cx, const int *cy, int *moved,
+                 hipStream_t st);
 long long scan_tmp_ints(long long n);
 
 }  // namespace vor
