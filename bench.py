@@ -291,7 +291,8 @@ def main():
     else:
         evals = st.evals - st.adaptive_evals
         kern_s = float(np.mean(cells_ms)) / 1000.0
-        kname = "vor::k_cells_fast<256>"
+        kname = ("vor::k_cells_fast<256, true>" if ps.region is not None
+                 else "vor::k_cells_fast<256, false>")
     achieved = evals * FLOPS_PER_EVAL / kern_s / 1e12
     traffic = (measured_traffic(kname, f"{args.dist}_n{ps.n}")
                if (args.box, args.seed, args.region_sides) == (1 << 24, 2, 0) else None)
