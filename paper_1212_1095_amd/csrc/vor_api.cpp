@@ -118,8 +118,10 @@ struct Workspace {
         if (stream) (void)hipStreamSynchronize(stream);
         drop_graph();
         for (auto &x : b) x.release();
+        for (DevBuf *x : {&lcx, &lcy, &lqx, &lqy, &lkeys, &lcnt, &lflag}) x->release();
         h_in.release();
         h_small.release();
+        h_lloyd.release();
         if (ev0) (void)hipEventDestroy(ev0);
         if (ev1) (void)hipEventDestroy(ev1);
         for (auto &x : ek)
