@@ -10,7 +10,9 @@ Prints ONE JSON line.  Also measured, outside the timed steps:
     library's stream during the timed steps;
   * the oracle (C, exact half-plane clipping) on a bounded sample of the same cells, on the
     host cores, which also checks the sampled GPU cells bit for bit;
-  * the exact-only GPU path on the same set, and the batched and served modes (--extras).
+  * the exact-only GPU path on the same set, and the batched (two batch shapes) and served
+    modes (--extras);
+  * with --peaks only: the measured FP32 FMA rate and device copy rate of the card.
 """
 import argparse
 import json
@@ -25,7 +27,8 @@ sys.path.insert(0, ROOT)
 
 # Per candidate evaluation the FP32 filter executes these floating-point operations:
 # 2 sub (delta), mul + fma (q: 3 flops), 2 mul (delta.d products), add (den), add (|.| sum),
-# fma (upper den bound: 2 flops), rcp, mul (key) = 13 flops.
+# fma (upper den bound: 2 flops), rcp, mul (key) = 13 flops; the compiled inner loop has exactly
+# these 11 FP32 instructions per candidate (2 of them FMAs).
 FLOPS_PER_EVAL = 13
 PEAK_FP32_TFLOPS = 157.3      # MI355X FP32 vector (spec sheet)
 PEAK_FP32_NONPACKED = 78.6    # without packed FP32 (the build disables packed FP32 ops)
@@ -97,6 +100,37 @@ def bench_batched(vor, k=4096, seed=4, steps=3):
             "vertices": False}
 
 
+def bench_batched_config1(vor, k=4096, steps=3):
+    """4096 sets of the small single-set shape (n = 1000 uniform in [1, 2^16)^2, X = [0, 2^16]^2,
+    seeds 1001..5096) in one launch per stage, with vertices and Delaunay edges: cells/s and
+    the FP32 rate of the filtered cell kernel on that shape (stage events, graph per stage)."""
+    import sitegen
+    sets = [sitegen.uniform(1000, 1 << 16, seed=1001 + i) for i in range(k)]
+    args = [(s.x, s.y, s.box) for s in sets]
+    total = sum(s.n for s in sets)
+    with vor.Context(flags=vor.VOR_TIME_KERNELS) as ctx:
+        ctx.compute_batch(args)   # warm-up and graph capture
+        t0 = time.perf_counter()
+        dev, cells = [], []
+        for _ in range(steps):
+            rc, res = ctx.compute_batch(args)
+            dev.append(res[0].device_ms)
+            cells.append(res[0].cells_ms)
+        wall = (time.perf_counter() - t0) / steps
+        st = res[0].stats
+    evals = st.evals - st.adaptive_evals
+    kern_s = float(np.mean(cells)) / 1000.0
+    achieved = evals * FLOPS_PER_EVAL / kern_s / 1e12
+    return {"sets": k, "sites": int(total), "cells_per_s_end_to_end": round(total / wall, 1),
+            "cells_per_s_device": round(total / (np.mean(dev) / 1000.0), 1),
+            "device_ms": round(float(np.mean(dev)), 3), "wall_ms": round(1000 * wall, 3),
+            "cells_kernel_ms": round(1000 * kern_s, 4), "evals_per_cell": round(evals / total, 2),
+            "fp32_tflops": round(achieved, 4),
+            "frac_packed_peak": round(achieved / PEAK_FP32_TFLOPS, 6),
+            "frac_nonpacked_peak": round(achieved / PEAK_FP32_NONPACKED, 6),
+            "vertices": True}
+
+
 def bench_served(vor, count=200, seed=5, qps=None, max_n=1 << 18):
     """Poisson request stream (sizes log-uniform in [100, max_n], 45/45/10 uniform / clustered /
     lattice, in [1, 2^24)^2): p50 / p99 latency from submission to result, and cells/s."""
@@ -144,13 +178,25 @@ def bench_served(vor, count=200, seed=5, qps=None, max_n=1 << 18):
     return out
 
 
+def host_cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(ps, res, budget_s=12.0, threads=None):
     """Oracle on a bounded sample of cells; returns (cells/s, cores, sample, sample_cells)."""
     from oracle import cdiagram
     if threads is None:
         threads = min(16, os.cpu_count() or 1)
     rng = np.random.default_rng(12345)
-    probe = np.sort(rng.choice(ps.n, size=min(ps.n, 8 * threads), replace=False)).astype(np.int32)
+    probe = np.sort(rng.choice(ps.n, size=min(ps.n, max(64, 8 * threads)),
+                               replace=False)).astype(np.int32)
     t0 = time.perf_counter()
     cdiagram.cells(ps.x, ps.y, ps.box, which=probe, threads=threads, vertices=False,
                    region=ps.region)
@@ -200,6 +246,8 @@ def main():
     ap.add_argument("--sites-per-bucket", type=float, default=None)
     ap.add_argument("--block-halfwidth", type=int, default=None)
     ap.add_argument("--leaf-halfwidth", type=int, default=None)
+    ap.add_argument("--peaks", action="store_true",
+                    help="measure the FP32 FMA rate and the device copy rate, print them, exit")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB mebibytes (counter calibration)")
     args = ap.parse_args()
@@ -213,6 +261,19 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes": nbytes, "launches": 3}), flush=True)
+        return
+
+    if args.peaks:
+        import paper_1212_1095_amd as vor
+        fma = vor.vor_peak_fp32(0)
+        copy = vor.vor_peak_copy(1 << 30, 0)
+        print(json.dumps({"peak_fp32_tflops_measured": round(fma, 2),
+                          "peak_fp32_tflops_published_nonpacked": PEAK_FP32_NONPACKED,
+                          "peak_fp32_tflops_published_packed": PEAK_FP32_TFLOPS,
+                          "copy_GBps_measured": round(copy, 1),
+                          "hbm_GBps_published": 8000.0,
+                          "note": "FMA loop without packed FP32 (as the cell kernels are built); "
+                                  "copy of 1 GiB, bytes read plus written"}), flush=True)
         return
 
     if args.gpus != 1:
@@ -307,10 +368,14 @@ def main():
     cpu = None
     if not args.no_cpu:
         v, cores, m, bad, dt = cpu_baseline(ps, res, args.cpu_budget)
+        v1, _, m1, _, dt1 = cpu_baseline(ps, None, min(3.0, args.cpu_budget / 4), threads=1)
         cpu = {"value": round(v, 2), "unit": "cells/s", "cores": cores, "kind": "oracle",
                "sample": f"{m} cells sampled uniformly from the same n={ps.n} set "
                          f"(exact half-plane clipping, {dt:.1f} s wall)",
-               "sampled_cells_bit_exact": m - bad, "sampled_cells_mismatch": bad}
+               "sampled_cells_bit_exact": m - bad, "sampled_cells_mismatch": bad,
+               "single_thread_value": round(v1, 2),
+               "single_thread_sample": f"{m1} cells, {dt1:.1f} s wall",
+               "host_cpu": host_cpu_model(), "host_threads_available": os.cpu_count()}
         log(f"oracle sample: {m} cells in {dt:.2f} s on {cores} threads, mismatches {bad}")
         if bad:
             log("ERROR: sampled cells differ from the oracle")
@@ -348,6 +413,9 @@ def main():
         log("batched ...")
         extra["batched"] = bench_batched(vor)
         log(f"batched: {extra['batched']}")
+        log("batched, small single-set shape ...")
+        extra["batched_small_shape"] = bench_batched_config1(vor)
+        log(f"batched, small single-set shape: {extra['batched_small_shape']}")
         log("served ...")
         extra["served"] = bench_served(vor)
         log(f"served: {extra['served']}")

@@ -231,6 +231,17 @@ int vor_filter_keys(int32_t device, int64_t n, const int32_t *kind, const int32_
                     const int32_t *ny, const int64_t *c, const int64_t *dir, float *out,
                     int32_t *sigma);
 
+/* Measured peaks of GPU `device`, for roofline figures beside the published ones (diagnostics,
+ * not part of the Voronoi computation; each call allocates and frees its own device buffers and
+ * runs on a stream of its own, so it takes a few milliseconds).
+ *   vor_peak_fp32: FP32 FMA rate in TFLOP/s (2 flops per FMA) of a register-only loop built like
+ *                  the cell kernels, without packed FP32 instructions.
+ *   vor_peak_copy: device-to-device copy of `bytes` (rounded down to 16-byte words, at least 16)
+ *                  in GB/s, bytes read plus bytes written.
+ * Both return VOR_OK, VOR_E_INVAL (null output, bytes < 16), VOR_E_NOMEM or VOR_E_DEVICE. */
+int vor_peak_fp32(int32_t device, double *tflops);
+int vor_peak_copy(int32_t device, uint64_t bytes, double *gbps);
+
 /* Version string of the library build (never NULL). */
 const char *vor_version(void);
 

@@ -11,5 +11,6 @@ from ._binding import (  # noqa: F401
     VOR_FP32_FILTERED, VorError, Result, Stats,
     lib, lib_path, vor_create, vor_destroy, vor_compute, vor_compute_batch, vor_submit,
     vor_poll, vor_result_free, vor_strerror, vor_set_tuning, vor_get_tuning, vor_ticket_times,
-    vor_version, vor_filter_keys, vor_filter_keys_words, vor_lloyd, Context,
+    vor_version, vor_filter_keys, vor_filter_keys_words, vor_lloyd, vor_peak_fp32, vor_peak_copy,
+    Context,
 )

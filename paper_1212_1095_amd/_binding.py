@@ -97,10 +97,12 @@ def lib():
         L.vor_filter_keys.argtypes = [C.c_int32, C.c_int64, P(C.c_int32), P(C.c_int32),
                                       P(C.c_int32), P(C.c_int64), P(C.c_int64), P(C.c_float),
                                       P(C.c_int32)]
+        L.vor_peak_fp32.argtypes = [C.c_int32, P(C.c_double)]
+        L.vor_peak_copy.argtypes = [C.c_int32, C.c_uint64, P(C.c_double)]
         L.vor_version.restype = C.c_char_p
         for f in ("vor_create", "vor_destroy", "vor_compute", "vor_compute_batch", "vor_submit",
                   "vor_poll", "vor_ticket_times", "vor_set_tuning", "vor_get_tuning",
-                  "vor_filter_keys", "vor_lloyd"):
+                  "vor_filter_keys", "vor_lloyd", "vor_peak_fp32", "vor_peak_copy"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -380,6 +382,20 @@ def vor_filter_keys_words(kind, nx, ny, c, d, device: int = 0):
                                  out.ctypes.data_as(P(C.c_float)),
                                  sigma.ctypes.data_as(P(C.c_int32))), "vor_filter_keys")
     return out, sigma
+
+
+def vor_peak_fp32(device: int = 0) -> float:
+    """Measured FP32 FMA rate of the device in TFLOP/s (see include/vor.h)."""
+    v = C.c_double(0.0)
+    _check(lib().vor_peak_fp32(int(device), C.byref(v)), "vor_peak_fp32")
+    return v.value
+
+
+def vor_peak_copy(nbytes: int = 1 << 30, device: int = 0) -> float:
+    """Measured device-to-device copy rate in GB/s, read plus written (see include/vor.h)."""
+    v = C.c_double(0.0)
+    _check(lib().vor_peak_copy(int(device), int(nbytes), C.byref(v)), "vor_peak_copy")
+    return v.value
 
 
 class Context:
