@@ -277,9 +277,9 @@ def main():
         return
 
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; the path shards by cell "
-                                   "ranges or sets (see the design notes), but no multi-GPU "
-                                   "run is provided", "n_gpus": args.gpus}), flush=True)
+        print(json.dumps({"error": "this benchmark runs on one GPU only; the path shards by "
+                                   "cell ranges or sets (see the design notes), but no "
+                                   "multi-GPU run is provided", "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
 
     import torch

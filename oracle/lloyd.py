@@ -1,7 +1,7 @@
 """Lloyd iterations on the integer grid -- TEST INFRASTRUCTURE ONLY.
 
 The paper motivates fast diagram computation by algorithms that recompute the diagram many
-times, centroidal Voronoi relaxation among them.  One step, as this build defines it (the paper
+times, centroidal Voronoi relaxation among them.  One step, as this library defines it (the paper
 fixes no rounding), with the cell computed by the C oracle (the plain definition):
 
 1. for each cell k with site p and vertices (X_t/D_t, Y_t/D_t) in the stored order, the vertex
