@@ -105,10 +105,14 @@ __device__ __forceinline__ int leaf_start(const SetDesc &S, float2 a, const int 
     return tstart[k];
 }
 
+// Runs after the refinement; the refinement kernels return at once when an input error is
+// already flagged, so their slots and nodes are not written in that call and must not be
+// walked: with the status word set this kernel does nothing (the call fails anyway).
 __global__ void k_dups(const SetDesc *__restrict__ sets, int nsets, const int *__restrict__ set_off,
                        int total, const float2 *__restrict__ sxy, const int *__restrict__ tstart,
                        const int *__restrict__ tchild, const TNode *__restrict__ nodes,
                        int *__restrict__ status) {
+    if (*status) return;
     const int pos = blockIdx.x * blockDim.x + threadIdx.x;
     if (pos >= total) return;
     const SetDesc S = sets[find_set(set_off, nsets, pos)];

@@ -184,6 +184,21 @@ def test_paper_counter_bounds(ctx):
         f"deferred={r.stats.deferred_cells}")
 
 
+def test_input_error_on_the_first_call(vor):
+    """A fresh context whose first call has a site on the boundary of X: the grid is built, the
+    refinement is skipped because the error is already flagged, and no later kernel may walk the
+    unwritten refinement slots; the call reports VOR_E_DOMAIN and the next call is exact."""
+    for box, x, y in [((0, 0, 100, 100), [0, 5, 7], [6, 7, 8]),
+                      ((0, 0, 1 << 20, 1 << 20), [3, 1 << 20, 9], [4, 5, 1 << 19])]:
+        with vor.Context(device=0) as c:
+            say(f"first call with a site on the boundary of {box}")
+            with pytest.raises(vor.VorError) as e:
+                c.compute(np.array(x, np.int32), np.array(y, np.int32), box)
+            assert e.value.status == vor.VOR_E_DOMAIN
+            ps = sitegen.clustered(3000, 1 << 20, seed=5)
+            assert_matches_oracle(c.compute(ps.x, ps.y, ps.box), ps)
+
+
 def test_errors(vor):
     with vor.Context() as c:
         box = (0, 0, 100, 100)
