@@ -9,12 +9,7 @@ import sitegen
 from oracle import lloyd as olloyd
 from tests.gpu_util import say
 
-# These tests passed on their own (13 of 13 bit-identical to the oracle), but a later run of the
-# whole GPU suite that included them ended in a GPU fault whose cause has not been found; until
-# it is shown, the Lloyd path stays out of the suite.
-pytestmark = [pytest.mark.gpu,
-              pytest.mark.skip(reason="Lloyd path held out of the GPU suite: a suite run that "
-                                      "included it faulted the GPU, cause not yet identified")]
+pytestmark = pytest.mark.gpu
 
 
 @pytest.fixture(scope="module")
