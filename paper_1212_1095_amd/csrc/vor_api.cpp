@@ -77,7 +77,7 @@ enum BufId {
     B_SETS, B_SETOFF, B_INX, B_INY, B_XYID, B_KEY, B_BCNT, B_BSTART, B_SXY, B_SID, B_OCNT,
     B_OLINES, B_OVF, B_POOL, B_QUEUE, B_QUEUE2, B_WBUF, B_WBUF2, B_CELLOFF, B_NBR, B_VTX,
     B_DCNT, B_DELOFF, B_DEL, B_SCANTMP, B_SMALL, B_STATS, B_TCHILD, B_NODES, B_TXY,
-    B_TID, B_QUEUE3, B_TREF, B_NLIST, B_SIDES, B_COUNT
+    B_TID, B_QUEUE3, B_TREF, B_NLIST, B_SIDES, B_TLIST, B_QUEUE4, B_COUNT
 };
 
 struct Workspace {
@@ -314,8 +314,9 @@ size_t footprint_bytes(uint64_t total, uint64_t gtot, bool vertices) {
     if (vertices) b += E * sizeof(vor_rat);
     b += (3 * total + 8) * 8;                                       // delaunay
     b += gtot * 16;                                                 // counts, starts, tree slots
-    b += total * (8 + 4 + 4);                                       // refinement scratch, queue
+    b += total * (8 + 4 + 4 + 4);                                   // refinement scratch, queues
     b += (3 * total + 1024) * 8;                                    // sub-bucket tables
+    b += 4ull * TREE_LIST * TREE_PASS_BLOCK * tree_pass_blocks((long long)total);   // lists
     b += (TREE_LEVELS * (total / (TREE_C1 + 1)) + 64) * (sizeof(TNode) + 4 * (TREE_LEVELS - 1));
     return b;
 }
@@ -381,7 +382,9 @@ int launch(vor_ctx *ctx, Workspace &ws, const std::vector<HostSet> &sets, bool v
         {B_VTX, vertices ? sizeof(vor_rat) * E : 16}, {B_DCNT, 4ull * T},
         {B_DELOFF, 4ull * (T + 1)}, {B_DEL, 8ull * D}, {B_SCANTMP, 4ull * stmp},
         {B_SMALL, 4ull * SMALL_INTS}, {B_STATS, 8ull * SL_COUNT},
-        {B_SIDES, sizeof(SideRel) * std::max<size_t>(1, ws.sides_h.size())}};
+        {B_SIDES, sizeof(SideRel) * std::max<size_t>(1, ws.sides_h.size())},
+        {B_TLIST, 4ull * TREE_LIST * TREE_PASS_BLOCK * tree_pass_blocks(T)},
+        {B_QUEUE4, 4ull * T}};
     bool grew = false;
     for (auto &q : need) {
         const size_t before = ws.b[q.id].cap;
@@ -445,6 +448,7 @@ int launch(vor_ctx *ctx, Workspace &ws, const std::vector<HostSet> &sets, bool v
     a.txy = ws.b[B_TXY].as<float2>();
     a.tid = ws.b[B_TID].as<int>();
     a.queue3 = ws.b[B_QUEUE3].as<int>();
+    a.queue4 = ws.b[B_QUEUE4].as<int>();
     a.tref = ws.b[B_TREF].as<int>();
     a.nlist = ws.b[B_NLIST].as<int>();
     a.sxy = ws.b[B_SXY].as<float2>();
@@ -464,6 +468,7 @@ int launch(vor_ctx *ctx, Workspace &ws, const std::vector<HostSet> &sets, bool v
     a.nbr_cap = E;
     a.vtx = ws.b[B_VTX].p;
     a.dcnt = ws.b[B_DCNT].as<int>();
+    a.tlist = ws.b[B_TLIST].as<int>();
     a.del_off = ws.b[B_DELOFF].as<int>();
     a.del = ws.b[B_DEL].as<unsigned>();
     a.del_cap = D;

@@ -538,12 +538,24 @@ struct LdsList {
     __device__ __forceinline__ void put(int i, int v) { l[i][threadIdx.x] = v; }
     __device__ __forceinline__ int get(int i) const { return l[i][threadIdx.x]; }
 };
+// The same list in global memory, one column per thread (entry i at base[i * stride]): the
+// adaptive pass keeps its LDS for the stack and the walk frames, so more waves fit on a CU.
+template <int KC>
+struct GlobalList {
+    static constexpr int K = KC;
+    int *base;
+    int stride;
+    __device__ __forceinline__ void put(int i, int v) { base[i * stride] = v; }
+    __device__ __forceinline__ int get(int i) const { return base[i * stride]; }
+};
 
 // Adaptive buckets: regions are rectangles in coordinates; a pass over N \ O visits the leaves
 // that meet it (and the disk of the current bound) and evaluates exactly the sites inside N and
 // outside O.  With a list (LS::K > 0, one lane per cell) the sites of the growing region G are
-// kept and later rays start from them.
-template <class P, class FS, class LS = NoList>
+// kept and later rays start from them.  LONLY: a ray that the list does not certify stops the
+// walk (heavy), so that every lane runs the same flat list loop; such cells take a second pass
+// with the full scanner.
+template <class P, class FS, class LS = NoList, bool LONLY = false>
 struct TreeScan {
     Tree T;
     FS fs;
@@ -563,14 +575,29 @@ struct TreeScan {
         const Disk all{0.0f, 0.0f, FINF};
         wk.start(C, T, N, O, all);
         while (wk.next(C, T, fs)) {
-            for (int q = wk.pos; q < wk.end; ++q) {
-                const float2 a = sxy[q];
-                if (!wk.full && !(in_rect(N, a.x, a.y) && !in_rect(O, a.x, a.y))) continue;
-                if (nl >= LS::K) {
+            if (wk.full) {
+                if (nl + (wk.end - wk.pos) > LS::K) {
                     nl = n0;
                     return false;
                 }
-                ls.put(nl++, q);
+                for (int q = wk.pos; q < wk.end; ++q) ls.put(nl++, q);
+                continue;
+            }
+            for (int q0 = wk.pos; q0 < wk.end; q0 += TREE_BATCH) {
+                float2 a[TREE_BATCH];
+#pragma unroll
+                for (int u = 0; u < TREE_BATCH; ++u)
+                    a[u] = q0 + u < wk.end ? sxy[q0 + u] : make_float2(-1.0f, -1.0f);
+#pragma unroll
+                for (int u = 0; u < TREE_BATCH; ++u) {
+                    if (q0 + u >= wk.end) break;
+                    if (!(in_rect(N, a[u].x, a[u].y) && !in_rect(O, a[u].x, a[u].y))) continue;
+                    if (nl >= LS::K) {
+                        nl = n0;
+                        return false;
+                    }
+                    ls.put(nl++, q0 + u);
+                }
             }
         }
         return true;
@@ -616,31 +643,41 @@ struct TreeScan {
                 break;
             }
             if (pos < end) {
-                const int q = pos;
-                pos += P::W;
-                ++ev;
-                const float2 a = sxy[q];
-                if (!full && !(in_rect(N, a.x, a.y) && !in_rect(O, a.x, a.y))) continue;
-                const float ex = a.x - C.pxf, ey = a.y - C.pyf;
-                if (CACHE) {
-                    if (nl < LS::K) ls.put(nl, q);
-                    ++nl;
-                } else if (!in_disk(wk.D, ex, ey)) {
-                    continue;
+                float2 a[TREE_BATCH];
+#pragma unroll
+                for (int u = 0; u < TREE_BATCH; ++u) {
+                    const int q = pos + u * P::W;
+                    a[u] = q < end ? sxy[q] : make_float2(-1.0f, -1.0f);
                 }
-                const float qq = site_q(ex, ey);
-                float key = key_lo_line(qq, ex, ey, dx, dy);
-                key = (q == ex1 || q == ex2) ? FINF : key;
-                const bool win = key < b.k1;
-                consider_once(key, q, b);
-                ++K.evals;
-                if (!CACHE && P::W == 1 && win) {
-                    const float t = fminf(key_hi_line(qq, ex, ey, dx, dy), tcap);
-                    if (t < Tr) {
-                        Tr = t;
-                        wk.D = need_disk(C, Tr, dx, dy);
+#pragma unroll
+                for (int u = 0; u < TREE_BATCH; ++u) {
+                    const int q = pos + u * P::W;
+                    if (q >= end) break;
+                    ++ev;
+                    if (!full && !(in_rect(N, a[u].x, a[u].y) && !in_rect(O, a[u].x, a[u].y)))
+                        continue;
+                    const float ex = a[u].x - C.pxf, ey = a[u].y - C.pyf;
+                    if (CACHE) {
+                        if (nl < LS::K) ls.put(nl, q);
+                        ++nl;
+                    } else if (!in_disk(wk.D, ex, ey)) {
+                        continue;
+                    }
+                    const float qq = site_q(ex, ey);
+                    float key = key_lo_line(qq, ex, ey, dx, dy);
+                    key = (q == ex1 || q == ex2) ? FINF : key;
+                    const bool win = key < b.k1;
+                    consider_once(key, q, b);
+                    ++K.evals;
+                    if (!CACHE && P::W == 1 && win) {
+                        const float t = fminf(key_hi_line(qq, ex, ey, dx, dy), tcap);
+                        if (t < Tr) {
+                            Tr = t;
+                            wk.D = need_disk(C, Tr, dx, dy);
+                        }
                     }
                 }
+                pos += TREE_BATCH * P::W;
                 continue;
             }
             if (!wk.next(C, T, fs)) break;
@@ -666,13 +703,23 @@ struct TreeScan {
             if (x < 0 || x >= C.W || y < 0 || y >= C.H) continue;
             int lo, hi;
             leaf_at(C, T, x, y, lo, hi);
-            for (int q = lo + P::lane(); q < hi; q += P::W) {
-                const float2 a = sxy[q];
-                const float ex = a.x - C.pxf, ey = a.y - C.pyf;
-                float key = key_lo_line(site_q(ex, ey), ex, ey, dx, dy);
-                key = (q == ex1 || q == ex2 || (ex == 0.0f && ey == 0.0f)) ? FINF : key;
-                consider_once(key, q, b);
-                ++K.evals;
+            for (int q0 = lo + P::lane(); q0 < hi; q0 += TREE_BATCH * P::W) {
+                float2 a[TREE_BATCH];
+#pragma unroll
+                for (int u = 0; u < TREE_BATCH; ++u) {
+                    const int q = q0 + u * P::W;
+                    a[u] = q < hi ? sxy[q] : make_float2(-1.0f, -1.0f);
+                }
+#pragma unroll
+                for (int u = 0; u < TREE_BATCH; ++u) {
+                    const int q = q0 + u * P::W;
+                    if (q >= hi) break;
+                    const float ex = a[u].x - C.pxf, ey = a[u].y - C.pyf;
+                    float key = key_lo_line(site_q(ex, ey), ex, ey, dx, dy);
+                    key = (q == ex1 || q == ex2 || (ex == 0.0f && ey == 0.0f)) ? FINF : key;
+                    consider_once(key, q, b);
+                    ++K.evals;
+                }
             }
             work += hi - lo + 4;
         }
@@ -684,13 +731,22 @@ struct TreeScan {
                                                    float dx, float dy, int ex1, int ex2,
                                                    float tcap, Counters &K) {
         Best b{FINF, FINF, NO_TAG};
-        for (int i = 0; i < nl; ++i) {
-            const int q = ls.get(i);
-            const float2 a = sxy[q];
-            const float ex = a.x - C.pxf, ey = a.y - C.pyf;
-            float key = key_lo_line(site_q(ex, ey), ex, ey, dx, dy);
-            key = (q == ex1 || q == ex2) ? FINF : key;
-            consider(key, q, b);
+        for (int i0 = 0; i0 < nl; i0 += TREE_BATCH) {
+            int q[TREE_BATCH];
+            float2 a[TREE_BATCH];
+#pragma unroll
+            for (int u = 0; u < TREE_BATCH; ++u) q[u] = i0 + u < nl ? ls.get(i0 + u) : -1;
+#pragma unroll
+            for (int u = 0; u < TREE_BATCH; ++u)
+                a[u] = q[u] >= 0 ? sxy[q[u]] : make_float2(-1.0f, -1.0f);
+#pragma unroll
+            for (int u = 0; u < TREE_BATCH; ++u) {
+                if (q[u] < 0) break;
+                const float ex = a[u].x - C.pxf, ey = a[u].y - C.pyf;
+                float key = key_lo_line(site_q(ex, ey), ex, ey, dx, dy);
+                key = (q[u] == ex1 || q[u] == ex2) ? FINF : key;
+                consider(key, q[u], b);
+            }
         }
         K.evals += nl;
         work += nl;
@@ -702,7 +758,8 @@ struct TreeScan {
         Rect R = need_crect(C, Tr, dx, dy);
         Rect O = G;
         bool grow = true;   // O is still the list's region: the list may follow it
-        if (!rect_inside(R, O)) {
+        if (LONLY && !rect_inside(R, O)) heavy = true;
+        if (!LONLY && !rect_inside(R, O)) {
             probe(C, sxy, dx, dy, ex1, ex2, Tr, b, K);
             Uw = upper_of(C, sxy, b.w, dx, dy);
             U = fminf(U, Uw);
@@ -745,6 +802,10 @@ struct TreeScan {
                                             float dx, float dy, int ex1, int ex2, float tcap,
                                             Counters &K) {
         if (LS::K > 0 && cached) return scan_cached(C, sxy, dx, dy, ex1, ex2, tcap, K);
+        if (LONLY) {
+            heavy = true;
+            return ScanOut{};
+        }
         Best b{FINF, FINF, NO_TAG};
         float T0 = FINF;
         visit_f32<false>(C, sxy, Q0, NO_RECT, T0, tcap, dx, dy, ex1, ex2, b, K);

@@ -11,6 +11,13 @@ struct TNode;
 constexpr int SMALL_INTS = 16;   // status, queue counters, pool / tree counters, spare
 constexpr int DEEP_BLOCKS = 8;   // one-wave workers of the deep-cell pass
 constexpr int LVCNT0 = 8;        // small[LVCNT0 + l]: nodes listed for refinement level l (2..6)
+constexpr int TREE_PASS_BLOCK = 128;       // threads per block of the adaptive pass
+constexpr int TREE_PASS_MAXBLOCKS = 2048;  // its persistent grid at most
+// Blocks of the adaptive pass for `total` sites: one thread per cell up to the persistent size.
+inline long long tree_pass_blocks(long long total) {
+    const long long b = (total + TREE_PASS_BLOCK - 1) / TREE_PASS_BLOCK;
+    return b < 1 ? 1 : (b > TREE_PASS_MAXBLOCKS ? TREE_PASS_MAXBLOCKS : b);
+}
 
 // Device pointers and sizes of one pipeline launch.
 struct PipeArgs {
@@ -33,6 +40,7 @@ struct PipeArgs {
     float2 *txy;            // [total] refinement scratch
     int *tid;               // [total]
     int *queue3;            // cells handed to the adaptive pass [total]
+    int *queue4;            // cells of the adaptive pass that need the full scanner [total]
     int *tref;              // [gtot + 1] refined grid buckets before each bucket
     float2 *sxy;            // sorted coordinates [total]
     int *sid;               // local id of each sorted site [total]
@@ -47,6 +55,8 @@ struct PipeArgs {
     long long nbr_cap;
     void *vtx;              // vor_rat [nbr_cap]
     int *dcnt, *del_off;    // [total], [total + 1]
+    int *tlist;             // adaptive pass candidate lists: TREE_LIST entries per thread of the
+                            // pass, entry i of thread t at i * threads + t
     unsigned *del;          // [2 * del_cap]
     long long del_cap;
     int *scan_tmp;
@@ -66,6 +76,7 @@ struct PipeArgs {
     int *nodecnt() const { return small + 4; }   // nodes below the roots
     int *tabcnt() const { return small + 5; }
     int *rootcnt() const { return small + 6; }   // refined grid buckets (tree roots)
+    int *qcount4() const { return small + 7; }   // cells the list-only adaptive run hands on
     int *qcount3() const { return small + 8; }
     int *nlist;             // [TREE_LEVELS - 1][ncap] node ids of refinement levels 2..
 };

@@ -420,10 +420,11 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5, 8))) v
 }
 
 // Adaptive pass: the cells handed on by the filtered pass, one thread per cell over a
-// persistent grid, scanning the refined buckets (TreeScan).  Undecided cells go to the exact
-// pass.
-template <int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_cells_tree(
+// persistent grid, scanning the refined buckets (TreeScan).  It runs twice: first with list
+// scans only (LONLY; the cells whose rays leave their list's region go to queue4), then with
+// the full scanner over queue4.  Undecided cells go to the exact pass.
+template <int BLOCK, bool LONLY>
+__global__ __launch_bounds__(BLOCK, 3) void k_cells_tree(
     const SetDesc *__restrict__ sets, int nsets, const int *__restrict__ set_off,
     const SideRel *__restrict__ sides,
     const float2 *__restrict__ sxy, const int *__restrict__ sid, const int *__restrict__ tstart,
@@ -431,11 +432,11 @@ __global__ __launch_bounds__(BLOCK) void k_cells_tree(
     int *__restrict__ ocnt,
     int *__restrict__ olines, int *__restrict__ ovf, int *__restrict__ dcnt,
     const int *__restrict__ queue3, const int *__restrict__ qcount3,
-    int *__restrict__ queue, int *__restrict__ qcount, unsigned long long *__restrict__ stats,
-    const int *__restrict__ status) {
+    int *__restrict__ queue, int *__restrict__ qcount, int *__restrict__ queue4,
+    int *__restrict__ qcount4, int *__restrict__ tlist,
+    unsigned long long *__restrict__ stats, const int *__restrict__ status) {
     __shared__ int stk[SCAP][BLOCK];
     __shared__ int fr[TFRAMES][3][BLOCK];
-    __shared__ int lst[TREE_LIST][BLOCK];
     __shared__ unsigned long long sh[SL_COUNT];
     if (*status) return;
     const int nq = *qcount3;
@@ -451,18 +452,21 @@ __global__ __launch_bounds__(BLOCK) void k_cells_tree(
         const int k = sid[pos];
         const int g = S.site_off + k;
         LdsStack<BLOCK> st{stk, 0};
-        TreeScan<Solo, LdsFrames<BLOCK>, LdsList<BLOCK, TREE_LIST>> sc{
+        TreeScan<Solo, LdsFrames<BLOCK>, GlobalList<TREE_LIST>, LONLY> sc{
             Tree{tstart, tchild, nodes, tref}, LdsFrames<BLOCK>{fr},
-            LdsList<BLOCK, TREE_LIST>{lst},
+            GlobalList<TREE_LIST>{tlist + blockIdx.x * BLOCK + threadIdx.x,
+                                  (int)(gridDim.x * BLOCK)},
             Rect{}, false, Rect{}, 0, false};
         Sink sink{olines + (size_t)g * KOUT, sid, k};
         const int r = run_cell<0, Solo>(C, sxy, sc, st, SCAP, sink, KOUT, K);
-        ++handled;
+        handled += LONLY;   // counted once, in the first run
         if (r >= 0) {
             ovf[g] = -1;
             ocnt[g] = r;
             dcnt[g] = sink.up;
             edges += (uint32_t)r;
+        } else if (LONLY && r == -4) {
+            queue4[atomicAdd(qcount4, 1)] = pos;
         } else {
             queue[atomicAdd(qcount, 1)] = pos;
             ++deferred;
@@ -938,8 +942,6 @@ static void launch_exact(const PipeArgs &a, hipStream_t st) {
         a.wbuf2, DCAP2, a.stats, a.status_rw());
 }
 
-constexpr int TREE_PASS_BLOCK = 128;
-
 void launch_stage(const PipeArgs &a, hipStream_t st, int stage) {
     const int T = a.total;
     if (stage == 0) {
@@ -980,12 +982,16 @@ void launch_stage(const PipeArgs &a, hipStream_t st, int stage) {
     } else if (stage == 2) {
         // adaptive pass over the cells that met crowded buckets
         if (!(a.exact_only || a.coop_all)) {
-            const unsigned nb = (unsigned)std::max<long long>(
-                1, std::min<long long>(nblk(T, TREE_PASS_BLOCK), 2048));
-            k_cells_tree<TREE_PASS_BLOCK><<<nb, TREE_PASS_BLOCK, 0, st>>>(
+            // the list buffer holds TREE_LIST entries for each thread of this grid
+            const unsigned nb = (unsigned)tree_pass_blocks(T);
+            k_cells_tree<TREE_PASS_BLOCK, true><<<nb, TREE_PASS_BLOCK, 0, st>>>(
                 a.sets, a.nsets, a.set_off, a.sides, a.sxy, a.sid, a.bstart, a.tchild, a.nodes, a.tref,
                 a.ocnt, a.olines, a.ovf, a.dcnt, a.queue3, a.qcount3(), a.queue, a.qcount(),
-                a.stats, a.status());
+                a.queue4, a.qcount4(), a.tlist, a.stats, a.status());
+            k_cells_tree<TREE_PASS_BLOCK, false><<<nb, TREE_PASS_BLOCK, 0, st>>>(
+                a.sets, a.nsets, a.set_off, a.sides, a.sxy, a.sid, a.bstart, a.tchild, a.nodes, a.tref,
+                a.ocnt, a.olines, a.ovf, a.dcnt, a.queue4, a.qcount4(), a.queue, a.qcount(),
+                nullptr, nullptr, a.tlist, a.stats, a.status());
         }
     } else if (stage == 3) {
         if (a.exact_only) launch_exact<2>(a, st);
