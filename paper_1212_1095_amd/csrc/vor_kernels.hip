@@ -422,9 +422,11 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5, 8))) v
 // Adaptive pass: the cells handed on by the filtered pass, one thread per cell over a
 // persistent grid, scanning the refined buckets (TreeScan).  It runs twice: first with list
 // scans only (LONLY; the cells whose rays leave their list's region go to queue4), then with
-// the full scanner over queue4.  Undecided cells go to the exact pass.
+// the full scanner over queue4.  The list-only run keeps every lane in the same flat loop and
+// fits four waves per SIMD (a few spills), the full run three.  Undecided cells go to the
+// exact pass.
 template <int BLOCK, bool LONLY>
-__global__ __launch_bounds__(BLOCK, 3) void k_cells_tree(
+__global__ __launch_bounds__(BLOCK, LONLY ? 4 : 3) void k_cells_tree(
     const SetDesc *__restrict__ sets, int nsets, const int *__restrict__ set_off,
     const SideRel *__restrict__ sides,
     const float2 *__restrict__ sxy, const int *__restrict__ sid, const int *__restrict__ tstart,
