@@ -191,7 +191,7 @@ __global__ __launch_bounds__(REFINE_BLOCK) void k_tree_refine(
     float2 *__restrict__ txy, int *__restrict__ tid, int *__restrict__ status) {
     __shared__ int cnt[REFINE_MAXSUB];
     __shared__ int pre[REFINE_MAXSUB + 1];
-    __shared__ int sh_tab, sh_part[REFINE_BLOCK];
+    __shared__ int sh_tab;
     __shared__ int sh_box[4];
     if (*status) return;
     const int nroot = min(*rootcnt, ncap);
@@ -248,28 +248,20 @@ __global__ __launch_bounds__(REFINE_BLOCK) void k_tree_refine(
             atomicAdd(&cnt[j2 * m + i2], 1);
         }
         __syncthreads();
-        // exclusive scan of cnt[0..mm) into pre: a chunk per thread, then the chunk sums
-        const int per = (mm + REFINE_BLOCK - 1) / REFINE_BLOCK;
-        const int c0 = threadIdx.x * per, c1 = min(c0 + per, mm);
-        int sum = 0;
-        for (int k = c0; k < c1; ++k) sum += cnt[k];
-        sh_part[threadIdx.x] = sum;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            int acc = 0;
-            for (int u = 0; u < REFINE_BLOCK; ++u) {
-                const int v = sh_part[u];
-                sh_part[u] = acc;
-                acc += v;
+        // exclusive scan of cnt[0..mm) into pre (mm <= 64): one wavefront, lane k holds cnt[k]
+        static_assert(REFINE_MAXSUB <= 64, "the sub-bucket scan uses one wavefront");
+        if (threadIdx.x < 64) {
+            const int lane = threadIdx.x;
+            const int v = lane < mm ? cnt[lane] : 0;
+            int x = v;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int y = __shfl_up(x, o, 64);
+                if (lane >= o) x += y;
             }
+            if (lane < mm) pre[lane] = x - v;
+            if (lane == 0) pre[mm] = t.cnt;
         }
-        __syncthreads();
-        int acc = sh_part[threadIdx.x];
-        for (int k = c0; k < c1; ++k) {
-            pre[k] = acc;
-            acc += cnt[k];
-        }
-        if (threadIdx.x == 0) pre[mm] = t.cnt;
         __syncthreads();
         const long long base = tab0 + tb;
         for (int k = threadIdx.x; k <= mm; k += REFINE_BLOCK) tstart[base + k] = t.a + pre[k];
