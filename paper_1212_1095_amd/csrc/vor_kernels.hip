@@ -413,10 +413,11 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5, 8))) v
 
 // Adaptive pass: the cells handed on by the filtered pass, one thread per cell over a
 // persistent grid, scanning the refined buckets (TreeScan).  It runs twice: first with list
-// scans only (LONLY; the cells whose rays leave their list's region go to queue4), then with
-// the full scanner over queue4.  The list-only run keeps every lane in the same flat loop and
-// fits four waves per SIMD (a few spills), the full run three.  Undecided cells go to the
-// exact pass.
+// scans only (LONLY; FP32 decisions only; the cells whose rays leave their list's region or
+// meet an uncertified decision go to queue4), then with the full scanner over queue4, which
+// decides uncertified rays exactly in the lane.  The list-only run keeps every lane in the same
+// flat loop and fits four waves per SIMD (a few spills), the full run three.  Cells over the
+// work budget or the stack / line capacity go to the exact pass.
 template <int BLOCK, bool LONLY>
 __global__ __launch_bounds__(BLOCK, LONLY ? 4 : 3) void k_cells_tree(
     const SetDesc *__restrict__ sets, int nsets, const int *__restrict__ set_off,
@@ -452,14 +453,14 @@ __global__ __launch_bounds__(BLOCK, LONLY ? 4 : 3) void k_cells_tree(
                                   (int)(gridDim.x * BLOCK)},
             Rect{}, false, Rect{}, 0, false};
         Sink sink{olines + (size_t)g * KOUT, sid, k};
-        const int r = run_cell<0, Solo>(C, sxy, sc, st, SCAP, sink, KOUT, K);
+        const int r = run_cell<LONLY ? 0 : 1, Solo>(C, sxy, sc, st, SCAP, sink, KOUT, K);
         handled += LONLY;   // counted once, in the first run
         if (r >= 0) {
             ovf[g] = -1;
             ocnt[g] = r;
             dcnt[g] = sink.up;
             edges += (uint32_t)r;
-        } else if (LONLY && r == -4) {
+        } else if (LONLY && (r == -4 || r == -1)) {
             queue4[atomicAdd(qcount4, 1)] = pos;
         } else {
             queue[atomicAdd(qcount, 1)] = pos;
