@@ -418,6 +418,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5, 8))) v
 // decides uncertified rays exactly in the lane.  The list-only run keeps every lane in the same
 // flat loop and fits four waves per SIMD (a few spills), the full run three.  Cells over the
 // work budget or the stack / line capacity go to the exact pass.
+// Below this many handed-over cells the adaptive pass is one full run: two short runs would
+// each cost the latency of their slowest lane (a polygon with 6.5k handed-over cells: 4.2 ms in
+// two runs, 1.7 ms in one), while a large hand-over gains from the list-only run.
+constexpr int TREE_SPLIT_MIN = 65536;
 template <int BLOCK, bool LONLY>
 __global__ __launch_bounds__(BLOCK, LONLY ? 4 : 3) void k_cells_tree(
     const SetDesc *__restrict__ sets, int nsets, const int *__restrict__ set_off,
@@ -434,14 +438,19 @@ __global__ __launch_bounds__(BLOCK, LONLY ? 4 : 3) void k_cells_tree(
     __shared__ int fr[TFRAMES][3][BLOCK];
     __shared__ unsigned long long sh[SL_COUNT];
     if (*status) return;
-    const int nq = *qcount3;
+    // few handed-over cells: one full run over them (two runs would add their latencies)
+    const int n3 = *qcount3;
+    const bool direct = n3 < TREE_SPLIT_MIN;
+    if (LONLY && direct) return;
+    const int nq = (LONLY || direct) ? n3 : *qcount4;
+    const int *const qin = (LONLY || direct) ? queue3 : queue4;
     if ((int)(blockIdx.x * BLOCK) >= nq) return;
     if (threadIdx.x < SL_COUNT) sh[threadIdx.x] = 0;
     __syncthreads();
     Counters K{0, 0, 0, 0, 0, 0};
     uint32_t edges = 0, deferred = 0, handled = 0;
     for (int qi = blockIdx.x * BLOCK + threadIdx.x; qi < nq; qi += gridDim.x * BLOCK) {
-        const int pos = queue3[qi];
+        const int pos = qin[qi];
         const SetDesc S = sets[find_set(set_off, nsets, pos)];
         const Cell C = make_cell(S, sxy[pos], sides);
         const int k = sid[pos];
@@ -454,7 +463,7 @@ __global__ __launch_bounds__(BLOCK, LONLY ? 4 : 3) void k_cells_tree(
             Rect{}, false, Rect{}, 0, false};
         Sink sink{olines + (size_t)g * KOUT, sid, k};
         const int r = run_cell<LONLY ? 0 : 1, Solo>(C, sxy, sc, st, SCAP, sink, KOUT, K);
-        handled += LONLY;   // counted once, in the first run
+        handled += LONLY || direct;   // counted once
         if (r >= 0) {
             ovf[g] = -1;
             ocnt[g] = r;
@@ -985,8 +994,8 @@ void launch_stage(const PipeArgs &a, hipStream_t st, int stage) {
                 a.queue4, a.qcount4(), a.tlist, a.stats, a.status());
             k_cells_tree<TREE_PASS_BLOCK, false><<<nb, TREE_PASS_BLOCK, 0, st>>>(
                 a.sets, a.nsets, a.set_off, a.sides, a.sxy, a.sid, a.bstart, a.tchild, a.nodes, a.tref,
-                a.ocnt, a.olines, a.ovf, a.dcnt, a.queue4, a.qcount4(), a.queue, a.qcount(),
-                nullptr, nullptr, a.tlist, a.stats, a.status());
+                a.ocnt, a.olines, a.ovf, a.dcnt, a.queue3, a.qcount3(), a.queue, a.qcount(),
+                a.queue4, a.qcount4(), a.tlist, a.stats, a.status());
         }
     } else if (stage == 3) {
         if (a.exact_only) launch_exact<2>(a, st);
