@@ -290,6 +290,9 @@ struct vor_ctx {
     std::mutex mu;           // serialises vor_compute*
     bool use_graph = true;
     long long coop_below = 4096;   // sets up to this size: one wave per cell
+    // sites per admitted batch of the request loop (a request larger than this runs alone):
+    // bounds how long a request that arrives just after an admission waits for the batch ahead
+    long long serve_batch_sites = 1 << 18;
     // request loop
     Workspace rws[2];
     std::mutex qmu;
@@ -748,12 +751,16 @@ void request_loop(vor_ctx *ctx) {
                 std::lock_guard<std::mutex> lk(ctx->qmu);
                 if (ctx->stop) break;
                 size_t used = 0;
+                long long sites = 0;
                 const size_t cap = ctx->budget / 2;
                 while (!ctx->pending.empty()) {
                     auto &r = ctx->pending.front();
                     const bool alone = (r->footprint >> 62) & 1;
                     const size_t fp = r->footprint & (((size_t)1 << 62) - 1);
-                    if (!take.empty() && (alone || used + fp > cap)) break;
+                    const long long ns = (long long)r->x.size();
+                    if (!take.empty() &&
+                        (alone || used + fp > cap || sites + ns > ctx->serve_batch_sites))
+                        break;
                     if (take.empty() && fp > ctx->budget) {
                         r->status = VOR_E_NOMEM;
                         r->t_done = now_s();
@@ -762,6 +769,7 @@ void request_loop(vor_ctx *ctx) {
                     }
                     take.push_back(r);
                     used += fp;
+                    sites += ns;
                     ctx->pending.pop_front();
                     if (alone) break;
                 }
@@ -856,6 +864,7 @@ int vor_create(const vor_opts *opts, vor_ctx **out) {
     const char *g = std::getenv("VOR_NO_GRAPH");
     c->use_graph = !(g && g[0] == '1');
     if (const char *cb = std::getenv("VOR_COOP_BELOW")) c->coop_below = std::atoll(cb);
+    if (const char *sb = std::getenv("VOR_SERVE_BATCH_SITES")) c->serve_batch_sites = std::atoll(sb);
     size_t fr = 0, tot = 0;
     (void)hipMemGetInfo(&fr, &tot);
     c->budget = c->opts.hbm_budget_bytes ? c->opts.hbm_budget_bytes : (uint64_t)(tot / 4 * 3);
