@@ -282,6 +282,9 @@ struct Request {
     size_t footprint = 0;
 };
 
+// Batches of the request loop on the GPU at once (one workspace and stream each); three or four
+// gave no better latency on the mixed request stream.
+constexpr int REQ_WORKSPACES = 2;
 struct vor_ctx {
     int device = 0;
     vor_opts opts{};
@@ -294,7 +297,7 @@ struct vor_ctx {
     // bounds how long a request that arrives just after an admission waits for the batch ahead
     long long serve_batch_sites = 1 << 18;
     // request loop
-    Workspace rws[2];
+    Workspace rws[REQ_WORKSPACES];
     std::mutex qmu;
     std::condition_variable qcv;
     std::deque<std::shared_ptr<Request>> pending;
@@ -700,13 +703,18 @@ void request_loop(vor_ctx *ctx) {
         std::vector<SetDesc> descs;
         std::vector<int> set_off;
         bool busy = false;
-    } fl[2];
+    } fl[REQ_WORKSPACES];
+    auto any_busy = [&] {
+        for (const auto &f : fl)
+            if (f.busy) return true;
+        return false;
+    };
     const bool vertices = !(ctx->opts.flags & VOR_NO_VERTICES);
     const bool exact_only = ctx->opts.precision == VOR_EXACT_ONLY;
     for (;;) {
         bool did = false;
         // completions
-        for (int w = 0; w < 2; ++w) {
+        for (int w = 0; w < REQ_WORKSPACES; ++w) {
             if (!fl[w].busy) continue;
             const hipError_t q = hipStreamQuery(ctx->rws[w].stream);
             if (q == hipErrorNotReady) continue;
@@ -744,7 +752,7 @@ void request_loop(vor_ctx *ctx) {
             }
         }
         // admissions
-        for (int w = 0; w < 2; ++w) {
+        for (int w = 0; w < REQ_WORKSPACES; ++w) {
             if (fl[w].busy) continue;
             std::vector<std::shared_ptr<Request>> take;
             {
@@ -752,7 +760,7 @@ void request_loop(vor_ctx *ctx) {
                 if (ctx->stop) break;
                 size_t used = 0;
                 long long sites = 0;
-                const size_t cap = ctx->budget / 2;
+                const size_t cap = ctx->budget / REQ_WORKSPACES;
                 while (!ctx->pending.empty()) {
                     auto &r = ctx->pending.front();
                     const bool alone = (r->footprint >> 62) & 1;
@@ -805,9 +813,9 @@ void request_loop(vor_ctx *ctx) {
         }
         {
             std::unique_lock<std::mutex> lk(ctx->qmu);
-            if (ctx->stop && !fl[0].busy && !fl[1].busy) break;
+            if (ctx->stop && !any_busy()) break;
             if (!did) {
-                if (fl[0].busy || fl[1].busy)
+                if (any_busy())
                     ctx->qcv.wait_for(lk, std::chrono::microseconds(100));
                 else
                     ctx->qcv.wait_for(lk, std::chrono::milliseconds(20),
