@@ -179,7 +179,8 @@ const char *vor_strerror(int status);
  * around p's leaf bucket that the coordinate-rectangle scan takes first (0..4); scan_path:
  * VOR_PATH_GRID_FIRST (bucket-rectangle scans, cells that meet a crowded bucket move to the
  * coordinate-rectangle scan over the refined buckets) or VOR_PATH_TREE (every cell through the
- * coordinate-rectangle scan).  Results do not depend on any knob. */
+ * coordinate-rectangle scan).  Results do not depend on any knob.  A new context starts with
+ * {1.5, 256, 2, 0, VOR_PATH_GRID_FIRST}. */
 #define VOR_PATH_GRID_FIRST 0
 #define VOR_PATH_TREE 1
 typedef struct {

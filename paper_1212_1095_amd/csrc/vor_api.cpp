@@ -288,7 +288,9 @@ constexpr int REQ_WORKSPACES = 2;
 struct vor_ctx {
     int device = 0;
     vor_opts opts{};
-    vor_tuning tune{1.0f, 256, 0, 0, VOR_PATH_GRID_FIRST};
+    // the autotuned setting for uniform 2^20 sites, also the fastest measured for batches of
+    // 32..65536-site sets and of 1000-site sets
+    vor_tuning tune{1.5f, 256, 2, 0, VOR_PATH_GRID_FIRST};
     Workspace ws;            // vor_compute / vor_compute_batch
     std::mutex mu;           // serialises vor_compute*
     bool use_graph = true;
