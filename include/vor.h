@@ -180,7 +180,8 @@ const char *vor_strerror(int status);
  * VOR_PATH_GRID_FIRST (bucket-rectangle scans, cells that meet a crowded bucket move to the
  * coordinate-rectangle scan over the refined buckets) or VOR_PATH_TREE (every cell through the
  * coordinate-rectangle scan).  Results do not depend on any knob.  A new context starts with
- * {1.5, 256, 2, 0, VOR_PATH_GRID_FIRST}. */
+ * {1.5, 256, 2, 0, VOR_PATH_GRID_FIRST}, or {1.0, 256, 1, 0, VOR_PATH_GRID_FIRST} with
+ * VOR_EXACT_ONLY. */
 #define VOR_PATH_GRID_FIRST 0
 #define VOR_PATH_TREE 1
 typedef struct {

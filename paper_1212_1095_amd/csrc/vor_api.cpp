@@ -861,6 +861,9 @@ int vor_create(const vor_opts *opts, vor_ctx **out) {
         delete c;
         return VOR_E_INVAL;
     }
+    // exact-only: every cell in the wave-per-cell pass, which prefers a finer grid (36.6 against
+    // 38.9 ms for uniform 2^20 sites)
+    if (c->opts.precision == VOR_EXACT_ONLY) c->tune = vor_tuning{1.0f, 256, 1, 0, VOR_PATH_GRID_FIRST};
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || c->device < 0 || c->device >= ndev) {
         (void)hipGetLastError();
