@@ -418,10 +418,13 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5, 8))) v
 // decides uncertified rays exactly in the lane.  The list-only run keeps every lane in the same
 // flat loop and fits four waves per SIMD (a few spills), the full run three.  Cells over the
 // work budget or the stack / line capacity go to the exact pass.
-// Below this many handed-over cells the adaptive pass is one full run: two short runs would
-// each cost the latency of their slowest lane (a polygon with 6.5k handed-over cells: 4.2 ms in
-// two runs, 1.7 ms in one), while a large hand-over gains from the list-only run.
+
+// Below this many handed-over cells the adaptive pass is one full run over queue3 (the
+// list-only run returns at once): two short runs would each cost the latency of their slowest
+// lane (a polygon with 6.5k handed-over cells: 4.2 ms in two runs, 1.7 ms in one), while a large
+// hand-over gains from the list-only run.
 constexpr int TREE_SPLIT_MIN = 65536;
+
 template <int BLOCK, bool LONLY>
 __global__ __launch_bounds__(BLOCK, LONLY ? 4 : 3) void k_cells_tree(
     const SetDesc *__restrict__ sets, int nsets, const int *__restrict__ set_off,
