@@ -127,3 +127,19 @@ def test_grid_first_hands_clustered_cells_on(vor):
         r = c.compute(ps.x, ps.y, ps.box)
         assert r.stats.adaptive_cells < ps.n // 100
         assert_matches_oracle(r, ps, vertices=False)
+
+
+@pytest.mark.parametrize("dist", ["clustered", "uniform"])
+def test_two_run_adaptive_pass_full_parity(vor, dist):
+    """More than 65536 cells through the adaptive pass (every cell, 2 sites per bucket): the
+    list-only run and the full run both take part; every cell equals the oracle's."""
+    n = 90000
+    ps = (sitegen.clustered(n, 1 << 24, seed=13) if dist == "clustered"
+          else sitegen.uniform(n, 1 << 22, seed=14))
+    with vor.Context(device=0) as c:
+        c.tune(2.0, 256, 0, 0, vor.VOR_PATH_TREE)
+        say(f"[tree, two runs] {dist} n={n}")
+        r = c.compute(ps.x, ps.y, ps.box)
+        assert r.stats.adaptive_cells == n
+        assert_matches_oracle(r, ps)
+        assert symmetric(r)
