@@ -149,12 +149,15 @@ int vor_create(const vor_opts *opts, vor_ctx **out);
 /* Destroy a context: pending tickets are cancelled, their results freed. */
 int vor_destroy(vor_ctx *ctx);
 
-/* Blocking: one point set -> *out (free with vor_result_free). */
+/* Blocking: one point set -> *out (free with vor_result_free).  A set holds at most 2^27
+ * sites (VOR_E_INVAL beyond): the library's entry offsets are 32-bit, and 2^27 sites keep the
+ * bound of 10 entries per site below 2^31. */
 int vor_compute(vor_ctx *ctx, const vor_set *set, vor_result **out);
 
 /* Blocking: k independent point sets in one persistent launch per pipeline stage, the whole
  * pipeline captured once as a HIP graph and replayed.  outs[i] receives set i's result (its
- * status field carries a per-set error). */
+ * status field carries a per-set error).  The sets together hold at most 2^27 sites
+ * (VOR_E_NOMEM beyond, before any device work; split larger batches). */
 int vor_compute_batch(vor_ctx *ctx, const vor_set *sets, uint32_t k, vor_result **outs);
 
 /* Request loop: copy the set into library memory and enqueue it; returns immediately. */

@@ -197,6 +197,11 @@ void region_sides(uint32_t K, const int32_t *vx, const int32_t *vy, int32_t x0, 
     }
 }
 
+// Sites in one pipeline run (a set, a batch, or the requests admitted together).  Entry
+// offsets and the overflow pool are 32-bit: with at most 10 entries per site (the bound on a
+// cell's edges summed over the diagram), 2^27 sites keep every offset below 2^31.
+constexpr long long MAX_RUN_SITES = 1LL << 27;
+
 // Validates a set and returns the HostSet the pipeline runs (device: inputs in HBM).
 int check_set(const vor_set *s, HostSet &h) {
     if (!s || s->n == 0 || !s->x || !s->y) return VOR_E_INVAL;
@@ -215,7 +220,7 @@ int check_set(const vor_set *s, HostSet &h) {
     if (b.x0 < -lim || b.y0 < -lim || b.x1 > lim || b.y1 > lim) return VOR_E_DOMAIN;
     if ((long long)b.x1 - b.x0 > (1LL << 24) || (long long)b.y1 - b.y0 > (1LL << 24))
         return VOR_E_DOMAIN;
-    if (s->n > (1u << 27)) return VOR_E_INVAL;
+    if ((long long)s->n > MAX_RUN_SITES) return VOR_E_INVAL;
     return VOR_OK;
 }
 
@@ -877,7 +882,8 @@ int vor_create(const vor_opts *opts, vor_ctx **out) {
     const char *g = std::getenv("VOR_NO_GRAPH");
     c->use_graph = !(g && g[0] == '1');
     if (const char *cb = std::getenv("VOR_COOP_BELOW")) c->coop_below = std::atoll(cb);
-    if (const char *sb = std::getenv("VOR_SERVE_BATCH_SITES")) c->serve_batch_sites = std::atoll(sb);
+    if (const char *sb = std::getenv("VOR_SERVE_BATCH_SITES"))
+        c->serve_batch_sites = std::min(std::max(std::atoll(sb), 1LL), MAX_RUN_SITES);
     size_t fr = 0, tot = 0;
     (void)hipMemGetInfo(&fr, &tot);
     c->budget = c->opts.hbm_budget_bytes ? c->opts.hbm_budget_bytes : (uint64_t)(tot / 4 * 3);
@@ -951,7 +957,7 @@ int vor_compute_batch(vor_ctx *ctx, const vor_set *sets, uint32_t k, vor_result 
         hs.push_back(h);
         total += sets[i].n;
     }
-    if (total >= (1LL << 30)) return VOR_E_NOMEM;
+    if (total > MAX_RUN_SITES) return VOR_E_NOMEM;   // more than one run holds
     std::lock_guard<std::mutex> lk(ctx->mu);
     if (hipSetDevice(ctx->device) != hipSuccess) return VOR_E_DEVICE;
     std::vector<vor_result *> res;

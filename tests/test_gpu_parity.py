@@ -219,3 +219,22 @@ def test_errors(vor):
         # the context still works after errors
         ps = sitegen.uniform(100, 1 << 10, seed=3)
         assert_matches_oracle(c.compute(ps.x, ps.y, ps.box), ps)
+
+
+def test_site_limit_per_run(vor):
+    """Entry offsets are 32-bit: a batch whose sets hold more than 2^27 sites together is
+    refused with VOR_E_NOMEM before any device work (the sets here share one host array, which
+    is never read), and the context still works afterwards."""
+    n = 1 << 21
+    x = np.arange(1, n + 1, dtype=np.int32)
+    box = (0, 0, 1 << 24, 1 << 24)
+    with vor.Context() as c:
+        say("batch of 65 sets of 2^21 sites (2^27 + 2^21 in all)")
+        with pytest.raises(vor.VorError) as e:
+            c.compute_batch([(x, x, box)] * 65)
+        assert e.value.status == vor.VOR_E_NOMEM
+        ps = sitegen.uniform(500, 1 << 12, seed=4)
+        rc, res = c.compute_batch([(ps.x, ps.y, ps.box)] * 2)
+        assert rc == vor.VOR_OK
+        for r in res:
+            assert_matches_oracle(r, ps)
