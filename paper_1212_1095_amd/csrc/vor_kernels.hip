@@ -721,6 +721,8 @@ __device__ __forceinline__ Rat pair_vertex(const SetDesc &S, const SideRel *__re
 
 constexpr int EMIT_BLOCK = 256;   // cells per block (consecutive ids)
 constexpr int EMIT_ECAP = 2048;   // CSR entries staged per block (mean about 6 per cell)
+constexpr int EMIT_PER = EMIT_ECAP / EMIT_BLOCK;   // staged entries per thread, at most
+static_assert(EMIT_ECAP % EMIT_BLOCK == 0, "whole rounds of staged entries per thread");
 
 // Cell by cell (blocks whose entries exceed the LDS capacity: cells with very many edges).
 // Returns false, writing nothing, when the neighbours > k are not the dn the cell pass counted.
@@ -778,6 +780,7 @@ __global__ __launch_bounds__(EMIT_BLOCK) void k_emit(
     __shared__ int cdl[EMIT_BLOCK];
     __shared__ int crot[EMIT_BLOCK];
     __shared__ int cset[EMIT_BLOCK];
+    __shared__ int cso[EMIT_BLOCK];
     __shared__ int2 pc[EMIT_BLOCK];
     __shared__ int bad, stop;
     const int tid = threadIdx.x;
@@ -822,6 +825,7 @@ __global__ __launch_bounds__(EMIT_BLOCK) void k_emit(
                 crow[tid] = src;
                 cdl[tid] = (int)(dbase - D0);
                 cset[tid] = s;
+                cso[tid] = set_off[s];
                 pc[tid] = p;
                 for (int t = 0; t < m; ++t) own[lo + t] = (unsigned char)tid;
             }
@@ -839,12 +843,28 @@ __global__ __launch_bounds__(EMIT_BLOCK) void k_emit(
             atomicOr(status, ST_INTERNAL);
         return;
     }
-    // per entry: the line, and the coordinates of its site
-    for (int e = tid; e < ne; e += EMIT_BLOCK) {
-        const int o = own[e];
-        const int j = crow[o][e - clo[o]];
-        lin[e] = j;
-        if (VERT) qc[e] = j >= 0 ? xyid[set_off[cset[o]] + j] : make_int2(0, 0);
+    // per entry: the line, and the coordinates of its site.  All of a thread's line reads are
+    // issued before any is used, then all of its coordinate gathers: two round trips to memory
+    // instead of two per entry.
+    {
+        int jj[EMIT_PER];
+#pragma unroll
+        for (int i = 0; i < EMIT_PER; ++i) {
+            const int e = tid + i * EMIT_BLOCK;
+            jj[i] = 0;
+            if (e < ne) {
+                const int o = own[e];
+                jj[i] = crow[o][e - clo[o]];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < EMIT_PER; ++i) {
+            const int e = tid + i * EMIT_BLOCK;
+            if (e < ne) {
+                lin[e] = jj[i];
+                if (VERT) qc[e] = jj[i] >= 0 ? xyid[cso[own[e]] + jj[i]] : make_int2(0, 0);
+            }
+        }
     }
     __syncthreads();
     // per cell: rotation, and the count of neighbours > k against the cell pass's count
