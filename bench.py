@@ -6,12 +6,17 @@ tensors) when the timed region starts; one step = the whole device pipeline (val
 projector cells, CSR neighbour lists, pair-form vertices, Delaunay edges) through the C ABI.
 
 Prints ONE JSON line.  Also measured, outside the timed steps:
+  * every cell of the last timed step's own output, copied to the host after the timed region,
+    against the oracle's stored digests of the workload (bit_exact);
   * roofline of the dominant kernel (the filtered cell pass), timed with HIP events on the
     library's stream during the timed steps;
   * the oracle (C, exact half-plane clipping) on a bounded sample of the same cells, on the
-    host cores, which also checks the sampled GPU cells bit for bit;
-  * the exact-only GPU path on the same set, and the batched (two batch shapes) and served
-    modes (--extras);
+    host cores (cpu_baseline), which also checks the sampled cells bit for bit;
+  * "modes" (each with its own steps and timings, and its own outputs checked against the
+    oracle's digests): the exact-only GPU path on the same set; 4096 config-4 sets in one
+    batched call; 4096 sets of the small single-set shape in one batched call, with the
+    roofline of its filtered cell kernel; the config-5 request stream served by the request
+    loop (capacity, then p50 / p99 latency at 0.5 and 0.8 of it);
   * with --peaks only: the measured FP32 FMA rate and device copy rate of the card.
 """
 import argparse
@@ -33,6 +38,7 @@ FLOPS_PER_EVAL = 13
 PEAK_FP32_TFLOPS = 157.3      # MI355X FP32 vector (spec sheet)
 PEAK_FP32_NONPACKED = 78.6    # without packed FP32 (the build disables packed FP32 ops)
 HBM_PEAK_GBS = 8000.0
+ALL_MODES = ("exact", "batched", "batched1", "served")
 
 
 def log(*a):
@@ -79,102 +85,164 @@ def make_workload(n, B, seed, dist="uniform", sides=0):
     return gen(n, B, seed=seed)
 
 
-def bench_batched(vor, k=4096, seed=4, steps=3):
-    """4096 independent sets, sizes log-uniform in [32, 65536], uniform in [1, 2^20)^2, in one
-    launch per stage (graph replayed); host inputs and host results, as the batch API takes."""
-    import sitegen
-    sets = sitegen.batch_sets(k, seed, B=1 << 20, lo=32, hi=65536)
-    args = [(s.x, s.y, s.box) for s in sets]
-    total = sum(s.n for s in sets)
-    with vor.Context(flags=vor.VOR_NO_VERTICES) as ctx:
-        ctx.compute_batch(args)   # warm-up and graph capture
-        t0 = time.perf_counter()
-        dev = []
-        for _ in range(steps):
-            rc, res = ctx.compute_batch(args)
-            dev.append(res[0].device_ms)
-        wall = (time.perf_counter() - t0) / steps
-    return {"sets": k, "sites": int(total), "cells_per_s_end_to_end": round(total / wall, 1),
-            "cells_per_s_device": round(total / (np.mean(dev) / 1000.0), 1),
-            "device_ms": round(float(np.mean(dev)), 3), "wall_ms": round(1000 * wall, 3),
-            "vertices": False}
+def golden_record(name):
+    """The stored oracle digests of a workload (tests/golden/fullsize_digests.json)."""
+    path = os.path.join(ROOT, "tests", "golden", "fullsize_digests.json")
+    try:
+        with open(path) as f:
+            return json.load(f)["configs"].get(name)
+    except (OSError, ValueError, KeyError):
+        return None
 
 
-def bench_batched_config1(vor, k=4096, steps=3):
-    """4096 sets of the small single-set shape (n = 1000 uniform in [1, 2^16)^2, X = [0, 2^16]^2,
-    seeds 1001..5096) in one launch per stage, with vertices and Delaunay edges: cells/s and
-    the FP32 rate of the filtered cell kernel on that shape (stage events, graph per stage)."""
-    import sitegen
-    sets = [sitegen.uniform(1000, 1 << 16, seed=1001 + i) for i in range(k)]
-    args = [(s.x, s.y, s.box) for s in sets]
-    total = sum(s.n for s in sets)
-    with vor.Context(flags=vor.VOR_TIME_KERNELS) as ctx:
-        ctx.compute_batch(args)   # warm-up and graph capture
+def digest_check(results, name):
+    """Every cell of `results` against the oracle's stored digests of workload `name`:
+    (checked cells, mismatch description or None); (0, reason) when nothing is stored."""
+    from oracle import golden_digests
+    gold = golden_record(name)
+    if gold is None:
+        return 0, f"no stored digests for {name}"
+    if gold["sets"] != len(results):
+        return 0, f"{name}: {len(results)} diagrams, {gold['sets']} stored"
+    dg = golden_digests.Digest()
+    for r in results:
+        vw = None if r.vtx is None else np.frombuffer(r.vtx.tobytes(), "<u8").reshape(-1, 5)
+        dg.add(r.cell_off, r.nbr, vw, r.dele)
+    got = dg.result()["sha256"]
+    kinds = [k for k in ("cell_off", "nbr", "vtx", "del")
+             if results[0].vtx is not None or k != "vtx"]
+    bad = [k for k in kinds if got[k] != gold["sha256"][k]]
+    cells = int(sum(r.n for r in results))
+    return (cells, None) if not bad else (0, f"{name}: {bad} differ from the oracle's digests")
+
+
+def bench_exact_only(vor, torch, xd, yd, ps, steps):
+    """The plain exact-only GPU path on the same HBM-resident set (every decision exact)."""
+    with vor.Context(device=0, precision=vor.VOR_EXACT_ONLY,
+                     flags=vor.VOR_RESULT_DEVICE) as ectx:
+        def step():
+            return ectx.compute((xd.data_ptr(), ps.n), (yd.data_ptr(), ps.n), ps.box,
+                                device_ptrs=True, region=ps.region)
+        for _ in range(2):
+            step()
+        torch.cuda.synchronize()
         t0 = time.perf_counter()
-        dev, cells = [], []
         for _ in range(steps):
+            er = step()
+        torch.cuda.synchronize()
+        ew = (time.perf_counter() - t0) / steps
+        host = ectx.to_host(er)
+    return ew, host, er.device_ms
+
+
+def bench_batched(vor, sets, name, steps=3, flags=0, kernel_roofline=False):
+    """Sets in one call (one launch per stage, graph replayed), host inputs and host results as
+    the batch API takes them; the last step's results are checked against the oracle's digests."""
+    args = [(s.x, s.y, s.box) for s in sets]
+    total = int(sum(s.n for s in sets))
+    with vor.Context(flags=flags) as ctx:
+        ctx.compute_batch(args)   # warm-up and graph capture
+        dev, cells, walls = [], [], []
+        for _ in range(steps):
+            t0 = time.perf_counter()
             rc, res = ctx.compute_batch(args)
+            walls.append(time.perf_counter() - t0)
+            assert rc == vor.VOR_OK, rc
             dev.append(res[0].device_ms)
             cells.append(res[0].cells_ms)
-        wall = (time.perf_counter() - t0) / steps
-        st = res[0].stats
-    evals = st.evals - st.adaptive_evals
-    kern_s = float(np.mean(cells)) / 1000.0
-    achieved = evals * FLOPS_PER_EVAL / kern_s / 1e12
-    return {"sets": k, "sites": int(total), "cells_per_s_end_to_end": round(total / wall, 1),
-            "cells_per_s_device": round(total / (np.mean(dev) / 1000.0), 1),
-            "device_ms": round(float(np.mean(dev)), 3), "wall_ms": round(1000 * wall, 3),
-            "cells_kernel_ms": round(1000 * kern_s, 4), "evals_per_cell": round(evals / total, 2),
-            "fp32_tflops": round(achieved, 4),
-            "frac_packed_peak": round(achieved / PEAK_FP32_TFLOPS, 6),
-            "frac_nonpacked_peak": round(achieved / PEAK_FP32_NONPACKED, 6),
-            "vertices": True}
+    checked, err = digest_check(res, name)
+    st = res[0].stats
+    wall = float(np.mean(walls))
+    out = {"sets": len(sets), "sites": total, "steps": steps,
+           "ms_per_step_end_to_end": round(1000 * wall, 3),
+           "device_ms_per_step": round(float(np.mean(dev)), 3),
+           "cells_per_s_end_to_end": round(total / wall, 1),
+           "cells_per_s_device": round(total / (np.mean(dev) / 1000.0), 1),
+           "vertices": not (flags & vor.VOR_NO_VERTICES),
+           "bit_exact_cells": checked, "bit_exact_error": err,
+           "fallback_rates": dict(zip(("ray_order", "vertex_in_cell"),
+                                      [round(v, 8) for v in st.fallback_rates()])),
+           "exact_decisions": st.exact_decisions}
+    if kernel_roofline:
+        evals = st.evals - st.adaptive_evals
+        kern_s = float(np.mean(cells)) / 1000.0
+        achieved = evals * FLOPS_PER_EVAL / kern_s / 1e12
+        out["roofline"] = {"bound": "alu", "achieved": round(achieved, 4),
+                           "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                           "frac": round(achieved / PEAK_FP32_TFLOPS, 6), "traffic": None,
+                           "kernel": "vor::k_cells_fast<256, false>",
+                           "kernel_ms": round(1000 * kern_s, 4),
+                           "flops_per_eval": FLOPS_PER_EVAL, "evals_per_launch": int(evals),
+                           "evals_per_cell": round(evals / total, 2),
+                           "frac_nonpacked_peak": round(achieved / PEAK_FP32_NONPACKED, 6)}
+    return out
 
 
-def bench_served(vor, count=200, seed=5, qps=None, max_n=1 << 18):
-    """Poisson request stream (sizes log-uniform in [100, max_n], 45/45/10 uniform / clustered /
-    lattice, in [1, 2^24)^2): p50 / p99 latency from submission to result, and cells/s."""
+def bench_served(vor, count=200, seed=5, hi=1 << 20):
+    """Poisson request stream (sizes log-uniform in [100, hi], 45/45/10 uniform / clustered /
+    lattice, in [1, 2^24)^2), with vertices: capacity (back to back), then p50 / p99 latency
+    from submission to result at 0.5 and 0.8 of it.  Failed requests are counted, not timed.
+    The requests with n <= 2^16 are checked against the oracle's digests on every pass."""
     import sitegen
-    reqs = sitegen.request_stream(count, qps or 1.0, seed=seed, hi=max_n)
-    with vor.Context(flags=vor.VOR_NO_VERTICES) as ctx:
-        # capacity: run the stream back to back once to size the arrival rate
-        t0 = time.perf_counter()
-        tks = [ctx.submit(r.x, r.y, r.box) for _, r in reqs]
-        pending = set(tks)
-        while pending:
+    from oracle import golden_digests
+    reqs = sitegen.request_stream(count, 1.0, seed=seed, hi=hi)
+    gold = golden_record("config5")
+    watch = set(gold.get("stream_index", [])) if gold else set()
+    total = int(sum(r.n for _, r in reqs))
+
+    def run(arrivals):
+        """Submit at the given offsets (None: all at once); returns (latencies of the OK
+        requests in s, failures, wall s, results of the watched requests in stream order)."""
+        lat, fails, kept = [], 0, {}
+        pending = {}
+        i = 0
+        t_start = time.perf_counter()
+        while i < count or pending:
+            now = time.perf_counter() - t_start
+            while i < count and (arrivals is None or arrivals[i] <= now):
+                r = reqs[i][1]
+                pending[ctx.submit(r.x, r.y, r.box)] = i
+                i += 1
             for t in list(pending):
-                st, _ = ctx.poll(t)
-                if st != vor.VOR_PENDING:
-                    pending.discard(t)
-            time.sleep(0.0005)
-        cap_s = time.perf_counter() - t0
-        total = sum(r.n for _, r in reqs)
-        rate = count / cap_s          # requests per second at saturation
-        out = {"requests": count, "sites": int(total), "capacity_req_per_s": round(rate, 1)}
+                st, res = ctx.poll(t)
+                if st == vor.VOR_PENDING:
+                    continue
+                if st == vor.VOR_OK:
+                    lat.append(res.t_done - res.t_submit)
+                    if pending[t] in watch:
+                        kept[pending[t]] = res
+                else:
+                    fails += 1
+                del pending[t]
+            time.sleep(0.0002)
+        return lat, fails, time.perf_counter() - t_start, [kept[k] for k in sorted(kept)]
+
+    def verify(kept):
+        if not watch or len(kept) != len(watch):
+            return 0, "not every watched request returned"
+        return digest_check(kept, "config5")
+
+    out = {"requests": count, "sites": total, "max_request_sites": hi, "vertices": True}
+    with vor.Context() as ctx:
+        _, fails, cap_s, kept = run(None)
+        rate = count / cap_s
+        out["capacity_req_per_s"] = round(rate, 1)
+        out["capacity_cells_per_s"] = round(total / cap_s, 1)
+        out["capacity_failed"] = fails
+        ok_cells, err = verify(kept)
         for rho in (0.5, 0.8):
             arrivals = np.array([a for a, _ in reqs]) / (rho * rate)
-            lat, t_start = [], time.perf_counter()
-            tickets, i = [], 0
-            pending = {}
-            while i < count or pending:
-                now = time.perf_counter() - t_start
-                while i < count and arrivals[i] <= now:
-                    r = reqs[i][1]
-                    pending[ctx.submit(r.x, r.y, r.box)] = i
-                    i += 1
-                for t in list(pending):
-                    st, _ = ctx.poll(t)
-                    if st != vor.VOR_PENDING:
-                        ts, ta, td = ctx.times(t) if st == vor.VOR_OK else (0, 0, 0)
-                        lat.append(td - ts)
-                        del pending[t]
-                time.sleep(0.0002)
-            wall = time.perf_counter() - t_start
-            lat_ms = 1000 * np.array(lat)
+            lat, fails, wall, kept = run(arrivals)
+            lat_ms = 1000 * np.array(lat) if lat else np.zeros(1)
+            c, e = verify(kept)
+            ok_cells, err = min(ok_cells, c), err or e
             out[f"load_{rho}"] = {"qps": round(rho * rate, 1),
                                   "p50_ms": round(float(np.percentile(lat_ms, 50)), 3),
                                   "p99_ms": round(float(np.percentile(lat_ms, 99)), 3),
-                                  "cells_per_s": round(total / wall, 1)}
+                                  "cells_per_s": round(total / wall, 1), "failed": fails,
+                                  "completed": len(lat)}
+    out["bit_exact_cells_per_pass"] = ok_cells
+    out["bit_exact_error"] = err
     return out
 
 
@@ -244,7 +312,10 @@ def main():
     ap.add_argument("--lloyd", type=int, default=0, metavar="K",
                     help="also time K Lloyd steps on the workload (vor_lloyd)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
-    ap.add_argument("--extras", action="store_true", help="also time exact-only mode")
+    ap.add_argument("--modes", default=",".join(ALL_MODES),
+                    help="comma list of the further modes timed after the plain set: exact "
+                         "(exact-only path, same set), batched (config 4), batched1 (4096 "
+                         "config-1 shaped sets), served (config 5 stream); '' for none")
     ap.add_argument("--cpu-budget", type=float, default=10.0,
                     help="wall seconds of the oracle's all-core sample (single thread: a quarter)")
     ap.add_argument("--path", default=None, choices=["grid", "tree"],
@@ -288,6 +359,11 @@ def main():
                                    "multi-GPU run is provided", "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
 
+    modes = [m for m in args.modes.split(",") if m]
+    for m in modes:
+        if m not in ALL_MODES:
+            raise SystemExit(f"unknown mode {m}; choose from {','.join(ALL_MODES)}")
+
     import torch
     import paper_1212_1095_amd as vor
 
@@ -307,7 +383,7 @@ def main():
     tuned = autotune.best_params(ps.n, args.dist)
     if tuned is not None:
         tuning = list(tuned)
-        tuning_source = "autotuned (" + os.path.basename(autotune.TABLE) + ")"
+        tuning_source = "autotuner table (" + os.path.basename(autotune.TABLE) + ")"
     for i, v in ((0, args.sites_per_bucket), (2, args.block_halfwidth), (3, args.leaf_halfwidth),
                  (4, None if args.path is None else (1 if args.path == "tree" else 0))):
         if v is not None:
@@ -339,14 +415,16 @@ def main():
         f"grid {last.grid_ms:.3f} cells {np.mean(cells_ms):.3f} adaptive {np.mean(adapt_ms):.3f} "
         f"exact {last.exact_ms:.3f} "
         f"emit {last.emit_ms:.3f} ms, graph {last.graph_replayed}; stats {st}")
+    # the last timed step's own output, copied to the host after the timed region: every cell
+    # against the oracle's digests of this workload (when stored), and the oracle sample below
+    res = ctx.to_host(last)
     ctx.close()
-
-    # host copy of one full result for the sampled bit-exact check (outside the timed region)
-    res = None
-    if not args.no_cpu:
-        with vor.Context(device=0) as hctx:
-            hctx.tune(*tuning)
-            res = hctx.compute(ps.x, ps.y, ps.box, region=ps.region)
+    default_cfg = {(1 << 20, 1 << 24, 2, "uniform", 0): "config2",
+                   (1 << 20, 1 << 24, 3, "clustered", 0): "config3",
+                   (1000, 1 << 16, 1, "uniform", 0): "config1"}
+    wname = default_cfg.get((ps.n, args.box, args.seed, args.dist, args.region_sides))
+    exact_cells, exact_err = digest_check([res], wname) if wname else (0, "no stored digests")
+    log(f"timed output vs oracle digests: {exact_cells} cells bit-exact, {exact_err or 'ok'}")
 
     # roofline of the dominant kernel: algorithmic flops per launch / mean launch duration.
     # The filtered grid pass runs as one kernel, the adaptive (coordinate-rectangle) pass as two
@@ -387,6 +465,44 @@ def main():
         if bad:
             log("ERROR: sampled cells differ from the oracle")
 
+    out_modes = {}
+    if "exact" in modes:
+        k = max(3, args.steps // 4)
+        ew, ehost, edev = bench_exact_only(vor, torch, xd, yd, ps, k)
+        c, e = digest_check([ehost], wname) if wname else (0, "no stored digests")
+        out_modes["exact_only"] = {"steps": k, "ms_per_step": round(1000 * ew, 3),
+                                   "device_ms": round(edev, 3),
+                                   "cells_per_s": round(ps.n / ew, 1),
+                                   "bit_exact_cells": c, "bit_exact_error": e,
+                                   "filtered_speedup": round((ps.n / (wall / args.steps)) /
+                                                             (ps.n / ew), 2)}
+        log(f"exact-only: {out_modes['exact_only']}")
+    if "batched" in modes:
+        import sitegen
+        sets = sitegen.batch_sets(4096, 4, B=1 << 20, lo=32, hi=65536)
+        log("batched config 4 ...")
+        out_modes["batched_config4"] = bench_batched(vor, sets, "config4")
+        out_modes["batched_config4"]["workload"] = (
+            "4096 sets, sizes log-uniform in [32,65536], uniform in [1,2^20)^2, X=[0,2^20]^2, "
+            "seed 4, FP32 filter + exact fallback, vertices and Delaunay edges")
+        log(f"batched config 4: {out_modes['batched_config4']}")
+        del sets
+    if "batched1" in modes:
+        from oracle import golden_digests
+        sets = golden_digests.config1_batch_sets()
+        log("batched config-1 shape ...")
+        out_modes["batched_config1_shape"] = bench_batched(
+            vor, sets, "config1_batch", flags=vor.VOR_TIME_KERNELS, kernel_roofline=True)
+        out_modes["batched_config1_shape"]["workload"] = (
+            "4096 sets of n=1000 uniform in [1,2^16)^2, X=[0,2^16]^2, seeds 1001..5096, FP32 "
+            "filter + exact fallback, vertices and Delaunay edges")
+        log(f"batched config-1 shape: {out_modes['batched_config1_shape']}")
+        del sets
+    if "served" in modes:
+        log("served config 5 ...")
+        out_modes["served_config5"] = bench_served(vor)
+        log(f"served config 5: {out_modes['served_config5']}")
+
     extra = {}
     if args.lloyd > 0:
         with vor.Context(device=0) as lctx:
@@ -401,32 +517,8 @@ def main():
                                   "whole pipeline with vertices, the centroid and collision "
                                   "kernels, and one host round trip"}
         log(f"lloyd: {extra['lloyd']}")
-    if args.extras:
-        with vor.Context(device=0, precision=vor.VOR_EXACT_ONLY,
-                         flags=vor.VOR_RESULT_DEVICE | vor.VOR_TIME_KERNELS) as ectx:
-            for _ in range(2):
-                ectx.compute((xd.data_ptr(), ps.n), (yd.data_ptr(), ps.n), ps.box,
-                             device_ptrs=True)
-            torch.cuda.synchronize()
-            k = max(3, args.steps // 4)
-            t0 = time.perf_counter()
-            for _ in range(k):
-                er = ectx.compute((xd.data_ptr(), ps.n), (yd.data_ptr(), ps.n), ps.box,
-                                  device_ptrs=True)
-            torch.cuda.synchronize()
-            ew = (time.perf_counter() - t0) / k
-        extra["exact_only_cells_per_s"] = round(ps.n / ew, 1)
-        extra["exact_only_ms_per_step"] = round(1000 * ew, 3)
-        log("batched ...")
-        extra["batched"] = bench_batched(vor)
-        log(f"batched: {extra['batched']}")
-        log("batched, small single-set shape ...")
-        extra["batched_small_shape"] = bench_batched_config1(vor)
-        log(f"batched, small single-set shape: {extra['batched_small_shape']}")
-        log("served ...")
-        extra["served"] = bench_served(vor)
-        log(f"served: {extra['served']}")
 
+    fr = st.fallback_rates()
     out = {
         "metric": "Voronoi cells/sec (bit-exact) plain vs batched; p50/p99 latency per request",
         "value": round(value, 1),
@@ -449,13 +541,20 @@ def main():
                                 f"{args.seed}, FP32 filter + exact fallback, vertices and "
                                 f"Delaunay edges"),
                    "n": ps.n, "box": args.box, "mode": "plain (single set)"},
+        "bit_exact": {"cells": exact_cells, "error": exact_err,
+                      "what": "the last timed step's own output, every cell, against the "
+                              "oracle's stored digests (tests/golden/fullsize_digests.json)"},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "modes": out_modes,
         "stats": {"evals_per_cell": round(st.evals / ps.n, 2),
                   "rays_per_cell": round(st.rays / ps.n, 3),
                   "nodes_per_cell": round(st.nodes / ps.n, 3),
                   "shells_per_cell": round(st.shells / ps.n, 3),
                   "exact_decisions": st.exact_decisions, "deferred_cells": st.deferred_cells,
+                  "fallback_cmp": st.fallback_cmp, "fallback_incircle": st.fallback_incircle,
+                  "fallback_rate_ray_order": round(fr[0], 9),
+                  "fallback_rate_vertex_in_cell": round(fr[1], 9),
                   "edges_per_cell": round(st.edges / ps.n, 3),
                   "device_ms": round(float(np.mean(dev_ms)), 4),
                   "adaptive_cells": st.adaptive_cells,

@@ -117,6 +117,15 @@ typedef struct {
     uint64_t adaptive_cells;  /* cells whose scans met a crowded bucket, computed again over
                                  the refined buckets (adaptive bucketing of Method 11.5)      */
     uint64_t adaptive_evals;  /* candidate evaluations of that pass (included in evals)       */
+    /* Exact fallbacks by predicate kind (exact_decisions = fallback_cmp + fallback_incircle).
+     * A plain ray's decision orders the hit parameters t_j = c_j / (N_j.d) of eq. Tdef; a
+     * vertex ray's decision is whether u = L1 ∩ L2 lies in the cell, an incircle-type test
+     * (Algorithm 1, lines Vertex / OutsideCell).  Rates: fallback_cmp / (rays + vertex_tests -
+     * vertex_rays) and fallback_incircle / vertex_rays.  With VOR_EXACT_ONLY every decision is
+     * exact and these count nothing. */
+    uint64_t fallback_cmp;      /* plain rays whose FP32 argmin was not certified             */
+    uint64_t fallback_incircle; /* vertex rays whose FP32 decision was not certified          */
+    uint64_t vertex_rays;       /* rays shot towards a candidate vertex (Den > 0)             */
 } vor_stats;
 
 /* Result of one point set.  Host memory owned by the library (device memory with
@@ -141,6 +150,8 @@ typedef struct {
     int32_t graph_replayed;    /* 1 when the pipeline ran as replayed HIP graph(s)            */
     int32_t status;            /* VOR_OK, or the error of this set inside a batch             */
     float adaptive_ms;         /* with VOR_TIME_KERNELS: the pass over refined buckets         */
+    double t_submit, t_admit, t_done; /* request loop: the request's submit / admission / done
+                                         times (seconds, monotonic clock); 0 otherwise        */
 } vor_result;
 
 /* Create a context on opts->device (NULL opts: device 0, FP32 filtered, host results). */
@@ -149,28 +160,60 @@ int vor_create(const vor_opts *opts, vor_ctx **out);
 /* Destroy a context: pending tickets are cancelled, their results freed. */
 int vor_destroy(vor_ctx *ctx);
 
-/* Blocking: one point set -> *out (free with vor_result_free).  A set holds at most 2^27
- * sites (VOR_E_INVAL beyond): the library's entry offsets are 32-bit, and 2^27 sites keep the
- * bound of 10 entries per site below 2^31. */
+/* Blocking: one point set -> *out (free with vor_result_free).  Every cell is computed on its
+ * own by the projector (Algorithm 1 with the endpoint method of Section 5 / Appendix 1 over the
+ * buckets of Method 11.5), the cells in parallel (Theorem 9.1(d)).  A set holds at most 2^27
+ * sites (VOR_E_INVAL beyond): entry offsets are 32-bit, and the entries of n sites in a K-gon
+ * number at most 6n + K - 6 (Euler's formula). */
 int vor_compute(vor_ctx *ctx, const vor_set *set, vor_result **out);
 
-/* Blocking: k independent point sets in one persistent launch per pipeline stage, the whole
- * pipeline captured once as a HIP graph and replayed.  outs[i] receives set i's result (its
- * status field carries a per-set error).  The sets together hold at most 2^27 sites
- * (VOR_E_NOMEM beyond, before any device work; split larger batches). */
+/* Blocking: k independent point sets in one launch per pipeline stage (the cells of every set
+ * of the batch in each kernel's grid, so that the cells of all sets run in parallel as
+ * Theorem 9.1(d) allows), the whole pipeline captured once as a HIP graph and replayed.
+ * outs[i] receives set i's result (its status field carries a per-set error: a set with an
+ * input error is found by running the sets one by one, and the others still succeed).  The
+ * sets together hold at most 2^27 sites (VOR_E_NOMEM beyond, before any device work; split
+ * larger batches).  Host inputs only (VOR_SET_DEVICE: VOR_E_INVAL). */
 int vor_compute_batch(vor_ctx *ctx, const vor_set *sets, uint32_t k, vor_result **outs);
 
-/* Request loop: copy the set into library memory and enqueue it; returns immediately. */
+/* Request loop (the parallel setting of Theorem 9.1(d) applied to independent requests):
+ * copy the set into library memory and enqueue it; returns immediately with a ticket.  A host
+ * thread admits queued requests in submission order into one of two device workspaces (each
+ * admitted group runs as one batched pipeline, as vor_compute_batch) while their HBM
+ * footprints (vor_footprint) and those of the batches already on the GPU fit the context's
+ * budget; two admitted groups overlap on the device.  Thread-safe.  VOR_E_INVAL for a bad set
+ * or device input (VOR_SET_DEVICE). */
 int vor_submit(vor_ctx *ctx, const vor_set *set, uint64_t *ticket);
 
-/* VOR_OK (and *out, ownership passes to the caller), VOR_PENDING, or the request's error. */
+/* VOR_OK (and *out, ownership passes to the caller; its t_* fields hold the request's latency
+ * stamps), VOR_PENDING, or the request's error (VOR_E_NOMEM: larger than the whole budget).  A
+ * ticket is consumed by the poll that returns VOR_OK or an error: the context keeps nothing of
+ * it, and later polls of it return VOR_E_TICKET.  Thread-safe. */
 int vor_poll(vor_ctx *ctx, uint64_t ticket, vor_result **out);
 
-/* Per-request latency stamps (seconds, monotonic clock): submit, admit, done. */
+/* Latency stamps (seconds, monotonic clock) of a ticket not yet consumed: submit, admission
+ * (0 while queued), done (0 while running).  VOR_E_TICKET for unknown or consumed tickets. */
 int vor_ticket_times(vor_ctx *ctx, uint64_t ticket, double *t_submit, double *t_admit,
                      double *t_done);
 
+/* Number of tickets the context holds (submitted and not yet consumed by vor_poll). */
+int vor_ticket_count(vor_ctx *ctx, uint64_t *held);
+
+/* HBM footprint in bytes that admission charges for the set under the context's options and
+ * tuning (device buffers of one pipeline run: inputs, grid, refinement, queues, the filtered
+ * pass's lines, the entry pool sized by 6n + K + 16, vertices unless VOR_NO_VERTICES, Delaunay
+ * pairs).  Errors as vor_compute's validation. */
+int vor_footprint(vor_ctx *ctx, const vor_set *set, uint64_t *bytes);
+
 void vor_result_free(vor_result *r);
+
+/* Host copy of a result whose arrays are device memory (VOR_RESULT_DEVICE, or a result struct
+ * filled with device pointers of the same layout): n, cell_off, nbr, vtx (may be NULL), m and
+ * del are read from `dev`, the arrays copied, every other field taken over.  The device arrays
+ * must still be valid (before the context's next call).  *out is host memory owned by the
+ * library until vor_result_free.  VOR_E_INVAL for null arguments, VOR_E_DEVICE on a copy error.
+ * (Section 6 representation and Section 7 Delaunay list, as vor_compute returns them.) */
+int vor_result_to_host(vor_ctx *ctx, const vor_result *dev, vor_result **out);
 
 /* Static string for a status code (never NULL). */
 const char *vor_strerror(int status);
@@ -235,6 +278,29 @@ int vor_lloyd(vor_ctx *ctx, const vor_set *set, uint32_t iters, int32_t *out_x, 
 int vor_filter_keys(int32_t device, int64_t n, const int32_t *kind, const int32_t *nx,
                     const int32_t *ny, const int64_t *c, const int64_t *dir, float *out,
                     int32_t *sigma);
+
+/* Diagnostic (not on the hot path): the candidate regions that the scans certify for one ray
+ * bound, computed by the same device functions the cell passes use, so that they can be checked
+ * in exact arithmetic against the lemma on sites in the large square (Appendix 1: every site
+ * not farther from y than p lies in the square S[y, |y - p|], hence in the integer rectangle of
+ * eq. (S_I)) for the point y = p + (T/2) d_s of Method 11.6.  Frame: coordinates relative to
+ * the box origin; the ray parameter is doubled (w = 2 (x - p) = t d_s).
+ *   geom    [7n] per instance: px, py (0 <= p <= extent), W, H (box extent, 1..2^24), s
+ *           (bucket side >= 1), gx, gy (grid, gx s >= W, gy s >= H)
+ *   dir     [4n] ray direction d as in vor_filter_keys (|component| < 2^100, d != 0)
+ *   T       [n] upper bound of the endpoint parameter in units of d_s = d 2^-sigma
+ *           (>= 0; +inf: the whole region)
+ *   z       [2n] one test point per instance (relative coordinates, |.| <= 2^25)
+ *   rects   [8n] out: the bucket rectangle bx0, bx1, by0, by1 (inclusive, clipped to the grid),
+ *           then the coordinate rectangle x0, x1, y0, y1 (inclusive, clipped to the box)
+ *   disk    [3n] out: centre (p-relative) and squared radius of the pruning disk
+ *   inside  [n] out: 1 when the disk test admits z
+ *   sigma   [n] out: the scaling exponent;  ds [2n] out: d_s as the scans round it
+ * Host arrays owned by the caller; n == 0 is a no-op.  VOR_E_INVAL for a null pointer or an
+ * argument out of range, VOR_E_NOMEM / VOR_E_DEVICE for HIP failures. */
+int vor_region_diag(int32_t device, int64_t n, const int32_t *geom, const int64_t *dir,
+                    const float *T, const int32_t *z, int32_t *rects, float *disk,
+                    int32_t *inside, int32_t *sigma, float *ds);
 
 /* Measured peaks of GPU `device`, for roofline figures beside the published ones (diagnostics,
  * not part of the Voronoi computation; each call allocates and frees its own device buffers and

@@ -90,15 +90,18 @@ class Cells:
     vx: np.ndarray | None = None   # object array of Python ints (X numerators)
     vy: np.ndarray | None = None
     vd: np.ndarray | None = None   # int64
+    vwords: np.ndarray | None = None   # uint64 [E, 5] with raw=True
 
     def lines(self, i: int) -> list:
         return self.nbr[self.off[i]:self.off[i + 1]].tolist()
 
 
 def cells(x, y, box, which=None, threads: int | None = None, vertices: bool = True,
-          region=None) -> Cells:
+          region=None, raw: bool = False) -> Cells:
     """Cells of the listed sites (all by default).  X is the box, or, when region = (vx, vy) is
-    given, that convex polygon (counter-clockwise; sides named -1, -2, ...)."""
+    given, that convex polygon (counter-clockwise; sides named -1, -2, ...).  raw: keep the
+    vertices as 64-bit words only (``vwords`` [E, 5]: X low, X high, Y low, Y high, D, the
+    little-endian layout of a pair-form vertex) instead of Python integers."""
     x = np.ascontiguousarray(x, dtype=np.int32)
     y = np.ascontiguousarray(y, dtype=np.int32)
     n = x.shape[0]
@@ -150,6 +153,15 @@ def cells(x, y, box, which=None, threads: int | None = None, vertices: bool = Tr
             r = lib().vor_oracle_vertices(n, _p(x, C.c_int32), _p(y, C.c_int32), *box, *tail)
         if r != 0:
             raise ValueError("oracle vertex error")
+        if raw:
+            w = np.empty((tot, 5), dtype=np.uint64)
+            w[:, 0] = X2[0:2 * tot:2]
+            w[:, 1] = X2[1:2 * tot:2]
+            w[:, 2] = Y2[0:2 * tot:2]
+            w[:, 3] = Y2[1:2 * tot:2]
+            w[:, 4] = D[:tot].view(np.uint64)
+            out.vwords = w
+            return out
         out.vx = limbs_to_int(X2[:2 * tot])
         out.vy = limbs_to_int(Y2[:2 * tot])
         out.vd = D[:tot].copy()

@@ -10,7 +10,9 @@ from ._binding import (  # noqa: F401
     VOR_CHECK_SYMMETRY, VOR_TIME_KERNELS, VOR_PATH_GRID_FIRST, VOR_PATH_TREE, VOR_EXACT_ONLY,
     VOR_FP32_FILTERED, VorError, Result, Stats,
     lib, lib_path, vor_create, vor_destroy, vor_compute, vor_compute_batch, vor_submit,
-    vor_poll, vor_result_free, vor_strerror, vor_set_tuning, vor_get_tuning, vor_ticket_times,
-    vor_version, vor_filter_keys, vor_filter_keys_words, vor_lloyd, vor_peak_fp32, vor_peak_copy,
+    vor_poll, vor_result_free, vor_result_to_host, vor_strerror, vor_set_tuning, vor_get_tuning,
+    vor_ticket_times, vor_ticket_count, vor_footprint,
+    vor_version, vor_filter_keys, vor_filter_keys_words, vor_region_diag, vor_lloyd,
+    vor_peak_fp32, vor_peak_copy,
     Context,
 )

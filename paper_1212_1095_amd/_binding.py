@@ -44,7 +44,8 @@ class vor_stats(C.Structure):
     _fields_ = [(k, C.c_uint64) for k in ("rays", "nodes", "evals", "exact_decisions",
                                            "deferred_cells", "asym_pairs", "shells", "edges",
                                            "vertex_tests", "adaptive_cells",
-                                           "adaptive_evals")]
+                                           "adaptive_evals", "fallback_cmp",
+                                           "fallback_incircle", "vertex_rays")]
 
 
 class vor_result(C.Structure):
@@ -53,7 +54,8 @@ class vor_result(C.Structure):
                 ("stats", vor_stats), ("device_ms", C.c_float), ("cells_ms", C.c_float),
                 ("exact_ms", C.c_float), ("grid_ms", C.c_float), ("emit_ms", C.c_float),
                 ("graph_replayed", C.c_int32), ("status", C.c_int32),
-                ("adaptive_ms", C.c_float)]
+                ("adaptive_ms", C.c_float), ("t_submit", C.c_double), ("t_admit", C.c_double),
+                ("t_done", C.c_double)]
 
 
 class vor_tuning(C.Structure):
@@ -85,7 +87,10 @@ def lib():
         L.vor_poll.argtypes = [C.c_void_p, C.c_uint64, P(P(vor_result))]
         L.vor_ticket_times.argtypes = [C.c_void_p, C.c_uint64, P(C.c_double), P(C.c_double),
                                        P(C.c_double)]
+        L.vor_ticket_count.argtypes = [C.c_void_p, P(C.c_uint64)]
+        L.vor_footprint.argtypes = [C.c_void_p, P(vor_set), P(C.c_uint64)]
         L.vor_result_free.argtypes = [P(vor_result)]
+        L.vor_result_to_host.argtypes = [C.c_void_p, P(vor_result), P(P(vor_result))]
         L.vor_result_free.restype = None
         L.vor_strerror.argtypes = [C.c_int]
         L.vor_strerror.restype = C.c_char_p
@@ -97,12 +102,17 @@ def lib():
         L.vor_filter_keys.argtypes = [C.c_int32, C.c_int64, P(C.c_int32), P(C.c_int32),
                                       P(C.c_int32), P(C.c_int64), P(C.c_int64), P(C.c_float),
                                       P(C.c_int32)]
+        L.vor_region_diag.argtypes = [C.c_int32, C.c_int64, P(C.c_int32), P(C.c_int64),
+                                      P(C.c_float), P(C.c_int32), P(C.c_int32), P(C.c_float),
+                                      P(C.c_int32), P(C.c_int32), P(C.c_float)]
         L.vor_peak_fp32.argtypes = [C.c_int32, P(C.c_double)]
         L.vor_peak_copy.argtypes = [C.c_int32, C.c_uint64, P(C.c_double)]
         L.vor_version.restype = C.c_char_p
-        for f in ("vor_create", "vor_destroy", "vor_compute", "vor_compute_batch", "vor_submit",
-                  "vor_poll", "vor_ticket_times", "vor_set_tuning", "vor_get_tuning",
-                  "vor_filter_keys", "vor_lloyd", "vor_peak_fp32", "vor_peak_copy"):
+        for f in ("vor_create", "vor_destroy", "vor_compute", "vor_result_to_host", "vor_compute_batch", "vor_submit",
+                  "vor_poll", "vor_ticket_times", "vor_ticket_count", "vor_footprint",
+                  "vor_set_tuning", "vor_get_tuning",
+                  "vor_filter_keys", "vor_region_diag", "vor_lloyd", "vor_peak_fp32",
+                  "vor_peak_copy"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -173,6 +183,15 @@ class Stats:
     vertex_tests: int
     adaptive_cells: int
     adaptive_evals: int
+    fallback_cmp: int
+    fallback_incircle: int
+    vertex_rays: int
+
+    def fallback_rates(self):
+        """Exact fallbacks per filtered decision of each kind: (ray order, vertex-in-cell)."""
+        plain = self.rays + self.vertex_tests - self.vertex_rays
+        return (self.fallback_cmp / plain if plain else 0.0,
+                self.fallback_incircle / self.vertex_rays if self.vertex_rays else 0.0)
 
 
 @dataclass
@@ -191,6 +210,9 @@ class Result:
     emit_ms: float = 0.0
     graph_replayed: int = 0
     adaptive_ms: float = 0.0
+    t_submit: float = 0.0      # request loop: latency stamps (seconds, monotonic clock)
+    t_admit: float = 0.0
+    t_done: float = 0.0
 
     def lines(self, k: int) -> list:
         return self.nbr[self.cell_off[k]:self.cell_off[k + 1]].tolist()
@@ -237,7 +259,8 @@ def _to_result(rp, device: bool = False) -> Result:
             .reshape(m, 2) if m else np.zeros((0, 2), np.uint32))
     return Result(n, off, nbr, vtx, dele, st, float(r.device_ms), int(r.status),
                   float(r.cells_ms), float(r.exact_ms), float(r.grid_ms), float(r.emit_ms),
-                  int(r.graph_replayed), float(r.adaptive_ms))
+                  int(r.graph_replayed), float(r.adaptive_ms), float(r.t_submit),
+                  float(r.t_admit), float(r.t_done))
 
 
 def vor_result_free(rp) -> None:
@@ -258,6 +281,27 @@ def vor_compute(ctx, x, y, box, device_ptrs=False, keep_raw=False, device_result
         return _to_result(rp, device_result)
     finally:
         lib().vor_result_free(rp)
+
+
+def vor_result_to_host(ctx, res: Result) -> Result:
+    """Host copy of a device-resident result (compute with VOR_RESULT_DEVICE); call it before
+    the context's next call, while the device arrays are valid."""
+    dp = res.device_ptrs
+    r = vor_result()
+    r.n = res.n
+    r.cell_off, r.nbr, r.vtx, r.del_ = dp["cell_off"], dp["nbr"], dp["vtx"], dp["del"]
+    r.m = dp["m"]
+    r.status = res.status
+    rp = C.POINTER(vor_result)()
+    _check(lib().vor_result_to_host(ctx, C.byref(r), C.byref(rp)), "vor_result_to_host")
+    try:
+        out = _to_result(rp)
+    finally:
+        lib().vor_result_free(rp)
+    out.stats, out.device_ms, out.cells_ms = res.stats, res.device_ms, res.cells_ms
+    out.exact_ms, out.grid_ms, out.emit_ms = res.exact_ms, res.grid_ms, res.emit_ms
+    out.graph_replayed, out.adaptive_ms = res.graph_replayed, res.adaptive_ms
+    return out
 
 
 def vor_compute_batch(ctx, sets):
@@ -308,6 +352,19 @@ def vor_ticket_times(ctx, ticket: int):
     _check(lib().vor_ticket_times(ctx, C.c_uint64(ticket), C.byref(a), C.byref(b), C.byref(c)),
            "vor_ticket_times")
     return a.value, b.value, c.value
+
+
+def vor_ticket_count(ctx) -> int:
+    v = C.c_uint64()
+    _check(lib().vor_ticket_count(ctx, C.byref(v)), "vor_ticket_count")
+    return int(v.value)
+
+
+def vor_footprint(ctx, x, y, box, region=None) -> int:
+    s, keep = _make_set(x, y, box, region=region)
+    v = C.c_uint64()
+    _check(lib().vor_footprint(ctx, C.byref(s), C.byref(v)), "vor_footprint")
+    return int(v.value)
 
 
 def vor_set_tuning(ctx, sites_per_bucket: float, block: int, block_halfwidth: int = 0,
@@ -384,6 +441,52 @@ def vor_filter_keys_words(kind, nx, ny, c, d, device: int = 0):
     return out, sigma
 
 
+def _dir_words(dx, dy):
+    """Exact directions (Python ints) as int64 words [n, 4]: x_hi, x_lo, y_hi, y_lo."""
+    M = (1 << 64) - 1
+
+    def split(v):
+        v = int(v)
+        lo = v & M
+        return v >> 64, lo - (1 << 64) if lo >= 1 << 63 else lo
+
+    d = np.zeros((len(dx), 4), np.int64)
+    for i in range(len(dx)):
+        d[i, 0], d[i, 1] = split(dx[i])
+        d[i, 2], d[i, 3] = split(dy[i])
+    return d
+
+
+def vor_region_diag(geom, dx, dy, T, z, device: int = 0):
+    """Candidate regions of single ray bounds on the device (diagnostic entry, see
+    include/vor.h).  geom [n, 7] (px, py, W, H, s, gx, gy); dx, dy: exact directions as Python
+    ints; T [n] float32; z [n, 2] test points.  Returns a dict of arrays: bucket_rect [n, 4],
+    coord_rect [n, 4], disk [n, 3], inside [n], sigma [n], ds [n, 2]."""
+    geom = np.ascontiguousarray(geom, np.int32).reshape(-1, 7)
+    n = geom.shape[0]
+    d = _dir_words(dx, dy)
+    T = np.ascontiguousarray(T, np.float32)
+    z = np.ascontiguousarray(z, np.int32).reshape(-1, 2)
+    if d.shape[0] != n or T.shape != (n,) or z.shape[0] != n:
+        raise ValueError("vor_region_diag: per-instance arrays of different lengths")
+    rects = np.zeros((n, 8), np.int32)
+    disk = np.zeros((n, 3), np.float32)
+    inside = np.zeros(n, np.int32)
+    sigma = np.zeros(n, np.int32)
+    ds = np.zeros((n, 2), np.float32)
+    P = C.POINTER
+    _check(lib().vor_region_diag(int(device), n, geom.ctypes.data_as(P(C.c_int32)),
+                                 d.ctypes.data_as(P(C.c_int64)), T.ctypes.data_as(P(C.c_float)),
+                                 z.ctypes.data_as(P(C.c_int32)),
+                                 rects.ctypes.data_as(P(C.c_int32)),
+                                 disk.ctypes.data_as(P(C.c_float)),
+                                 inside.ctypes.data_as(P(C.c_int32)),
+                                 sigma.ctypes.data_as(P(C.c_int32)),
+                                 ds.ctypes.data_as(P(C.c_float))), "vor_region_diag")
+    return {"bucket_rect": rects[:, :4], "coord_rect": rects[:, 4:], "disk": disk,
+            "inside": inside, "sigma": sigma, "ds": ds}
+
+
 def vor_peak_fp32(device: int = 0) -> float:
     """Measured FP32 FMA rate of the device in TFLOP/s (see include/vor.h)."""
     v = C.c_double(0.0)
@@ -413,6 +516,9 @@ class Context:
     def compute_batch(self, sets):
         return vor_compute_batch(self.h, sets)
 
+    def to_host(self, res):
+        return vor_result_to_host(self.h, res)
+
     def lloyd(self, x, y, box, iters, region=None):
         return vor_lloyd(self.h, x, y, box, iters, region)
 
@@ -424,6 +530,12 @@ class Context:
 
     def times(self, ticket):
         return vor_ticket_times(self.h, ticket)
+
+    def ticket_count(self):
+        return vor_ticket_count(self.h)
+
+    def footprint(self, x, y, box, region=None):
+        return vor_footprint(self.h, x, y, box, region)
 
     def tune(self, sites_per_bucket, block, block_halfwidth=0, leaf_halfwidth=0, scan_path=0):
         vor_set_tuning(self.h, sites_per_bucket, block, block_halfwidth, leaf_halfwidth,

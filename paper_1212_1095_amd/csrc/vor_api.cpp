@@ -20,6 +20,7 @@
 #include "vor.h"
 #include "vor_device.hpp"
 #include "vor_internal.h"
+#include "vor_plan.h"
 #include "vor_tree.hpp"
 
 using namespace vor;
@@ -73,12 +74,6 @@ struct HostBuf {   // pinned staging
     }
 };
 
-enum BufId {
-    B_SETS, B_SETOFF, B_INX, B_INY, B_XYID, B_KEY, B_BCNT, B_BSTART, B_SXY, B_SID, B_OCNT,
-    B_OLINES, B_OVF, B_POOL, B_QUEUE, B_QUEUE2, B_WBUF, B_WBUF2, B_CELLOFF, B_NBR, B_VTX,
-    B_DCNT, B_DELOFF, B_DEL, B_SCANTMP, B_SMALL, B_STATS, B_TCHILD, B_NODES, B_TXY,
-    B_TID, B_QUEUE3, B_TREF, B_NLIST, B_SIDES, B_TLIST, B_QUEUE4, B_COUNT
-};
 
 struct Workspace {
     DevBuf b[B_COUNT];
@@ -114,6 +109,13 @@ struct Workspace {
         }
         have_graph = false;
     }
+    // device and pinned buffers back to the runtime (the stream must be idle); the next launch
+    // allocates what it needs again
+    void release_buffers() {
+        drop_graph();
+        for (auto &x : b) x.release();
+        h_in.release();
+    }
     void destroy() {
         if (stream) (void)hipStreamSynchronize(stream);
         drop_graph();
@@ -131,131 +133,8 @@ struct Workspace {
     }
 };
 
-struct HostSet {   // validated description of one input set
-    uint32_t n;
-    const int32_t *x, *y;
-    vor_box box;           // X, or the bounding box of a polygon X
-    bool device;
-    uint32_t nreg = 0;     // vertices of a convex polygon X (0: X is the box)
-    const int32_t *rx = nullptr, *ry = nullptr;
-    double area = 0;       // area of X
-};
 
-double region_area(uint32_t K, const int32_t *vx, const int32_t *vy) {
-    __int128 s = 0;
-    for (uint32_t e = 0; e < K; ++e) {
-        const uint32_t f = (e + 1) % K;
-        s += (__int128)vx[e] * vy[f] - (__int128)vy[e] * vx[f];
-    }
-    return (double)s / 2.0;
-}
 
-// Convex polygon X (Remark 11.1): 3..VOR_MAX_SIDES vertices, counter-clockwise, every turn
-// strictly left and the edge directions going round once (they switch between the upper and
-// the lower half-plane exactly twice).  Writes its bounding box.
-int check_region(uint32_t K, const int32_t *vx, const int32_t *vy, vor_box &bb) {
-    if (K < 3 || K > VOR_MAX_SIDES || !vx || !vy) return VOR_E_INVAL;
-    const long long lim = 1LL << 30;
-    long long mnx = vx[0], mxx = vx[0], mny = vy[0], mxy = vy[0];
-    for (uint32_t e = 0; e < K; ++e) {
-        if (vx[e] < -lim || vx[e] > lim || vy[e] < -lim || vy[e] > lim) return VOR_E_DOMAIN;
-        mnx = std::min<long long>(mnx, vx[e]);
-        mxx = std::max<long long>(mxx, vx[e]);
-        mny = std::min<long long>(mny, vy[e]);
-        mxy = std::max<long long>(mxy, vy[e]);
-    }
-    if (mxx - mnx > (1LL << 24) || mxy - mny > (1LL << 24)) return VOR_E_DOMAIN;
-    int changes = 0;
-    for (uint32_t e = 0; e < K; ++e) {
-        const uint32_t f = (e + 1) % K, g = (e + 2) % K;
-        const long long ax = (long long)vx[f] - vx[e], ay = (long long)vy[f] - vy[e];
-        const long long bx = (long long)vx[g] - vx[f], by = (long long)vy[g] - vy[f];
-        if (ax * by - ay * bx <= 0) return VOR_E_INVAL;
-        const bool ua = ay > 0 || (ay == 0 && ax > 0), ub = by > 0 || (by == 0 && bx > 0);
-        changes += ua != ub;
-    }
-    if (changes != 2) return VOR_E_INVAL;
-    bb = vor_box{(int32_t)mnx, (int32_t)mny, (int32_t)mxx, (int32_t)mxy};
-    return VOR_OK;
-}
-
-// Side lines of a checked polygon, relative to its bounding-box origin (x0, y0): side e is
-// N.x <= c with the primitive outward normal N = (dy, -dx) / gcd.
-void region_sides(uint32_t K, const int32_t *vx, const int32_t *vy, int32_t x0, int32_t y0,
-                  std::vector<SideRel> &out) {
-    for (uint32_t e = 0; e < K; ++e) {
-        const long long ax = (long long)vx[e] - x0, ay = (long long)vy[e] - y0;
-        const long long bx = (long long)vx[(e + 1) % K] - x0, by = (long long)vy[(e + 1) % K] - y0;
-        long long dx = bx - ax, dy = by - ay, g = std::gcd(dx < 0 ? -dx : dx, dy < 0 ? -dy : dy);
-        SideRel s;
-        s.nx = (int32_t)(dy / g);
-        s.ny = (int32_t)(-dx / g);
-        s.c = (int64_t)s.nx * ax + (int64_t)s.ny * ay;
-        s.vx = (int32_t)ax;
-        s.vy = (int32_t)ay;
-        out.push_back(s);
-    }
-}
-
-// Sites in one pipeline run (a set, a batch, or the requests admitted together).  Entry
-// offsets and the overflow pool are 32-bit: with at most 10 entries per site (the bound on a
-// cell's edges summed over the diagram), 2^27 sites keep every offset below 2^31.
-constexpr long long MAX_RUN_SITES = 1LL << 27;
-
-// Validates a set and returns the HostSet the pipeline runs (device: inputs in HBM).
-int check_set(const vor_set *s, HostSet &h) {
-    if (!s || s->n == 0 || !s->x || !s->y) return VOR_E_INVAL;
-    h = HostSet{s->n, s->x, s->y, s->box, (s->flags & VOR_SET_DEVICE) != 0};
-    if (s->nregion) {
-        const int rc = check_region(s->nregion, s->region_x, s->region_y, h.box);
-        if (rc != VOR_OK) return rc;
-        h.nreg = s->nregion;
-        h.rx = s->region_x;
-        h.ry = s->region_y;
-        h.area = region_area(h.nreg, h.rx, h.ry);
-    }
-    const vor_box &b = h.box;
-    if (!(b.x0 < b.x1 && b.y0 < b.y1)) return VOR_E_INVAL;
-    const long long lim = 1LL << 30;
-    if (b.x0 < -lim || b.y0 < -lim || b.x1 > lim || b.y1 > lim) return VOR_E_DOMAIN;
-    if ((long long)b.x1 - b.x0 > (1LL << 24) || (long long)b.y1 - b.y0 > (1LL << 24))
-        return VOR_E_DOMAIN;
-    if ((long long)s->n > MAX_RUN_SITES) return VOR_E_INVAL;
-    return VOR_OK;
-}
-
-// Uniform grid of Method 11.5 with about `rho` sites per square bucket.
-// `area`: the area of X (W H for the box; less for a polygon X, whose sites crowd a part of
-// the bounding box: the buckets are sized for the sites' density in X).
-void choose_grid(const vor_box &b, uint32_t n, float rho, int hw, SetDesc &d, double area = 0) {
-    const double W = (double)b.x1 - b.x0, H = (double)b.y1 - b.y0;
-    if (!(area > 0) || area > W * H) area = W * H;
-    double s = std::sqrt(area * (double)rho / (double)n);
-    long long si = (long long)std::ceil(s);
-    if (si < 1) si = 1;
-    long long gx = (long long)std::ceil(W / (double)si), gy = (long long)std::ceil(H / (double)si);
-    // keep the grid at most ~4 buckets per site of X's area (16 at most in all)
-    const long long per = (long long)std::min(16.0, std::ceil(4.0 * W * H / area));
-    while (gx * gy > per * (long long)n + 16) {
-        si *= 2;
-        gx = (long long)std::ceil(W / (double)si);
-        gy = (long long)std::ceil(H / (double)si);
-    }
-    d.s = (int32_t)si;
-    d.gx = (int32_t)std::max(1LL, gx);
-    d.gy = (int32_t)std::max(1LL, gy);
-    // block of shells 0..h scanned first: about two site spacings in each direction
-    const double h = hw > 0 ? (double)hw : std::round(2.0 / std::sqrt((double)rho));
-    d.h = (int32_t)std::max(1.0, std::min(h, 16.0));
-}
-
-int map_status(int st) {
-    if (st & ST_DUP) return VOR_E_DUPLICATE;
-    if (st & ST_DOMAIN) return VOR_E_DOMAIN;
-    if (st & ST_CAPACITY) return VOR_E_CAPACITY;
-    if (st & ST_INTERNAL) return VOR_E_DEVICE;
-    return VOR_OK;
-}
 
 struct ResultBox {   // vor_result plus the storage it points to
     vor_result r;
@@ -285,6 +164,14 @@ struct Request {
     int status = VOR_PENDING;
     vor_result *result = nullptr;
     size_t footprint = 0;
+    bool alone = false;   // re-run by itself (an input error in its batch)
+    // the request is finished: its copied inputs are no longer needed
+    void release_inputs() {
+        std::vector<int32_t>().swap(x);
+        std::vector<int32_t>().swap(y);
+        std::vector<int32_t>().swap(rx);
+        std::vector<int32_t>().swap(ry);
+    }
 };
 
 // Batches of the request loop on the GPU at once (one workspace and stream each); three or four
@@ -318,21 +205,6 @@ struct vor_ctx {
 
 namespace {
 
-size_t footprint_bytes(uint64_t total, uint64_t gtot, bool vertices) {
-    const uint64_t E = 10 * total + 16;
-    size_t b = 0;
-    b += total * (4 + 4 + 8 + 4 + 8 + 4 + 4 + 4 + 4 + 4 + 4 + 4);   // inputs, grid, queues, counts
-    b += total * 4ull * KOUT;                                       // filtered-pass lines
-    b += E * 4 * 2;                                                 // pool, nbr
-    if (vertices) b += E * sizeof(vor_rat);
-    b += (3 * total + 8) * 8;                                       // delaunay
-    b += gtot * 16;                                                 // counts, starts, tree slots
-    b += total * (8 + 4 + 4 + 4);                                   // refinement scratch, queues
-    b += (3 * total + 1024) * 8;                                    // sub-bucket tables
-    b += 4ull * TREE_LIST * TREE_PASS_BLOCK * tree_pass_blocks((long long)total);   // lists
-    b += (TREE_LEVELS * (total / (TREE_C1 + 1)) + 64) * (sizeof(TNode) + 4 * (TREE_LEVELS - 1));
-    return b;
-}
 
 // Prepare descriptors, size the workspace and launch the pipeline on ws.stream.  Inputs are
 // either device pointers (single set, VOR_SET_DEVICE) or gathered into pinned staging and
@@ -343,70 +215,34 @@ int launch(vor_ctx *ctx, Workspace &ws, const std::vector<HostSet> &sets, bool v
     const int K = (int)sets.size();
     descs.resize(K);
     set_off.assign(K + 1, 0);
-    ws.sides_h.clear();
-    long long total = 0, gtot = 0;
+    size_t nsides = 0;
+    for (const HostSet &s : sets) nsides += s.nreg;
+    ws.sides_h.resize(nsides);
+    long long total = 0, gtot = 0, sides = 0;
+    int side_off = 0;
     for (int i = 0; i < K; ++i) {
         const HostSet &s = sets[i];
-        SetDesc &d = descs[i];
-        d.W = s.box.x1 - s.box.x0;
-        d.H = s.box.y1 - s.box.y0;
-        d.x0 = s.box.x0;
-        d.y0 = s.box.y0;
-        d.n = (int32_t)s.n;
-        d.site_off = (int32_t)total;
-        choose_grid(s.box, s.n, ctx->tune.sites_per_bucket, ctx->tune.block_halfwidth, d,
-                    s.area);
-        d.ht = ctx->tune.leaf_halfwidth;
-        d.bucket_off = (int32_t)gtot;
-        d.ns = (int32_t)s.nreg;
-        d.side_off = (int32_t)ws.sides_h.size();
-        if (s.nreg) region_sides(s.nreg, s.rx, s.ry, s.box.x0, s.box.y0, ws.sides_h);
+        sides += s.nreg ? s.nreg : 4;
+        plan_set(ctx->tune, s, total, gtot, side_off, descs[i], ws.sides_h.data());
+        side_off += (int)s.nreg;
         set_off[i] = (int)total;
         total += s.n;
-        gtot += (long long)d.gx * d.gy;
+        gtot += (long long)descs[i].gx * descs[i].gy;
     }
     set_off[K] = (int)total;
-    if (total >= (1LL << 30) || gtot >= (1LL << 30)) return VOR_E_NOMEM;
+    RunSizes z;
+    int rc = run_sizes(total, gtot, sides, K, nsides, vertices, exact_only, ctx->coop_below, z);
+    if (rc != VOR_OK) return rc;
     const long long T = total;
-    const long long E = 10 * T + 16;
-    const long long D = 3 * T + 8;
-    const bool coop_all = !exact_only && T <= ctx->coop_below;
-    // one-wave workers of the exact pass: enough to fill the GPU when every cell goes through
-    // it, fewer when it only takes the cells the filtered pass deferred
-    const int exact_blocks =
-        (int)std::max<long long>(1, std::min<long long>(exact_only || coop_all ? 8192 : 2048, T));
-    const long long stmp = scan_tmp_ints(std::max(T, gtot)) + 8;
-    // refinement: every node holds > TREE_C1 sites and the nodes of one level are disjoint;
-    // a node's table has m*m + 1 <= 2 cnt + 1 entries; a table or node overflow leaves the
-    // bucket unrefined (slower, still exact)
-    const long long ncap = std::max<long long>(64, TREE_LEVELS * (T / (TREE_C1 + 1)) + 64);
-    const long long tabcap = 3 * T + 1024;
-    struct Need { int id; size_t bytes; } need[] = {
-        {B_SETS, sizeof(SetDesc) * K}, {B_SETOFF, 4ull * (K + 1)}, {B_INX, 4ull * T},
-        {B_INY, 4ull * T}, {B_XYID, 8ull * T}, {B_KEY, 4ull * T}, {B_BCNT, 4ull * gtot},
-        {B_BSTART, 4ull * (gtot + 1 + tabcap)}, {B_TCHILD, 4ull * (gtot + 1 + tabcap)},
-        {B_NODES, sizeof(TNode) * ncap}, {B_TXY, 8ull * T}, {B_TID, 4ull * T},
-        {B_QUEUE3, 4ull * T}, {B_TREF, 4ull * (gtot + 1)},
-        {B_NLIST, 4ull * (TREE_LEVELS - 1) * ncap}, {B_SXY, 8ull * T}, {B_SID, 4ull * T},
-        {B_OCNT, 4ull * T}, {B_OLINES, 4ull * KOUT * T}, {B_OVF, 4ull * T}, {B_POOL, 4ull * E},
-        {B_QUEUE, 4ull * T}, {B_QUEUE2, 4ull * T},
-        {B_WBUF, 4ull * 2 * DCAP1 * exact_blocks}, {B_WBUF2, 4ull * 2 * DCAP2 * DEEP_BLOCKS},
-        {B_CELLOFF, 4ull * (T + 1)}, {B_NBR, 4ull * E},
-        {B_VTX, vertices ? sizeof(vor_rat) * E : 16}, {B_DCNT, 4ull * T},
-        {B_DELOFF, 4ull * (T + 1)}, {B_DEL, 8ull * D}, {B_SCANTMP, 4ull * stmp},
-        {B_SMALL, 4ull * SMALL_INTS}, {B_STATS, 8ull * SL_COUNT},
-        {B_SIDES, sizeof(SideRel) * std::max<size_t>(1, ws.sides_h.size())},
-        {B_TLIST, 4ull * TREE_LIST * TREE_PASS_BLOCK * tree_pass_blocks(T)},
-        {B_QUEUE4, 4ull * T}};
     bool grew = false;
-    for (auto &q : need) {
-        const size_t before = ws.b[q.id].cap;
-        const void *pb = ws.b[q.id].p;
-        if (ws.b[q.id].ensure(q.bytes) != hipSuccess) {
+    for (int id = 0; id < B_COUNT; ++id) {
+        const size_t before = ws.b[id].cap;
+        const void *pb = ws.b[id].p;
+        if (ws.b[id].ensure(z.b[id]) != hipSuccess) {
             (void)hipGetLastError();
             return VOR_E_NOMEM;
         }
-        grew |= (ws.b[q.id].cap != before) || (ws.b[q.id].p != pb);
+        grew |= (ws.b[id].cap != before) || (ws.b[id].p != pb);
     }
     if (grew) ws.drop_graph();
     // inputs
@@ -440,61 +276,10 @@ int launch(vor_ctx *ctx, Workspace &ws, const std::vector<HostSet> &sets, bool v
                            hipMemcpyHostToDevice, ws.stream);
     if (e != hipSuccess) return VOR_E_DEVICE;
 
-    std::memset(&a, 0, sizeof(a));
-    a.sets = ws.b[B_SETS].as<SetDesc>();
-    a.nsets = K;
-    a.sides = ws.b[B_SIDES].as<SideRel>();
-    a.any_poly = !ws.sides_h.empty();
-    a.set_off = ws.b[B_SETOFF].as<int>();
-    a.total = (int)T;
-    a.gtot = gtot;
-    a.in_x = in_x;
-    a.in_y = in_y;
-    a.xyid = ws.b[B_XYID].as<int2>();
-    a.key = ws.b[B_KEY].as<int>();
-    a.bcnt = ws.b[B_BCNT].as<int>();
-    a.bstart = ws.b[B_BSTART].as<int>();
-    a.tchild = ws.b[B_TCHILD].as<int>();
-    a.nodes = ws.b[B_NODES].as<TNode>();
-    a.ncap = (int)ncap;
-    a.tabcap = tabcap;
-    a.txy = ws.b[B_TXY].as<float2>();
-    a.tid = ws.b[B_TID].as<int>();
-    a.queue3 = ws.b[B_QUEUE3].as<int>();
-    a.queue4 = ws.b[B_QUEUE4].as<int>();
-    a.tref = ws.b[B_TREF].as<int>();
-    a.nlist = ws.b[B_NLIST].as<int>();
-    a.sxy = ws.b[B_SXY].as<float2>();
-    a.sid = ws.b[B_SID].as<int>();
-    a.ocnt = ws.b[B_OCNT].as<int>();
-    a.olines = ws.b[B_OLINES].as<int>();
-    a.ovf = ws.b[B_OVF].as<int>();
-    a.pool = ws.b[B_POOL].as<int>();
-    a.poolcap = E;
-    a.queue = ws.b[B_QUEUE].as<int>();
-    a.queue2 = ws.b[B_QUEUE2].as<int>();
-    a.wbuf = ws.b[B_WBUF].as<int>();
-    a.wbuf2 = ws.b[B_WBUF2].as<int>();
-    a.exact_blocks = exact_blocks;
-    a.cell_off = ws.b[B_CELLOFF].as<int>();
-    a.nbr = ws.b[B_NBR].as<int>();
-    a.nbr_cap = E;
-    a.vtx = ws.b[B_VTX].p;
-    a.dcnt = ws.b[B_DCNT].as<int>();
-    a.tlist = ws.b[B_TLIST].as<int>();
-    a.del_off = ws.b[B_DELOFF].as<int>();
-    a.del = ws.b[B_DEL].as<unsigned>();
-    a.del_cap = D;
-    a.scan_tmp = ws.b[B_SCANTMP].as<int>();
-    a.small = ws.b[B_SMALL].as<int>();
-    a.stats = ws.b[B_STATS].as<unsigned long long>();
-    a.block = ctx->tune.block;
-    a.tree_all = ctx->tune.scan_path == VOR_PATH_TREE;
-    a.exact_only = exact_only;
-    a.with_vertices = vertices;
-    a.check_symmetry = symmetry;
-    a.coop_all = coop_all;
-    a.time_stages = (ctx->opts.flags & VOR_TIME_KERNELS) != 0;
+    void *ptrs[B_COUNT];
+    for (int id = 0; id < B_COUNT; ++id) ptrs[id] = ws.b[id].p;
+    fill_args(a, ptrs, z, !ws.sides_h.empty(), in_x, in_y, ctx->tune, exact_only, vertices,
+              symmetry, (ctx->opts.flags & VOR_TIME_KERNELS) != 0);
 
     ws.last_timed = a.time_stages;
     if ((e = hipEventRecord(ws.ev0, ws.stream)) != hipSuccess) return VOR_E_DEVICE;
@@ -594,19 +379,6 @@ Summary read_summary(Workspace &ws) {
     return s;
 }
 
-void fill_stats(vor_stats &st, const Summary &s) {
-    st.rays = s.stats[SL_RAYS];
-    st.nodes = s.stats[SL_NODES];
-    st.evals = s.stats[SL_EVALS];
-    st.exact_decisions = s.stats[SL_EXACT];
-    st.deferred_cells = s.stats[SL_DEFERRED];
-    st.asym_pairs = s.stats[SL_ASYM];
-    st.shells = s.stats[SL_SHELLS];
-    st.edges = s.stats[SL_EDGES];
-    st.vertex_tests = s.stats[SL_VTESTS];
-    st.adaptive_cells = s.stats[SL_TREE];
-    st.adaptive_evals = s.stats[SL_TEVALS];
-}
 
 // Copy the results of every set back to host ResultBoxes (after the stream is idle).
 int collect_host(Workspace &ws, const PipeArgs &a, const std::vector<SetDesc> &descs,
@@ -645,7 +417,7 @@ int collect_host(Workspace &ws, const PipeArgs &a, const std::vector<SetDesc> &d
         r->vtx = vertices ? box->vtx.data() : nullptr;
         r->m = (uint64_t)(d1 - d0);
         r->del = box->del.data();
-        fill_stats(r->stats, sm);
+        fill_stats(r->stats, sm.stats);
         r->device_ms = sm.ms;
         r->cells_ms = sm.cells_ms;
         r->exact_ms = sm.exact_ms;
@@ -686,7 +458,7 @@ int run_sync(vor_ctx *ctx, Workspace &ws, const std::vector<HostSet> &sets,
         r->vtx = vertices ? (const vor_rat *)a.vtx : nullptr;
         r->m = (uint64_t)sm.dels;
         r->del = a.del;
-        fill_stats(r->stats, sm);
+        fill_stats(r->stats, sm.stats);
         r->device_ms = sm.ms;
         r->cells_ms = sm.cells_ms;
         r->exact_ms = sm.exact_ms;
@@ -710,7 +482,10 @@ void request_loop(vor_ctx *ctx) {
         std::vector<SetDesc> descs;
         std::vector<int> set_off;
         bool busy = false;
+        size_t fp = 0;   // admitted footprint
     } fl[REQ_WORKSPACES];
+    // footprint of the batches on the GPU: admission keeps it within the budget
+    size_t in_flight = 0;
     auto any_busy = [&] {
         for (const auto &f : fl)
             if (f.busy) return true;
@@ -727,6 +502,7 @@ void request_loop(vor_ctx *ctx) {
             if (q == hipErrorNotReady) continue;
             did = true;
             fl[w].busy = false;
+            in_flight -= fl[w].fp;
             std::vector<vor_result *> outs;
             int rc = q == hipSuccess ? VOR_OK : VOR_E_DEVICE;
             Summary sm{};
@@ -740,11 +516,14 @@ void request_loop(vor_ctx *ctx) {
                 // an input error of one request: re-run each alone so the others succeed
                 std::lock_guard<std::mutex> lk(ctx->qmu);
                 for (auto it = fl[w].reqs.rbegin(); it != fl[w].reqs.rend(); ++it) {
-                    (*it)->footprint |= (size_t)1 << 62;   // marks "run alone"
+                    (*it)->alone = true;
                     ctx->pending.push_front(*it);
                 }
                 continue;
             }
+            // a batch above its share of the budget leaves its buffers sized for it: release
+            // them so that the workspaces together keep within the budget
+            if (fl[w].fp > ctx->budget / REQ_WORKSPACES) ctx->rws[w].release_buffers();
             const double t = now_s();
             std::lock_guard<std::mutex> lk(ctx->qmu);
             for (size_t i = 0; i < fl[w].reqs.size(); ++i) {
@@ -752,10 +531,14 @@ void request_loop(vor_ctx *ctx) {
                 r.t_done = t;
                 if (rc == VOR_OK) {
                     r.result = outs[i];
+                    r.result->t_submit = r.t_submit;
+                    r.result->t_admit = r.t_admit;
+                    r.result->t_done = r.t_done;
                     r.status = VOR_OK;
                 } else {
                     r.status = rc;
                 }
+                r.release_inputs();
             }
         }
         // admissions
@@ -767,21 +550,23 @@ void request_loop(vor_ctx *ctx) {
                 if (ctx->stop) break;
                 size_t used = 0;
                 long long sites = 0;
-                const size_t cap = ctx->budget / REQ_WORKSPACES;
+                // what the batches already on the GPU leave of the budget
+                const size_t avail = ctx->budget > in_flight ? ctx->budget - in_flight : 0;
                 while (!ctx->pending.empty()) {
                     auto &r = ctx->pending.front();
-                    const bool alone = (r->footprint >> 62) & 1;
-                    const size_t fp = r->footprint & (((size_t)1 << 62) - 1);
+                    const bool alone = r->alone;
+                    const size_t fp = r->footprint;
                     const long long ns = (long long)r->x.size();
-                    if (!take.empty() &&
-                        (alone || used + fp > cap || sites + ns > ctx->serve_batch_sites))
-                        break;
-                    if (take.empty() && fp > ctx->budget) {
+                    if (take.empty() && fp > ctx->budget) {   // never fits, even alone
                         r->status = VOR_E_NOMEM;
                         r->t_done = now_s();
+                        r->release_inputs();
                         ctx->pending.pop_front();
                         continue;
                     }
+                    // waits (in order) until the batches in flight leave room for it
+                    if (used + fp > avail) break;
+                    if (!take.empty() && (alone || sites + ns > ctx->serve_batch_sites)) break;
                     take.push_back(r);
                     used += fp;
                     sites += ns;
@@ -805,6 +590,8 @@ void request_loop(vor_ctx *ctx) {
                 sets.push_back(h);
             }
             fl[w].reqs = take;
+            fl[w].fp = 0;
+            for (auto &r : take) fl[w].fp += r->footprint;
             int rc = launch(ctx, ctx->rws[w], sets, vertices, exact_only, false, ctx->use_graph,
                             fl[w].a, fl[w].descs, fl[w].set_off);
             if (rc != VOR_OK) {
@@ -813,10 +600,12 @@ void request_loop(vor_ctx *ctx) {
                 for (auto &r : take) {
                     r->status = rc;
                     r->t_done = now_s();
+                    r->release_inputs();
                 }
                 continue;
             }
             fl[w].busy = true;
+            in_flight += fl[w].fp;
         }
         {
             std::unique_lock<std::mutex> lk(ctx->qmu);
@@ -1072,7 +861,7 @@ int vor_submit(vor_ctx *ctx, const vor_set *set, uint64_t *ticket) {
     SetDesc d{};
     choose_grid(h.box, set->n, ctx->tune.sites_per_bucket, ctx->tune.block_halfwidth, d, h.area);
     r->footprint = footprint_bytes(set->n, (uint64_t)d.gx * d.gy,
-                                   !(ctx->opts.flags & VOR_NO_VERTICES));
+                                   !(ctx->opts.flags & VOR_NO_VERTICES), h.nreg ? h.nreg : 4);
     {
         std::lock_guard<std::mutex> lk(ctx->qmu);
         if (ctx->stop) return VOR_E_INVAL;
@@ -1099,15 +888,32 @@ int vor_poll(vor_ctx *ctx, uint64_t ticket, vor_result **out) {
     if (it == ctx->all.end()) return VOR_E_TICKET;
     Request &r = *it->second;
     if (r.status == VOR_PENDING) return VOR_PENDING;
-    int st = r.status;
+    const int st = r.status;
     if (st == VOR_OK) {
-        *out = r.result;
+        *out = r.result;   // carries the request's latency stamps
         r.result = nullptr;
     }
-    // keep the latency stamps readable, but the result is consumed
-    r.status = st == VOR_OK ? VOR_E_TICKET : st;
-    if (st != VOR_OK) ctx->all.erase(it);
+    ctx->all.erase(it);    // consumed: the context keeps nothing of it
     return st;
+}
+
+int vor_ticket_count(vor_ctx *ctx, uint64_t *held) {
+    if (!ctx || !held) return VOR_E_INVAL;
+    std::lock_guard<std::mutex> lk(ctx->qmu);
+    *held = ctx->all.size();
+    return VOR_OK;
+}
+
+int vor_footprint(vor_ctx *ctx, const vor_set *set, uint64_t *bytes) {
+    if (!ctx || !bytes) return VOR_E_INVAL;
+    HostSet h;
+    const int rc = check_set(set, h);
+    if (rc != VOR_OK) return rc;
+    SetDesc d{};
+    choose_grid(h.box, set->n, ctx->tune.sites_per_bucket, ctx->tune.block_halfwidth, d, h.area);
+    *bytes = footprint_bytes(set->n, (uint64_t)d.gx * d.gy, !(ctx->opts.flags & VOR_NO_VERTICES),
+                             h.nreg ? h.nreg : 4);
+    return VOR_OK;
 }
 
 int vor_ticket_times(vor_ctx *ctx, uint64_t ticket, double *ts, double *ta, double *td) {
@@ -1124,6 +930,46 @@ int vor_ticket_times(vor_ctx *ctx, uint64_t ticket, double *ts, double *ta, doub
 void vor_result_free(vor_result *r) {
     if (!r) return;
     delete reinterpret_cast<ResultBox *>(r);
+}
+
+int vor_result_to_host(vor_ctx *ctx, const vor_result *dev, vor_result **out) {
+    if (!ctx || !dev || !out) return VOR_E_INVAL;
+    *out = nullptr;
+    if (!dev->cell_off || (dev->m && !dev->del)) return VOR_E_INVAL;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (hipSetDevice(ctx->device) != hipSuccess) return VOR_E_DEVICE;
+    ResultBox *box;
+    vor_result *r = new_result(box);
+    if (!r) return VOR_E_NOMEM;
+    const size_t n = dev->n;
+    box->off.resize(n + 1);
+    hipError_t e = hipMemcpy(box->off.data(), dev->cell_off, 4 * (n + 1), hipMemcpyDeviceToHost);
+    const size_t E = e == hipSuccess ? box->off[n] : 0;
+    if (e == hipSuccess && E && !dev->nbr) e = hipErrorInvalidValue;
+    if (e == hipSuccess) {
+        box->nbr.resize(E);
+        if (E) e = hipMemcpy(box->nbr.data(), dev->nbr, 4 * E, hipMemcpyDeviceToHost);
+    }
+    if (e == hipSuccess && dev->vtx) {
+        box->vtx.resize(E);
+        if (E) e = hipMemcpy(box->vtx.data(), dev->vtx, sizeof(vor_rat) * E, hipMemcpyDeviceToHost);
+    }
+    if (e == hipSuccess) {
+        box->del.resize(2 * dev->m);
+        if (dev->m) e = hipMemcpy(box->del.data(), dev->del, 8 * dev->m, hipMemcpyDeviceToHost);
+    }
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        delete box;
+        return e == hipErrorInvalidValue ? VOR_E_INVAL : VOR_E_DEVICE;
+    }
+    *r = *dev;
+    r->cell_off = box->off.data();
+    r->nbr = box->nbr.data();
+    r->vtx = dev->vtx ? box->vtx.data() : nullptr;
+    r->del = box->del.data();
+    *out = r;
+    return VOR_OK;
 }
 
 }  // extern "C"

@@ -36,6 +36,8 @@ namespace vor {
 
 struct Counters {
     uint32_t rays, nodes, evals, exact, shells, vtests;
+    uint32_t xinc;    // exact decisions of vertex rays (the vertex-in-cell / incircle test)
+    uint32_t vrays;   // vertex rays (towards u = L1 ∩ L2) among the rays and vertex tests
 };
 
 // ------------------------------------------------------------------------------ exact argmin
@@ -984,6 +986,7 @@ __device__ __forceinline__ int ray(const Cell &C, Sc &sc, const float2 *__restri
         }
         if (MODE == 0) return -1;
         K.exact++;
+        K.xinc += vmode;
         // exact decision over the certified region, FP32-plausible candidates only
         sc.exact(C, sxy, d, s, vmode ? tu_hi : s.U, ex1, ex2, xb, K);
     }
@@ -1071,6 +1074,7 @@ __device__ __forceinline__ int cell_step(const Cell &C, const float2 *__restrict
         // a shot ray (Lemma on shot rays) yields a corner; a ray that confirms a vertex is the
         // in-cell test of the vertex
         if (leaf) K.vtests++; else K.rays++;
+        K.vrays += Den > 0;
     }
     if (phase < 3) {
         if (phase == 0) {

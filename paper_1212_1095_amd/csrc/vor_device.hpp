@@ -39,7 +39,7 @@ enum : int { ST_DOMAIN = 1, ST_DUP = 2, ST_CAPACITY = 4, ST_INTERNAL = 8 };
 // stats slots
 enum : int {
     SL_RAYS = 0, SL_NODES, SL_EVALS, SL_EXACT, SL_DEFERRED, SL_ASYM, SL_SHELLS, SL_EDGES,
-    SL_VTESTS, SL_TREE, SL_TEVALS, SL_COUNT
+    SL_VTESTS, SL_TREE, SL_TEVALS, SL_XINC, SL_VRAYS, SL_COUNT
 };
 
 struct SetDesc {
@@ -403,27 +403,5 @@ struct RowWalk {
         return true;
     }
 };
-
-// True when every site closer than p to the point y = p + (T/2) d_s (doubled-frame ray
-// parameter T, an upper bound of the endpoint) lies in the block of shells 0..k: the square
-// S[y, |y - p|] (Lemma on sites in the large square; eq. S_I gives the same bucket test)
-// fits inside the block, a block side on the grid edge counting as unbounded.
-__device__ __forceinline__ bool block_certifies(const Cell &C, int k, float T, float dx,
-                                                float dy) {
-    const Cell &S = C;
-    const bool el = C.bx - k <= 0, er = C.bx + k >= S.gx - 1;
-    const bool eb = C.by - k <= 0, et = C.by + k >= S.gy - 1;
-    if (el && er && eb && et) return true;
-    const float Tu = T * CERT_UP;
-    const float hx = 0.5f * Tu * dx, hy = 0.5f * Tu * dy;
-    const float yx = C.pxf + hx, yy = C.pyf + hy;
-    const float r = sqrtf(hx * hx + hy * hy);
-    const float M = (r + fabsf(yx) + fabsf(yy)) * 1.0e-5f + 1.0e-3f;
-    const bool l = el || (yx - r - M >= (float)(C.bx - k) * (float)S.s);
-    const bool rr = er || (yx + r + M < (float)(C.bx + k + 1) * (float)S.s);
-    const bool b = eb || (yy - r - M >= (float)(C.by - k) * (float)S.s);
-    const bool t = et || (yy + r + M < (float)(C.by + k + 1) * (float)S.s);
-    return l && rr && b && t;
-}
 
 }  // namespace vor

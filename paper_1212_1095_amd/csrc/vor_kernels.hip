@@ -355,6 +355,8 @@ __device__ __forceinline__ void reduce_stats(const Counters &K, uint32_t edges, 
     atomicAdd(&sh[SL_EDGES], (unsigned long long)edges);
     atomicAdd(&sh[SL_DEFERRED], (unsigned long long)deferred);
     atomicAdd(&sh[SL_VTESTS], (unsigned long long)K.vtests);
+    atomicAdd(&sh[SL_XINC], (unsigned long long)K.xinc);
+    atomicAdd(&sh[SL_VRAYS], (unsigned long long)K.vrays);
     if (tree) {
         atomicAdd(&sh[SL_TREE], (unsigned long long)tree);
         atomicAdd(&sh[SL_TEVALS], (unsigned long long)K.evals);
@@ -382,7 +384,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5, 8))) v
     if (threadIdx.x < SL_COUNT) sh[threadIdx.x] = 0;
     __syncthreads();
     const int pos = xcd_block(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
-    Counters K{0, 0, 0, 0, 0, 0};
+    Counters K{};
     uint32_t edges = 0, deferred = 0;
     if (pos < total) {
         const SetDesc S = sets[find_set(set_off, nsets, pos)];
@@ -450,7 +452,7 @@ __global__ __launch_bounds__(BLOCK, LONLY ? 4 : 3) void k_cells_tree(
     if ((int)(blockIdx.x * BLOCK) >= nq) return;
     if (threadIdx.x < SL_COUNT) sh[threadIdx.x] = 0;
     __syncthreads();
-    Counters K{0, 0, 0, 0, 0, 0};
+    Counters K{};
     uint32_t edges = 0, deferred = 0, handled = 0;
     for (int qi = blockIdx.x * BLOCK + threadIdx.x; qi < nq; qi += gridDim.x * BLOCK) {
         const int pos = qin[qi];
@@ -529,7 +531,7 @@ __global__ __launch_bounds__(64) void k_cells_exact(
     const int lane = threadIdx.x;
     int *area = LCAP > 0 ? larea : wbuf + (size_t)blockIdx.x * 2 * dcap;
     if (LCAP > 0) dcap = LCAP;
-    Counters K{0, 0, 0, 0, 0, 0};
+    Counters K{};
     uint32_t edges = 0;
     for (int qi = blockIdx.x; qi < nq; qi += gridDim.x) {
         const int pos = queue[qi];
@@ -572,7 +574,7 @@ __global__ __launch_bounds__(64) void k_cells_exact(
     }
     // every lane ran the same control flow: count it once; evaluations are split across lanes
     if (lane != 0) {
-        K.rays = K.nodes = K.exact = K.shells = K.vtests = 0;
+        K.rays = K.nodes = K.exact = K.shells = K.vtests = K.xinc = K.vrays = 0;
         edges = 0;
     }
     reduce_stats(K, edges, 0, 0, sh, stats);
@@ -787,17 +789,23 @@ __global__ __launch_bounds__(EMIT_BLOCK) void k_emit(
     const int g0 = blockIdx.x * EMIT_BLOCK;
     const int nc = min(EMIT_BLOCK, total - g0);
     const int g = g0 + tid;
+    if (tid == 0) {
+        stop = *status;   // one read, so that every wave of the block takes the same branch
+        bad = 0;
+        // more entries or Delaunay pairs in the run than the buffers hold (the sizes follow
+        // from Euler's formula, so this is a capacity error, never an internal one)
+        if (!stop && ((long long)cell_off[total] > cap || (long long)del_off[total] > del_cap)) {
+            atomicOr(status, ST_CAPACITY);
+            stop = ST_CAPACITY;
+        }
+    }
+    __syncthreads();
+    if (stop) return;
     const long long E0 = cell_off[g0], E1 = cell_off[g0 + nc];
     const long long D0 = del_off[g0], D1 = del_off[g0 + nc];
     const bool staged = E1 - E0 >= 0 && E1 - E0 <= EMIT_ECAP && D1 >= D0;
     const int ne = staged ? (int)(E1 - E0) : 0;
-    if (tid == 0) {
-        stop = *status;   // one read, so that every wave of the block takes the same branch
-        bad = 0;
-        clo[nc] = ne;
-    }
-    __syncthreads();
-    if (stop) return;
+    if (tid == 0) clo[nc] = ne;   // read after the next barrier
     // per cell: offsets, checks, where its lines are
     int s = 0, k = 0, m = 0, dn = 0;
     long long base = 0, dbase = 0;

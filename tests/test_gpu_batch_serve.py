@@ -116,8 +116,7 @@ def test_serving_results_identical_alone_and_in_mix(vor):
         for t, r in zip(tickets, reqs):
             st, res = done[t]
             assert st == vor.VOR_OK, (t, st)
-            ts, ta, td = ctx.times(t)
-            assert ts <= ta <= td
+            assert 0 < res.t_submit <= res.t_admit <= res.t_done
             alone = ctx.compute(r.x, r.y, r.box)
             same(res, alone)
         for r, t in list(zip(reqs, tickets))[:6]:
@@ -158,3 +157,38 @@ def test_destroy_with_pending_requests(vor):
     for _ in range(4):
         ctx.submit(ps.x, ps.y, ps.box)
     ctx.close()   # cancels pending requests, joins the loop, frees results
+
+
+def test_consumed_tickets_leave_nothing_behind(vor):
+    """A served request is forgotten once polled: the context's ticket map stays bounded."""
+    sets = [sitegen.uniform(300 + 7 * i, 1 << 20, 500 + i) for i in range(60)]
+    with vor.Context(flags=vor.VOR_NO_VERTICES) as ctx:
+        for rnd in range(4):
+            tickets = [ctx.submit(s.x, s.y, s.box) for s in sets]
+            assert ctx.ticket_count() == len(sets)
+            done = wait_all(ctx, tickets)
+            assert all(st == vor.VOR_OK for st, _ in done.values())
+            assert ctx.ticket_count() == 0, rnd
+        with pytest.raises(vor.VorError):
+            ctx.times(tickets[0])
+        st, _ = ctx.poll(tickets[0])
+        assert st == vor.VOR_E_TICKET
+
+
+def test_admission_keeps_the_budget_across_workspaces(vor):
+    """Two requests, each larger than half the budget: the second is admitted only after the
+    first is done, although a second workspace is free."""
+    a = sitegen.uniform(200000, 1 << 24, 41)
+    b = sitegen.uniform(180000, 1 << 24, 42)
+    with vor.Context() as c0:
+        fa, fb = c0.footprint(a.x, a.y, a.box), c0.footprint(b.x, b.y, b.box)
+    budget = int(1.5 * max(fa, fb))
+    assert fa > budget // 2 and fb > budget // 2 and fa + fb > budget
+    with vor.Context(hbm_budget_bytes=budget) as ctx:
+        ta = ctx.submit(a.x, a.y, a.box)
+        tb = ctx.submit(b.x, b.y, b.box)
+        done = wait_all(ctx, [ta, tb])
+    (sa, ra), (sb, rb) = done[ta], done[tb]
+    assert sa == vor.VOR_OK and sb == vor.VOR_OK
+    say(f"a: admit {ra.t_admit:.4f} done {ra.t_done:.4f}; b: admit {rb.t_admit:.4f}")
+    assert rb.t_admit >= ra.t_done

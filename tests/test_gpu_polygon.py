@@ -145,3 +145,56 @@ def test_polygon_errors(vor):
             c.compute(np.array([1000000], np.int32), np.array([1000000], np.int32),
                       (0, 0, 1, 1), region=big)
         assert e.value.status == vor.VOR_E_INVAL
+
+
+def round_polygon(K, R=1 << 22, c=1 << 23):
+    """A strictly convex K-gon with integer vertices on (about) a circle, counter-clockwise."""
+    import math
+    vx = np.array([c + round(R * math.cos(2 * math.pi * k / K)) for k in range(K)], np.int32)
+    vy = np.array([c + round(R * math.sin(2 * math.pi * k / K)) for k in range(K)], np.int32)
+    return vx, vy
+
+
+def sites_in_round_polygon(n, K, seed):
+    from oracle import cdiagram
+    reg = round_polygon(K)
+    ps = sitegen.in_polygon(n, reg, seed=seed)
+    assert cdiagram.validate(ps.x, ps.y, ps.box, region=ps.region) == 0
+    return ps
+
+
+def test_many_sides_few_sites(ctx):
+    """Entry capacity with many sides: one site in a 256-gon (its cell is X, 256 entries), five
+    sites in a 200-gon; more entries than 10 per site (sized by 6n + K)."""
+    for n, K in ((1, 256), (5, 200), (2, 256)):
+        ps = sites_in_round_polygon(n, K, seed=70 + n)
+        r = run(ctx, ps, f"{n} sites, {K} sides")
+        assert int(r.cell_off[-1]) > 10 * n
+        assert_matches_oracle(r, ps)
+
+
+def test_many_sides_in_a_mixed_batch_and_stream(vor):
+    import time
+    polys = [sites_in_round_polygon(5, 200, seed=81), sites_in_round_polygon(1, 256, seed=82)]
+    boxes = [sitegen.uniform(3000, 1 << 20, seed=83), sitegen.uniform(40, 1 << 16, seed=84)]
+    mix = [boxes[0], polys[0], boxes[1], polys[1]]
+    with vor.Context() as c:
+        rc, res = c.compute_batch([(p.x, p.y, p.box, p.region) if p.region is not None
+                                   else (p.x, p.y, p.box) for p in mix])
+        assert rc == vor.VOR_OK
+        for r, p in zip(res, mix):
+            assert_matches_oracle(r, p)
+        tickets = [c.submit(p.x, p.y, p.box, region=p.region) for p in mix]
+        out = {}
+        t0 = time.time()
+        while len(out) < len(tickets):
+            for t in tickets:
+                if t not in out:
+                    st, r = c.poll(t)
+                    if st != vor.VOR_PENDING:
+                        assert st == vor.VOR_OK, st
+                        out[t] = r
+            assert time.time() - t0 < 60
+            time.sleep(0.002)
+        for t, p in zip(tickets, mix):
+            assert_matches_oracle(out[t], p)

@@ -234,3 +234,42 @@ def test_theorem_constants():
         assert tc["cond1"] and tc["cond2"]
         if "printed_bound" in case:
             assert tc["per_site_bound"] <= case["printed_bound"] == 3 * tc["alpha2"] * 22
+
+
+def test_sites_closer_to_y_lie_in_the_integer_rectangle():
+    """Lemma on sites in the large square (Appendix 1) with eq. (S_I): for a point y on a ray
+    from p, every site not farther from y than p lies in the buckets of S_I[y, |y - p|]; and the
+    disks of the points y' of [p, y] nest (B[y', |y' - p|] inside B[y, |y - p|], the lemma on
+    B(y, y')).  Brute force over every lattice site of a window, in exact integers scaled by the
+    common denominator: rays along Pythagorean directions, so that |y - p| is rational."""
+    rng = np.random.default_rng(11)
+    triples = [(3, 4, 5), (5, 12, 13), (8, 15, 17), (7, 24, 25), (20, 21, 29), (1, 0, 1)]
+    checked = 0
+    for _ in range(400):
+        a, b, c = triples[int(rng.integers(0, len(triples)))]
+        if rng.random() < 0.5:
+            a, b = b, a
+        a, b = a * int(rng.choice([-1, 1])), b * int(rng.choice([-1, 1]))
+        p = (int(rng.integers(0, 60)), int(rng.integers(0, 60)))
+        s = int(rng.integers(1, 9))
+        tn, td = int(rng.integers(1, 400)), int(rng.integers(1, 12))
+        t = F(tn, td)
+        y = (p[0] + t * F(a, c), p[1] + t * F(b, c))
+        (A0, B0), (A1, B1) = paper_forms.integer_rectangle(y, t, s)
+        un = int(rng.integers(0, 1000))                 # y' = p + (un / 1000) t theta on [p, y]
+        # every lattice point of a window around y, coordinates scaled by L = c td 1000
+        L = c * td * 1000
+        qx, qy = np.meshgrid(np.arange(math.floor(y[0] - t) - 2, math.ceil(y[0] + t) + 3),
+                             np.arange(math.floor(y[1] - t) - 2, math.ceil(y[1] + t) + 3))
+        qx, qy = qx.ravel().astype(np.int64), qy.ravel().astype(np.int64)
+        Yx, Yy = p[0] * L + tn * a * 1000, p[1] * L + tn * b * 1000       # y * L
+        R = tn * c * 1000                                                # |y - p| * L
+        Y2x, Y2y = p[0] * L + tn * a * un, p[1] * L + tn * b * un        # y' * L
+        R2 = tn * c * un
+        near = (qx * L - Yx) ** 2 + (qy * L - Yy) ** 2 <= R * R
+        near2 = (qx * L - Y2x) ** 2 + (qy * L - Y2y) ** 2 <= R2 * R2
+        assert not np.any(near2 & ~near), "disk of y' not inside the disk of y"
+        inr = (qx >= A0) & (qx < B0) & (qy >= A1) & (qy < B1)
+        assert np.all(inr[near]), (p, y, t, s)
+        checked += int(near.sum())
+    assert checked > 100000
