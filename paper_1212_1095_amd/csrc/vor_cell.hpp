@@ -1003,6 +1003,31 @@ __device__ __forceinline__ int ray(const Cell &C, Sc &sc, const float2 *__restri
     return 1;
 }
 
+// ------------------------------------------------------------------------------ one subedge
+// The ray that resolves the subedge from the corner on line L1 to the next corner (counter-
+// clockwise) on line L2, L1 != L2 (Algorithm 1): Den = cross(N1, N2); Den = 0: the lines are
+// antiparallel and the ray runs along them (ParallelLines); otherwise u = L1 ∩ L2 = Z / Den and
+// the ray runs along Z (towards u for Den > 0, the Vertex / OutsideCell test, which skips the
+// two lines through u; away from it for Den < 0, OutsideWedge).
+__device__ __forceinline__ void split_dir(const Line &L1, const Line &L2, Dir &d, int64_t &Den,
+                                          int &ex1, int &ex2) {
+    Den = (int64_t)L1.nx * L2.ny - (int64_t)L1.ny * L2.nx;
+    if (Den == 0) {
+        d = make_dir(-(i128)L1.ny, (i128)L1.nx);
+    } else {
+        const i128 Zx = (i128)L1.c * L2.ny - (i128)L2.c * L1.ny;
+        const i128 Zy = (i128)L1.nx * L2.c - (i128)L2.nx * L1.c;
+        d = make_dir(Zx, Zy);
+        ex1 = L1.id;
+        ex2 = L2.id;
+    }
+}
+
+// The projector's corner ray i (0, 1, 2): (7, -4), (0, 1), (-7, -4), counter-clockwise, gaps < pi.
+__device__ __forceinline__ Dir corner_dir(int i) {
+    return make_dir(i == 1 ? 0 : (i == 0 ? 7 : -7), i == 1 ? 1 : -4);
+}
+
 // ------------------------------------------------------------------------------ one cell
 // The walk over a cell's subedges as a resumable state: cell_begin, then cell_step until it
 // returns non-zero.  Phases 0..2 shoot the projector's corner rays (7,-4), (0,1), (-7,-4)
@@ -1039,7 +1064,7 @@ __device__ __forceinline__ int cell_step(const Cell &C, const float2 *__restrict
     bool leaf = false;
     Line R{}, L3{};
     if (phase < 3) {
-        d = make_dir(phase == 1 ? 0 : (phase == 0 ? 7 : -7), phase == 1 ? 1 : -4);
+        d = corner_dir(phase);
     } else {
         if (st.depth == 0) {
             if (w.m > 1 && w.last == w.first) {
@@ -1052,20 +1077,8 @@ __device__ __forceinline__ int cell_step(const Cell &C, const float2 *__restrict
         K.nodes++;
         R = make_line(C, sxy, st.top());
         const Line &cur = w.cur;
-        if (cur.id == R.id) {
-            leaf = true;   // SameLines
-        } else {
-            Den = (int64_t)cur.nx * R.ny - (int64_t)cur.ny * R.nx;
-            if (Den == 0) {   // ParallelLines: direction of the lines, inside the wedge
-                d = make_dir(-(i128)cur.ny, (i128)cur.nx);
-            } else {          // OutsideWedge (Den < 0) or Vertex / OutsideCell (Den > 0)
-                const i128 Zx = (i128)cur.c * R.ny - (i128)R.c * cur.ny;
-                const i128 Zy = (i128)cur.nx * R.c - (i128)R.nx * cur.c;
-                d = make_dir(Zx, Zy);
-                ex1 = cur.id;
-                ex2 = R.id;
-            }
-        }
+        if (cur.id == R.id) leaf = true;   // SameLines
+        else split_dir(cur, R, d, Den, ex1, ex2);
     }
     if (!leaf) {
         const int r = ray<MODE, P, Sc>(C, sc, sxy, d, Den, ex1, ex2, L3, K);

@@ -30,7 +30,6 @@ typedef unsigned __int128 u128;
 constexpr int KOUT = 24;     // lines per cell kept by the filtered pass (more: deferred)
 constexpr int SCAP = 16;     // LDS stack entries per thread in the filtered pass
 constexpr int DCAP1 = 128;   // stack / output entries per worker in the exact pass
-constexpr int DCAP2 = 65536; // same for the few workers of the deep-cell pass
 constexpr int NODE_LIMIT_FACTOR = 4;
 
 // status bits (device status word)

@@ -9,7 +9,10 @@ struct SetDesc;
 struct SideRel;
 struct TNode;
 constexpr int SMALL_INTS = 16;   // status, queue counters, pool / tree counters, spare
-constexpr int DEEP_BLOCKS = 8;   // one-wave workers of the deep-cell pass
+constexpr int DEEP_BLOCKS = 4;   // workgroups of the deep-cell pass (one cell each at a time)
+constexpr int WIDE_WAVES = 8;    // waves of such a workgroup (subwedges resolved in parallel)
+constexpr int WIDE_CAP = 65536 + 64;   // corners of one deep cell (a cell has at most 65536
+                                       // lines; rays <= lines + 1, Lemma on shot rays)
 constexpr int LVCNT0 = 8;        // small[LVCNT0 + l]: nodes listed for refinement level l (2..6)
 constexpr int TREE_PASS_BLOCK = 128;       // threads per block of the adaptive pass
 constexpr int TREE_PASS_MAXBLOCKS = 2048;  // its persistent grid at most

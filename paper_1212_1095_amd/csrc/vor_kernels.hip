@@ -580,6 +580,165 @@ __global__ __launch_bounds__(64) void k_cells_exact(
     reduce_stats(K, edges, 0, 0, sh, stats);
 }
 
+// Deep cells (more lines than the exact pass holds per worker), with the subwedges of one cell
+// spread over the waves of a workgroup (the parallel case of Appendix 2: several processing
+// units share one cell's projector).  The cell's corners form a counter-clockwise linked list
+// (line of each corner, next corner); a subedge is a corner and its successor.  Rounds: every
+// pending subedge is resolved by one wave (its 64 lanes split the candidate scans), a new
+// corner is spliced in between its two corners and both halves become pending in the next
+// round; a barrier ends the round.  Two waves never touch the same corner's successor link,
+// since each owns the subedge that starts there.  After the last round one lane walks the list
+// and writes the corners' lines with repeats removed: the same cyclic list the depth-first walk
+// yields (the set of prime subedges does not depend on the order they are resolved in).
+// The work area of a block: corner lines, successor links, two frontier lists (WIDE_CAP each).
+template <int MODE>
+__global__ __launch_bounds__(64 * WIDE_WAVES) void k_cells_wide(
+    const SetDesc *__restrict__ sets, int nsets, const int *__restrict__ set_off,
+    const SideRel *__restrict__ sides,
+    const float2 *__restrict__ sxy, const int *__restrict__ sid, const int *__restrict__ bstart,
+    int *__restrict__ ocnt, int *__restrict__ olines, int *__restrict__ dcnt,
+    int *__restrict__ ovf, int *__restrict__ pool, int *__restrict__ poolcnt, long long poolcap,
+    const int *__restrict__ queue, const int *__restrict__ qcount, int *__restrict__ wbuf,
+    unsigned long long *__restrict__ stats, int *__restrict__ status) {
+    __shared__ unsigned long long sh[SL_COUNT];
+    __shared__ int fcount[2], ncorner, err, s_m, s_up, s_off;
+    if (*status & (ST_DOMAIN | ST_DUP)) return;
+    const int nq = *qcount;
+    if ((int)blockIdx.x >= nq) return;   // no cell for this worker
+    if (threadIdx.x < SL_COUNT) sh[threadIdx.x] = 0;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    int *cline = wbuf + (size_t)blockIdx.x * 4 * WIDE_CAP;
+    int *nxt = cline + WIDE_CAP;
+    int *F[2] = {nxt + WIDE_CAP, nxt + 2 * WIDE_CAP};
+    Counters K{};
+    uint32_t edges = 0;
+    for (int qi = blockIdx.x; qi < nq; qi += gridDim.x) {
+        const int pos = queue[qi];
+        const SetDesc S = sets[find_set(set_off, nsets, pos)];
+        const Cell C = make_cell(S, sxy[pos], sides);
+        const int k = sid[pos];
+        const int g = S.site_off + k;
+        GridScan<Coop, GlobalRows, false> sc{GlobalRows{0}, bstart, false};
+        sc.load(C, sxy);
+        __syncthreads();   // the previous cell's list is no longer read
+        if (threadIdx.x == 0) {
+            ncorner = 3;
+            err = 0;
+            fcount[0] = 3;
+            fcount[1] = 0;
+        }
+        // round 0: the projector's three corner rays, one wave each
+        if (wave < 3) {
+            Line L{};
+            ray<MODE, Coop>(C, sc, sxy, corner_dir(wave), 0, INT32_MIN, INT32_MIN, L, K);
+            K.rays++;
+            if (lane == 0) {
+                cline[wave] = L.id;
+                nxt[wave] = wave == 2 ? 0 : wave + 1;
+                F[0][wave] = wave;
+            }
+        }
+        __threadfence();
+        __syncthreads();
+        int cur = 0;
+        while (fcount[cur] > 0 && !err) {
+            const int nf = fcount[cur];
+            for (int f = wave; f < nf; f += WIDE_WAVES) {
+                const int i = F[cur][f];
+                const int j = nxt[i];
+                const Line L1 = make_line(C, sxy, cline[i]), L2 = make_line(C, sxy, cline[j]);
+                K.nodes++;
+                if (L1.id == L2.id) continue;   // SameLines
+                Dir d;
+                int64_t Den;
+                int ex1 = INT32_MIN, ex2 = INT32_MIN;
+                split_dir(L1, L2, d, Den, ex1, ex2);
+                Line L3{};
+                const int r = ray<MODE, Coop>(C, sc, sxy, d, Den, ex1, ex2, L3, K);
+                K.vrays += Den > 0;
+                if (r == 1) {   // u is a vertex of the cell: the subedge is prime
+                    K.vtests++;
+                    continue;
+                }
+                K.rays++;
+                int nk = 0;
+                if (lane == 0) nk = atomicAdd(&ncorner, 1);
+                nk = __shfl(nk, 0, 64);
+                if (nk >= WIDE_CAP || r < 0) {
+                    if (lane == 0) atomicOr(&err, nk >= WIDE_CAP ? ST_CAPACITY : ST_INTERNAL);
+                    continue;
+                }
+                if (lane == 0) {
+                    cline[nk] = L3.id;
+                    nxt[nk] = j;
+                    nxt[i] = nk;
+                    const int at = atomicAdd(&fcount[cur ^ 1], 2);
+                    F[cur ^ 1][at] = i;
+                    F[cur ^ 1][at + 1] = nk;
+                }
+            }
+            __threadfence();
+            __syncthreads();
+            if (threadIdx.x == 0) fcount[cur] = 0;
+            cur ^= 1;
+            __syncthreads();
+        }
+        if (err) {
+            if (threadIdx.x == 0) atomicOr(status, err);
+            continue;   // uniform across the block (err is read after the last barrier)
+        }
+        // the cyclic list of distinct lines, counter-clockwise from corner 0 (into F[0])
+        if (threadIdx.x == 0) {
+            int m = 0, up = 0, last = INT32_MIN, c = 0;
+            const int first = cline[0] >= 0 ? sid[cline[0]] : cline[0];
+            do {
+                const int id = cline[c];
+                const int v = id >= 0 ? sid[id] : id;
+                if (v != last) {
+                    F[0][m++] = v;
+                    up += v > k;
+                    last = v;
+                }
+                c = nxt[c];
+            } while (c != 0);
+            if (m > 1 && last == first) {
+                --m;
+                up -= last > k;
+            }
+            int off = -1;
+            if (m > KOUT) {
+                off = atomicAdd(poolcnt, m);
+                if ((long long)off + m > poolcap) {
+                    atomicOr(status, ST_CAPACITY);
+                    m = -1;
+                }
+            }
+            s_m = m;
+            s_up = up;
+            s_off = off;
+        }
+        __threadfence();
+        __syncthreads();
+        const int m = s_m, off = s_off;
+        if (m < 0) continue;
+        int *dst = off >= 0 ? pool + off : olines + (size_t)g * KOUT;
+        for (int t = threadIdx.x; t < m; t += blockDim.x) dst[t] = F[0][t];
+        if (threadIdx.x == 0) {
+            ovf[g] = off;
+            ocnt[g] = m;
+            dcnt[g] = s_up;
+            edges += (uint32_t)m;
+        }
+    }
+    // every lane of a wave ran the same control flow: count it once; evaluations are split
+    // across the lanes
+    if (lane != 0) {
+        K.rays = K.nodes = K.exact = K.shells = K.vtests = K.xinc = K.vrays = 0;
+        edges = 0;
+    }
+    reduce_stats(K, edges, 0, 0, sh, stats);
+}
+
 // ------------------------------------------------------------------------------ scan
 // Exclusive scan of n int32 values (>= 0) into out[0..n], out[n] = total.  Three launches:
 // block sums, a single-block scan of the sums, per-block scan plus offset.
@@ -969,12 +1128,11 @@ static void launch_exact(const PipeArgs &a, hipStream_t st) {
         a.sets, a.nsets, a.set_off, a.sides, a.sxy, a.sid, a.bstart, a.ocnt, a.olines, a.dcnt, a.ovf,
         a.pool, a.poolcnt(), a.poolcap, a.queue, a.qcount(), a.queue2,
         a.qcount2(), a.wbuf, DCAP1, a.stats, a.status_rw());
-    // deep cells: few workers with a large area each
-    k_cells_exact<MODE, 0><<<DEEP_BLOCKS, 64, 0, st>>>(
-        a.sets, a.nsets, a.set_off, a.sides, a.sxy, a.sid, a.bstart, a.ocnt, a.olines, a.dcnt, a.ovf,
-        a.pool, a.poolcnt(), a.poolcap, a.queue2, a.qcount2(), nullptr,
-        nullptr,
-        a.wbuf2, DCAP2, a.stats, a.status_rw());
+    // deep cells: few workgroups, the subwedges of each cell spread over their waves
+    k_cells_wide<MODE><<<DEEP_BLOCKS, 64 * WIDE_WAVES, 0, st>>>(
+        a.sets, a.nsets, a.set_off, a.sides, a.sxy, a.sid, a.bstart, a.ocnt, a.olines, a.dcnt,
+        a.ovf, a.pool, a.poolcnt(), a.poolcap, a.queue2, a.qcount2(), a.wbuf2, a.stats,
+        a.status_rw());
 }
 
 void launch_stage(const PipeArgs &a, hipStream_t st, int stage) {

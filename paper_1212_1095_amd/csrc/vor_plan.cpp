@@ -199,7 +199,7 @@ int run_sizes(long long T, long long gtot, long long sides, int K, size_t nsides
     b[B_OLINES] = 4ull * KOUT * T;
     b[B_POOL] = b[B_NBR] = 4ull * E;
     b[B_WBUF] = 4ull * 2 * DCAP1 * z.exact_blocks;
-    b[B_WBUF2] = 4ull * 2 * DCAP2 * DEEP_BLOCKS;
+    b[B_WBUF2] = 4ull * 4 * WIDE_CAP * DEEP_BLOCKS;
     b[B_CELLOFF] = b[B_DELOFF] = 4ull * (T + 1);
     b[B_VTX] = vertices ? sizeof(vor_rat) * E : 16;
     b[B_DEL] = 8ull * D;
