@@ -35,10 +35,14 @@
 namespace vor {
 
 struct Counters {
-    uint32_t rays, nodes, evals, exact, shells, vtests;
-    uint32_t xinc;    // exact decisions of vertex rays (the vertex-in-cell / incircle test)
-    uint32_t vrays;   // vertex rays (towards u = L1 ∩ L2) among the rays and vertex tests
+    uint32_t rays, nodes, evals, exact, shells;
+    // vertex tests (rays towards a candidate vertex that confirmed it) in the low 16 bits, and
+    // all vertex rays (towards u = L1 ∩ L2, confirming or not) in the high 16 bits: one
+    // register for both (a lane's counts stay far below 2^16)
+    uint32_t vt;
+    uint32_t xinc;   // exact decisions of vertex rays (the vertex-in-cell / incircle test)
 };
+constexpr uint32_t VT_VRAY = 1u << 16;
 
 // ------------------------------------------------------------------------------ exact argmin
 struct XBest {
@@ -1086,8 +1090,8 @@ __device__ __forceinline__ int cell_step(const Cell &C, const float2 *__restrict
         leaf = (r == 1);
         // a shot ray (Lemma on shot rays) yields a corner; a ray that confirms a vertex is the
         // in-cell test of the vertex
-        if (leaf) K.vtests++; else K.rays++;
-        K.vrays += Den > 0;
+        if (leaf) K.vt++; else K.rays++;
+        K.vt += Den > 0 ? VT_VRAY : 0u;
     }
     if (phase < 3) {
         if (phase == 0) {

@@ -354,9 +354,9 @@ __device__ __forceinline__ void reduce_stats(const Counters &K, uint32_t edges, 
     atomicAdd(&sh[SL_SHELLS], (unsigned long long)K.shells);
     atomicAdd(&sh[SL_EDGES], (unsigned long long)edges);
     atomicAdd(&sh[SL_DEFERRED], (unsigned long long)deferred);
-    atomicAdd(&sh[SL_VTESTS], (unsigned long long)K.vtests);
+    atomicAdd(&sh[SL_VTESTS], (unsigned long long)(K.vt & 0xFFFFu));
     atomicAdd(&sh[SL_XINC], (unsigned long long)K.xinc);
-    atomicAdd(&sh[SL_VRAYS], (unsigned long long)K.vrays);
+    atomicAdd(&sh[SL_VRAYS], (unsigned long long)(K.vt >> 16));
     if (tree) {
         atomicAdd(&sh[SL_TREE], (unsigned long long)tree);
         atomicAdd(&sh[SL_TEVALS], (unsigned long long)K.evals);
@@ -574,7 +574,7 @@ __global__ __launch_bounds__(64) void k_cells_exact(
     }
     // every lane ran the same control flow: count it once; evaluations are split across lanes
     if (lane != 0) {
-        K.rays = K.nodes = K.exact = K.shells = K.vtests = K.xinc = K.vrays = 0;
+        K.rays = K.nodes = K.exact = K.shells = K.vt = K.xinc = 0;
         edges = 0;
     }
     reduce_stats(K, edges, 0, 0, sh, stats);
@@ -655,9 +655,9 @@ __global__ __launch_bounds__(64 * WIDE_WAVES) void k_cells_wide(
                 split_dir(L1, L2, d, Den, ex1, ex2);
                 Line L3{};
                 const int r = ray<MODE, Coop>(C, sc, sxy, d, Den, ex1, ex2, L3, K);
-                K.vrays += Den > 0;
+                K.vt += Den > 0 ? VT_VRAY : 0u;
                 if (r == 1) {   // u is a vertex of the cell: the subedge is prime
-                    K.vtests++;
+                    K.vt++;
                     continue;
                 }
                 K.rays++;
@@ -733,7 +733,7 @@ __global__ __launch_bounds__(64 * WIDE_WAVES) void k_cells_wide(
     // every lane of a wave ran the same control flow: count it once; evaluations are split
     // across the lanes
     if (lane != 0) {
-        K.rays = K.nodes = K.exact = K.shells = K.vtests = K.xinc = K.vrays = 0;
+        K.rays = K.nodes = K.exact = K.shells = K.vt = K.xinc = 0;
         edges = 0;
     }
     reduce_stats(K, edges, 0, 0, sh, stats);
