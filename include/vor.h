@@ -313,6 +313,34 @@ int vor_region_diag(int32_t device, int64_t n, const int32_t *geom, const int64_
 int vor_peak_fp32(int32_t device, double *tflops);
 int vor_peak_copy(int32_t device, uint64_t bytes, double *gbps);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): vor_compute of one set that allocates nothing.  Every
+ * working buffer of the run is carved out of a fixed device array of the library,
+ * VOR_NOALLOC_SCRATCH_BYTES on each GPU it runs on (held until the process ends); the outputs go
+ * to the caller's device buffers.  No hipMalloc, hipFree or other allocating call is made.
+ *   device     GPU ordinal
+ *   stream     hipStream_t the work is enqueued on (NULL: the null stream); the call returns
+ *              after that stream has finished the call's work
+ *   set        n <= VOR_NOALLOC_MAX_SITES; x, y device pointers (VOR_SET_DEVICE) or host
+ *              arrays; the box or a convex polygon X as for vor_compute
+ *   precision  vor_precision; tuning: the defaults of a new context
+ *   cell_off   [n+1] device: CSR offsets (as vor_result.cell_off)
+ *   nbr        [nbr_cap] device: neighbour lists; nbr_cap >= 6n + K + 16 (K = 4 for the box)
+ *   vtx        [nbr_cap] device: pair-form vertices, or NULL (no vertices)
+ *   del        [2 del_cap] device: Delaunay pairs; del_cap >= 3n + 8
+ *   entries, m host out: cell_off[n] and the number of Delaunay pairs;  stats: host out or NULL
+ * Every call on a GPU shares that GPU's array, which keeps the last call's contents (the run
+ * clears what must start at zero itself).  Calls of one process on one GPU are serialised by a
+ * lock held until the call's work is done; work the caller enqueues elsewhere that touches the
+ * outputs must wait for the return.  VOR_E_INVAL for n above the maximum, capacities below the
+ * bounds, null pointers or a bad set; validation and device errors as vor_compute. */
+#define VOR_NOALLOC_MAX_SITES 32768u
+#define VOR_NOALLOC_SCRATCH_BYTES (32u << 20)
+int vor_compute_noalloc(int32_t device, void *stream, const vor_set *set, int32_t precision,
+                        uint32_t *cell_off, int32_t *nbr, vor_rat *vtx, uint64_t nbr_cap,
+                        uint32_t *del, uint64_t del_cap, uint64_t *entries, uint64_t *m,
+                        vor_stats *stats);
+
 /* Version string of the library build (never NULL). */
 const char *vor_version(void);
 

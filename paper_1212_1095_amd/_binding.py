@@ -102,6 +102,10 @@ def lib():
         L.vor_filter_keys.argtypes = [C.c_int32, C.c_int64, P(C.c_int32), P(C.c_int32),
                                       P(C.c_int32), P(C.c_int64), P(C.c_int64), P(C.c_float),
                                       P(C.c_int32)]
+        L.vor_compute_noalloc.argtypes = [C.c_int32, C.c_void_p, P(vor_set), C.c_int32,
+                                          C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64,
+                                          C.c_void_p, C.c_uint64, P(C.c_uint64), P(C.c_uint64),
+                                          P(vor_stats)]
         L.vor_region_diag.argtypes = [C.c_int32, C.c_int64, P(C.c_int32), P(C.c_int64),
                                       P(C.c_float), P(C.c_int32), P(C.c_int32), P(C.c_float),
                                       P(C.c_int32), P(C.c_int32), P(C.c_float)]
@@ -111,7 +115,8 @@ def lib():
         for f in ("vor_create", "vor_destroy", "vor_compute", "vor_result_to_host", "vor_compute_batch", "vor_submit",
                   "vor_poll", "vor_ticket_times", "vor_ticket_count", "vor_footprint",
                   "vor_set_tuning", "vor_get_tuning",
-                  "vor_filter_keys", "vor_region_diag", "vor_lloyd", "vor_peak_fp32",
+                  "vor_filter_keys", "vor_region_diag", "vor_compute_noalloc", "vor_lloyd",
+                  "vor_peak_fp32",
                   "vor_peak_copy"):
             getattr(L, f).restype = C.c_int
         _lib = L
@@ -302,6 +307,25 @@ def vor_result_to_host(ctx, res: Result) -> Result:
     out.exact_ms, out.grid_ms, out.emit_ms = res.exact_ms, res.grid_ms, res.emit_ms
     out.graph_replayed, out.adaptive_ms = res.graph_replayed, res.adaptive_ms
     return out
+
+
+VOR_NOALLOC_MAX_SITES = 32768
+
+
+def vor_compute_noalloc(x, y, box, cell_off, nbr, vtx, nbr_cap, dele, del_cap,
+                        precision=VOR_FP32_FILTERED, device=0, stream=0, device_ptrs=False,
+                        region=None):
+    """vor_compute_noalloc (see include/vor.h): x, y host arrays, or (device address, n) pairs
+    with device_ptrs=True; cell_off, nbr, vtx (or 0), dele: device addresses of the caller's
+    output buffers.  Returns (entries, m, Stats)."""
+    s, keep = _make_set(x, y, box, device_ptrs, region)
+    e, m, st = C.c_uint64(), C.c_uint64(), vor_stats()
+    _check(lib().vor_compute_noalloc(int(device), C.c_void_p(stream or None), C.byref(s),
+                                     int(precision), C.c_void_p(cell_off), C.c_void_p(nbr),
+                                     C.c_void_p(vtx or None), int(nbr_cap), C.c_void_p(dele),
+                                     int(del_cap), C.byref(e), C.byref(m), C.byref(st)),
+           "vor_compute_noalloc")
+    return int(e.value), int(m.value), Stats(*[int(getattr(st, f)) for f, _ in vor_stats._fields_])
 
 
 def vor_compute_batch(ctx, sets):

@@ -8,8 +8,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libvor.so")
-SOURCES = ["vor_kernels.hip", "vor_api.cpp", "vor_plan.cpp", "vor_diag.hip", "vor_lloyd.hip",
-           "vor_peak.hip"]
+SOURCES = ["vor_kernels.hip", "vor_api.cpp", "vor_plan.cpp", "vor_noalloc.cpp", "vor_diag.hip",
+           "vor_lloyd.hip", "vor_peak.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
