@@ -135,12 +135,21 @@ def bench_exact_only(vor, torch, xd, yd, ps, steps):
     return ew, host, er.device_ms
 
 
+def batch_size_table():
+    """The autotuner's per-set table for uniform batches (empty when none is stored)."""
+    from paper_1212_1095_amd import autotune
+    return autotune.size_table("uniform")
+
+
 def bench_batched(vor, sets, name, steps=3, flags=0, kernel_roofline=False):
     """Sets in one call (one launch per stage, graph replayed), host inputs and host results as
-    the batch API takes them; the last step's results are checked against the oracle's digests."""
+    the batch API takes them, per-set grid parameters from the autotuner's batch table; the last
+    step's results are checked against the oracle's digests."""
     args = [(s.x, s.y, s.box) for s in sets]
     total = int(sum(s.n for s in sets))
+    table = batch_size_table()
     with vor.Context(flags=flags) as ctx:
+        ctx.size_tuning(table)
         ctx.compute_batch(args)   # warm-up and graph capture
         dev, cells, walls = [], [], []
         for _ in range(steps):
@@ -162,7 +171,10 @@ def bench_batched(vor, sets, name, steps=3, flags=0, kernel_roofline=False):
            "bit_exact_cells": checked, "bit_exact_error": err,
            "fallback_rates": dict(zip(("ray_order", "vertex_in_cell"),
                                       [round(v, 8) for v in st.fallback_rates()])),
-           "exact_decisions": st.exact_decisions}
+           "exact_decisions": st.exact_decisions,
+           "tuning": {"per_set_size_classes": len(table),
+                      "source": "autotuner batch table (tuning.json)" if table
+                      else "library default"}}
     if kernel_roofline:
         evals = st.evals - st.adaptive_evals
         kern_s = float(np.mean(cells)) / 1000.0
@@ -223,7 +235,11 @@ def bench_served(vor, count=200, seed=5, hi=1 << 20):
         return digest_check(kept, "config5")
 
     out = {"requests": count, "sites": total, "max_request_sites": hi, "vertices": True}
+    table = batch_size_table()
+    out["tuning"] = {"per_set_size_classes": len(table),
+                     "source": "autotuner batch table (tuning.json)" if table else "library default"}
     with vor.Context() as ctx:
+        ctx.size_tuning(table)
         _, fails, cap_s, kept = run(None)
         rate = count / cap_s
         out["capacity_req_per_s"] = round(rate, 1)

@@ -241,6 +241,21 @@ typedef struct {
 int vor_set_tuning(vor_ctx *ctx, const vor_tuning *t);
 int vor_get_tuning(vor_ctx *ctx, vor_tuning *t);
 
+/* Per-set grid parameters by size class, for batches and the request loop (the autotuner's
+ * batch table, Method 11.5's bucket side and the warm-start block of Method 11.6 per set):
+ * a set of n sites takes sites_per_bucket, block_halfwidth and leaf_halfwidth from the entry
+ * whose log2n is nearest to log2(n) (the first on a tie); block and scan_path stay the context's
+ * (they are launch-wide).  count == 0 clears the table (every set uses vor_set_tuning's).  At
+ * most 64 entries; ranges as vor_tuning, 0 <= log2n <= 30; VOR_E_INVAL otherwise.  Results do
+ * not depend on it. */
+typedef struct {
+    int32_t log2n;
+    float sites_per_bucket;
+    int32_t block_halfwidth;
+    int32_t leaf_halfwidth;
+} vor_size_tuning;
+int vor_set_size_tuning(vor_ctx *ctx, const vor_size_tuning *t, uint32_t count);
+
 /* Lloyd iterations on the integer grid (centroidal Voronoi relaxation, the kind of repeated
  * diagram computation the paper's introduction motivates the method with).  Each of `iters`
  * steps computes the diagram of the current sites (X and validation as vor_compute) and moves

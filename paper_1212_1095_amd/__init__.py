@@ -11,7 +11,7 @@ from ._binding import (  # noqa: F401
     VOR_FP32_FILTERED, VorError, Result, Stats,
     lib, lib_path, vor_create, vor_destroy, vor_compute, vor_compute_batch, vor_submit,
     vor_poll, vor_result_free, vor_result_to_host, vor_strerror, vor_set_tuning, vor_get_tuning,
-    vor_ticket_times, vor_ticket_count, vor_footprint,
+    vor_set_size_tuning, vor_ticket_times, vor_ticket_count, vor_footprint,
     vor_version, vor_filter_keys, vor_filter_keys_words, vor_region_diag, vor_lloyd,
     vor_peak_fp32, vor_peak_copy, vor_compute_noalloc, VOR_NOALLOC_MAX_SITES,
     Context,

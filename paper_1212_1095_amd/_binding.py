@@ -58,6 +58,11 @@ class vor_result(C.Structure):
                 ("t_done", C.c_double)]
 
 
+class vor_size_tuning(C.Structure):
+    _fields_ = [("log2n", C.c_int32), ("sites_per_bucket", C.c_float),
+                ("block_halfwidth", C.c_int32), ("leaf_halfwidth", C.c_int32)]
+
+
 class vor_tuning(C.Structure):
     _fields_ = [("sites_per_bucket", C.c_float), ("block", C.c_int32),
                 ("block_halfwidth", C.c_int32), ("leaf_halfwidth", C.c_int32),
@@ -96,6 +101,7 @@ def lib():
         L.vor_strerror.restype = C.c_char_p
         L.vor_set_tuning.argtypes = [C.c_void_p, P(vor_tuning)]
         L.vor_get_tuning.argtypes = [C.c_void_p, P(vor_tuning)]
+        L.vor_set_size_tuning.argtypes = [C.c_void_p, P(vor_size_tuning), C.c_uint32]
         L.vor_version.argtypes = []
         L.vor_lloyd.argtypes = [C.c_void_p, P(vor_set), C.c_uint32, P(C.c_int32),
                                 P(C.c_int32), P(C.c_uint32)]
@@ -114,7 +120,7 @@ def lib():
         L.vor_version.restype = C.c_char_p
         for f in ("vor_create", "vor_destroy", "vor_compute", "vor_result_to_host", "vor_compute_batch", "vor_submit",
                   "vor_poll", "vor_ticket_times", "vor_ticket_count", "vor_footprint",
-                  "vor_set_tuning", "vor_get_tuning",
+                  "vor_set_tuning", "vor_get_tuning", "vor_set_size_tuning",
                   "vor_filter_keys", "vor_region_diag", "vor_compute_noalloc", "vor_lloyd",
                   "vor_peak_fp32",
                   "vor_peak_copy"):
@@ -397,6 +403,15 @@ def vor_set_tuning(ctx, sites_per_bucket: float, block: int, block_halfwidth: in
     _check(lib().vor_set_tuning(ctx, C.byref(t)), "vor_set_tuning")
 
 
+def vor_set_size_tuning(ctx, entries) -> None:
+    """entries: [(log2n, sites_per_bucket, block_halfwidth, leaf_halfwidth)] (see include/vor.h);
+    [] clears the table."""
+    arr = (vor_size_tuning * max(1, len(entries)))()
+    for i, (k, rho, h, ht) in enumerate(entries):
+        arr[i] = vor_size_tuning(int(k), float(rho), int(h), int(ht))
+    _check(lib().vor_set_size_tuning(ctx, arr, len(entries)), "vor_set_size_tuning")
+
+
 def vor_get_tuning(ctx):
     t = vor_tuning()
     _check(lib().vor_get_tuning(ctx, C.byref(t)), "vor_get_tuning")
@@ -564,6 +579,9 @@ class Context:
     def tune(self, sites_per_bucket, block, block_halfwidth=0, leaf_halfwidth=0, scan_path=0):
         vor_set_tuning(self.h, sites_per_bucket, block, block_halfwidth, leaf_halfwidth,
                        scan_path)
+
+    def size_tuning(self, entries):
+        vor_set_size_tuning(self.h, entries)
 
     def close(self):
         if self.h:

@@ -183,6 +183,8 @@ struct vor_ctx {
     // the autotuned setting for uniform 2^20 sites, also the fastest measured for batches of
     // 32..65536-site sets and of 1000-site sets
     vor_tuning tune{1.5f, 256, 2, 0, VOR_PATH_GRID_FIRST};
+    // per-set grid parameters by size class (vor_set_size_tuning); empty: `tune` for every set
+    std::vector<vor_size_tuning> size_tune;
     Workspace ws;            // vor_compute / vor_compute_batch
     std::mutex mu;           // serialises vor_compute*
     bool use_graph = true;
@@ -206,6 +208,21 @@ struct vor_ctx {
 namespace {
 
 
+// The tuning a set of n sites runs with: the context's, with the grid parameters of the size
+// class nearest to log2 n when a size table is set.
+vor_tuning set_tuning(const vor_ctx *ctx, uint32_t n) {
+    vor_tuning t = ctx->tune;
+    if (ctx->size_tune.empty()) return t;
+    const double l = std::log2((double)std::max<uint32_t>(n, 1));
+    const vor_size_tuning *best = &ctx->size_tune[0];
+    for (const vor_size_tuning &e : ctx->size_tune)
+        if (std::fabs(e.log2n - l) < std::fabs(best->log2n - l)) best = &e;
+    t.sites_per_bucket = best->sites_per_bucket;
+    t.block_halfwidth = best->block_halfwidth;
+    t.leaf_halfwidth = best->leaf_halfwidth;
+    return t;
+}
+
 // Prepare descriptors, size the workspace and launch the pipeline on ws.stream.  Inputs are
 // either device pointers (single set, VOR_SET_DEVICE) or gathered into pinned staging and
 // copied.  Returns a VOR status; on success the launch is in flight.
@@ -223,7 +240,7 @@ int launch(vor_ctx *ctx, Workspace &ws, const std::vector<HostSet> &sets, bool v
     for (int i = 0; i < K; ++i) {
         const HostSet &s = sets[i];
         sides += s.nreg ? s.nreg : 4;
-        plan_set(ctx->tune, s, total, gtot, side_off, descs[i], ws.sides_h.data());
+        plan_set(set_tuning(ctx, s.n), s, total, gtot, side_off, descs[i], ws.sides_h.data());
         side_off += (int)s.nreg;
         set_off[i] = (int)total;
         total += s.n;
@@ -718,6 +735,21 @@ int vor_get_tuning(vor_ctx *ctx, vor_tuning *t) {
     return VOR_OK;
 }
 
+int vor_set_size_tuning(vor_ctx *ctx, const vor_size_tuning *t, uint32_t count) {
+    if (!ctx || (count && !t) || count > 64) return VOR_E_INVAL;
+    for (uint32_t i = 0; i < count; ++i) {
+        const vor_size_tuning &e = t[i];
+        if (e.log2n < 0 || e.log2n > 30) return VOR_E_INVAL;
+        if (!(e.sites_per_bucket >= 0.0625f && e.sites_per_bucket <= 64.0f)) return VOR_E_INVAL;
+        if (e.block_halfwidth < 0 || e.block_halfwidth > 16) return VOR_E_INVAL;
+        if (e.leaf_halfwidth < 0 || e.leaf_halfwidth > 4) return VOR_E_INVAL;
+    }
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    std::lock_guard<std::mutex> lq(ctx->qmu);
+    ctx->size_tune.assign(t, t + count);
+    return VOR_OK;
+}
+
 int vor_compute(vor_ctx *ctx, const vor_set *set, vor_result **out) {
     if (!ctx || !out) return VOR_E_INVAL;
     *out = nullptr;
@@ -859,7 +891,8 @@ int vor_submit(vor_ctx *ctx, const vor_set *set, uint64_t *ticket) {
     }
     r->t_submit = now_s();
     SetDesc d{};
-    choose_grid(h.box, set->n, ctx->tune.sites_per_bucket, ctx->tune.block_halfwidth, d, h.area);
+    const vor_tuning st = set_tuning(ctx, set->n);
+    choose_grid(h.box, set->n, st.sites_per_bucket, st.block_halfwidth, d, h.area);
     r->footprint = footprint_bytes(set->n, (uint64_t)d.gx * d.gy,
                                    !(ctx->opts.flags & VOR_NO_VERTICES), h.nreg ? h.nreg : 4);
     {
@@ -910,7 +943,8 @@ int vor_footprint(vor_ctx *ctx, const vor_set *set, uint64_t *bytes) {
     const int rc = check_set(set, h);
     if (rc != VOR_OK) return rc;
     SetDesc d{};
-    choose_grid(h.box, set->n, ctx->tune.sites_per_bucket, ctx->tune.block_halfwidth, d, h.area);
+    const vor_tuning st = set_tuning(ctx, set->n);
+    choose_grid(h.box, set->n, st.sites_per_bucket, st.block_halfwidth, d, h.area);
     *bytes = footprint_bytes(set->n, (uint64_t)d.gx * d.gy, !(ctx->opts.flags & VOR_NO_VERTICES),
                              h.nreg ? h.nreg : 4);
     return VOR_OK;

@@ -67,3 +67,20 @@ def test_autotune_table_lookup(tmp_path):
     assert autotune.best_params(1000, "uniform", path=str(p)) == (2.0, 256, 0, 0, 1)
     assert autotune.best_params(900000, "uniform", path=str(p)) == (1.0, 128, 2, 0, 0)
     assert autotune.best_params(1000, "clustered", path=str(p)) is None
+
+
+def test_autotune_size_table(tmp_path):
+    """The batch section of the table becomes the per-set size classes of Context.size_tuning."""
+    import json
+    from paper_1212_1095_amd import autotune
+    table = {"uniform_batch": {"12": {"sites_per_bucket": 1.5, "block_halfwidth": 2,
+                                      "leaf_halfwidth": 0, "ms": 3.0},
+                               "5": {"sites_per_bucket": 2.0, "block_halfwidth": 1, "ms": 9.0}}}
+    p = tmp_path / "t.json"
+    p.write_text(json.dumps(table))
+    assert autotune.size_table("uniform", path=str(p)) == [(5, 2.0, 1, 0), (12, 1.5, 2, 0)]
+    assert autotune.size_table("clustered", path=str(p)) == []
+    for e in json.load(open(autotune.TABLE)).get("uniform", {}).values():
+        rho, h, ht, path = (e["sites_per_bucket"], e["block_halfwidth"], e["leaf_halfwidth"],
+                            e["scan_path"])
+        assert (rho, h, ht, path) in autotune.DEFAULT_GRID, "shipped entry outside the sweep grid"

@@ -192,3 +192,26 @@ def test_admission_keeps_the_budget_across_workspaces(vor):
     assert sa == vor.VOR_OK and sb == vor.VOR_OK
     say(f"a: admit {ra.t_admit:.4f} done {ra.t_done:.4f}; b: admit {rb.t_admit:.4f}")
     assert rb.t_admit >= ra.t_done
+
+
+def test_size_tuning_changes_no_result(vor):
+    """Per-set grid parameters by size class (vor_set_size_tuning) change speed only: a batch of
+    sets of several sizes gives the same bytes with two different tables and with none."""
+    sizes = [40, 300, 1000, 5000, 20000, 70]
+    sets = [sitegen.uniform(n, 1 << 20, 900 + i) for i, n in enumerate(sizes)]
+    args = [(s.x, s.y, s.box) for s in sets]
+    out = []
+    tables = [[], [(6, 0.7, 1, 0), (10, 2.0, 2, 0), (14, 1.0, 3, 1)],
+              [(5, 3.0, 1, 2), (12, 0.5, 2, 0)]]
+    with vor.Context() as ctx:
+        for t in tables:
+            ctx.size_tuning(t)
+            rc, res = ctx.compute_batch(args)
+            assert rc == vor.VOR_OK
+            out.append(res)
+        with pytest.raises(vor.VorError):
+            ctx.size_tuning([(5, 100.0, 1, 0)])   # sites per bucket out of range
+    for res in out[1:]:
+        for a, b in zip(out[0], res):
+            same(a, b)
+    assert_matches_oracle(out[1][3], sets[3])
