@@ -17,7 +17,7 @@ from . import build as _build
 
 _lib = None
 
-ERRORS = {0: "ok", -1: "invalid argument", -2: "site not strictly inside X / box too large",
+ERRORS = {0: "ok", -1: "invalid argument", -2: "site outside X / box too large",
           -3: "duplicate sites", -4: "capacity", -5: "out of memory"}
 
 

@@ -31,7 +31,7 @@
  * site lines, so D < 2^51, |X|, |Y| < 2^82, and the clip test c_j D - N_j.(X, Y) < 2^110:
  * every quantity fits __int128 exactly.
  *
- * Error codes: 0 ok, -1 invalid argument, -2 site not strictly inside X or box too large,
+ * Error codes: 0 ok, -1 invalid argument, -2 site outside the closed X or box too large,
  * -3 two equal sites, -4 output capacity too small, -5 out of memory.
  */
 #include <pthread.h>
@@ -279,7 +279,10 @@ static int check_distinct(int32_t n, const int32_t *x, const int32_t *y) {
 }
 
 /*
- * Input check (problem statement in Section 2: distinct sites strictly inside X).
+ * Input check: distinct sites in the closed X.  The problem statement of Section 2 takes the
+ * sites in the interior of X and notes that the definition of the cells extends to sites on the
+ * boundary of X unchanged (a cell is X intersected with the half-planes of the other sites);
+ * sites on the boundary are accepted, sites outside X are not.
  */
 int vor_oracle_validate(int32_t n, const int32_t *x, const int32_t *y, int32_t x0, int32_t y0,
                         int32_t x1, int32_t y1) {
@@ -289,7 +292,7 @@ int vor_oracle_validate(int32_t n, const int32_t *x, const int32_t *y, int32_t x
     const int64_t lim = (int64_t)1 << 30;
     if (x0 < -lim || y0 < -lim || x1 > lim || y1 > lim) return -2;
     for (int32_t i = 0; i < n; ++i)
-        if (!(x[i] > x0 && x[i] < x1 && y[i] > y0 && y[i] < y1)) return -2;
+        if (!(x[i] >= x0 && x[i] <= x1 && y[i] >= y0 && y[i] <= y1)) return -2;
     return check_distinct(n, x, y);
 }
 
@@ -297,8 +300,8 @@ int vor_oracle_validate(int32_t n, const int32_t *x, const int32_t *y, int32_t x
  * X a convex polygon (Remark 11.1): 3 <= K <= 256 vertices, |coordinate| <= 2^30, bounding box
  * extent <= 2^24, counter-clockwise and strictly convex (every turn strictly left) and simple
  * (the edge directions go round once: they change between the upper and the lower half-plane
- * exactly twice).  Sites strictly inside every side.  -1 for a bad polygon, -2 for a site
- * outside or an extent too large, -3 for equal sites.
+ * exactly twice).  Sites inside or on every side (the closed X).  -1 for a bad polygon, -2
+ * for a site outside or an extent too large, -3 for equal sites.
  */
 int vor_oracle_validate_poly(int32_t n, const int32_t *x, const int32_t *y, int32_t K,
                              const int32_t *vx, const int32_t *vy) {
@@ -329,7 +332,7 @@ int vor_oracle_validate_poly(int32_t n, const int32_t *x, const int32_t *y, int3
     int out = 0;
     for (int32_t i = 0; i < n && !out; ++i)
         for (int32_t e = 0; e < K; ++e)
-            if (S->sides[e].nx * x[i] + S->sides[e].ny * y[i] >= S->sides[e].c) {
+            if (S->sides[e].nx * x[i] + S->sides[e].ny * y[i] > S->sides[e].c) {
                 out = 1;
                 break;
             }

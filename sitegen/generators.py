@@ -261,3 +261,44 @@ def in_polygon(n: int, region, seed: int = 1, kind: str = "uniform") -> PointSet
     xs, ys = xs[:n], ys[:n]
     return PointSet(xs.astype(np.int32), ys.astype(np.int32), (x0, y0, x1, y1), kind, seed,
                     region=(vx.astype(np.int32), vy.astype(np.int32)))
+
+
+def boundary_points(box, region=None, count: int = 8, seed: int = 1):
+    """`count` distinct integer points on the boundary of X (sides and corners): X is the box
+    (x0, y0, x1, y1), or the convex polygon region = (vx, vy), whose side from v_e to v_{e+1}
+    holds the points v_e + t (dx, dy) / gcd(|dx|, |dy|), t = 0 .. gcd."""
+    rng = _rng(seed)
+    if region is None:
+        x0, y0, x1, y1 = box
+        region = (np.array([x0, x1, x1, x0], np.int64), np.array([y0, y0, y1, y1], np.int64))
+    vx = np.asarray(region[0], np.int64)
+    vy = np.asarray(region[1], np.int64)
+    K = vx.shape[0]
+    pts = {(int(vx[e]), int(vy[e])) for e in rng.permutation(K)[:max(1, count // 4)]}
+    for _ in range(50 * count):
+        if len(pts) >= count:
+            break
+        e = int(rng.integers(0, K))
+        f = (e + 1) % K
+        dx, dy = int(vx[f] - vx[e]), int(vy[f] - vy[e])
+        g = math.gcd(abs(dx), abs(dy))
+        t = int(rng.integers(0, g + 1))
+        pts.add((int(vx[e]) + t * (dx // g), int(vy[e]) + t * (dy // g)))
+    pts = sorted(pts)[:count]
+    order = rng.permutation(len(pts))
+    return (np.array([pts[i][0] for i in order], np.int32),
+            np.array([pts[i][1] for i in order], np.int32))
+
+
+def with_boundary_sites(ps: PointSet, count: int, seed: int = 1) -> PointSet:
+    """ps with up to `count` more sites on the boundary of its X (distinct from its sites),
+    inserted at random positions of the id order."""
+    rng = _rng(seed)
+    bx, by = boundary_points(ps.box, ps.region, count, seed)
+    have = set(zip(ps.x.tolist(), ps.y.tolist()))
+    keep = [i for i in range(bx.shape[0]) if (int(bx[i]), int(by[i])) not in have]
+    x = np.concatenate([ps.x, bx[keep]])
+    y = np.concatenate([ps.y, by[keep]])
+    perm = rng.permutation(x.shape[0])
+    return PointSet(x[perm].astype(np.int32), y[perm].astype(np.int32), ps.box,
+                    ps.kind + "+boundary", ps.seed, dict(ps.meta), ps.region)

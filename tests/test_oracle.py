@@ -192,8 +192,9 @@ def test_validate_codes():
     box = (0, 0, 16, 16)
     ok = (np.array([1, 2], np.int32), np.array([1, 2], np.int32))
     assert cdiagram.validate(*ok, box) == 0
-    assert cdiagram.validate(np.array([0, 2], np.int32), np.array([1, 2], np.int32), box) == -2
-    assert cdiagram.validate(np.array([16, 2], np.int32), np.array([1, 2], np.int32), box) == -2
+    assert cdiagram.validate(np.array([-1, 2], np.int32), np.array([1, 2], np.int32), box) == -2
+    assert cdiagram.validate(np.array([17, 2], np.int32), np.array([1, 2], np.int32), box) == -2
+    assert cdiagram.validate(np.array([0, 16], np.int32), np.array([1, 2], np.int32), box) == 0
     assert cdiagram.validate(np.array([3, 3], np.int32), np.array([4, 4], np.int32), box) == -3
     assert cdiagram.validate(*ok, (5, 0, 5, 16)) == -1
     assert cdiagram.validate(*ok, (0, 0, (1 << 24) + 1, 16)) == -2

@@ -112,13 +112,17 @@ def test_polygon_validation(name, vx, vy, code):
     assert r == code, name
 
 
-def test_sites_on_or_outside_the_polygon_are_rejected():
+def test_sites_outside_the_polygon_are_rejected():
     vx = np.array([0, 100, 0], np.int32)
     vy = np.array([0, 0, 100], np.int32)
-    for px, py in [(50, 50), (0, 10), (60, 60), (-1, 5)]:   # on the hypotenuse, a side, outside
+    for px, py in [(60, 60), (-1, 5), (51, 50)]:   # outside
         r = cdiagram.validate(np.array([px], np.int32), np.array([py], np.int32),
                               (0, 0, 100, 100), region=(vx, vy))
         assert r == -2, (px, py)
+    for px, py in [(50, 50), (0, 10), (0, 0)]:     # on the hypotenuse, a side, a vertex
+        r = cdiagram.validate(np.array([px], np.int32), np.array([py], np.int32),
+                              (0, 0, 100, 100), region=(vx, vy))
+        assert r == 0, (px, py)
     r = cdiagram.validate(np.array([10, 10], np.int32), np.array([10, 10], np.int32),
                           (0, 0, 100, 100), region=(vx, vy))
     assert r == -3
