@@ -1,8 +1,8 @@
 /*
  * vor.h -- C ABI of the MI355X projector-algorithm Voronoi/Delaunay library (libvor.so).
  *
- * The library computes, for n distinct integer point sites strictly inside an axis-aligned box
- * X, every Voronoi cell of the diagram restricted to X (Section 2, definition of the Voronoi
+ * The library computes, for n distinct integer point sites in an axis-aligned box X (or a convex
+ * polygon X), every Voronoi cell of the diagram restricted to X (Section 2, definition of the Voronoi
  * diagram; Section 3, Method 3.1; Section 4, Algorithm 1 with the endpoint method of Section 5
  * and Appendix 1), stored as in Section 6, and the Delaunay graph read off the neighbour lists
  * (Section 7).  Each cell is computed independently of the others (Theorem 9.1(d)).
@@ -13,9 +13,12 @@
  *
  * Coordinates: int32, |coordinate| <= 2^30, box extent x1-x0 and y1-y0 at most 2^24.
  * X is the box, or a convex polygon given with the set (Remark 11.1 on a general convex X).
- * Sites must lie strictly inside X (x0 < x < x1, y0 < y < y1 for the box) and be pairwise distinct
- * (problem statement in Section 2; a duplicate is an error, never silently dropped, since
- * dropping it would renumber the sites).
+ * Sites must lie in the closed X and be pairwise distinct (problem statement in Section 2; a
+ * duplicate is an error, never silently dropped, since dropping it would renumber the sites).
+ * The problem statement takes the sites in the interior of X and notes that the definition of
+ * a cell extends to sites on its boundary: such sites are accepted, and their cells are computed
+ * in the box grown by one unit (which holds them strictly inside) and intersected with X, the
+ * embedding of the paper's remark on a non-polygonal X (Section 10).
  */
 #ifndef VOR_H
 #define VOR_H
@@ -30,7 +33,7 @@ extern "C" {
 #define VOR_OK 0
 #define VOR_PENDING 1          /* vor_poll: ticket not finished yet                           */
 #define VOR_E_INVAL (-1)       /* null pointer, n == 0, empty or inverted box, bad argument   */
-#define VOR_E_DOMAIN (-2)      /* a site not strictly inside X, |coord| > 2^30, extent > 2^24  */
+#define VOR_E_DOMAIN (-2)      /* a site outside X, |coord| > 2^30, extent > 2^24             */
 #define VOR_E_DUPLICATE (-3)   /* two equal sites                                             */
 #define VOR_E_NOMEM (-4)       /* device memory or the HBM budget cannot hold the job         */
 #define VOR_E_DEVICE (-5)      /* a HIP runtime error                                         */

@@ -952,6 +952,14 @@ struct Sink {
     __device__ __forceinline__ void drop_last() { up -= lastup; }
 };
 
+// Output of a cell walk as sorted positions and side codes (the lines' own names, for a pass
+// that still works on the lines before converting them).
+struct PosSink {
+    int *dst;
+    __device__ __forceinline__ void put(int m, int id) { dst[m] = id; }
+    __device__ __forceinline__ void drop_last() {}
+};
+
 // ------------------------------------------------------------------------------ ray shots
 // MODE 0: FP32 filter, give up (defer the cell) when a decision is not certified.
 // MODE 1: FP32 filter, exact decision when not certified.
@@ -1057,9 +1065,9 @@ __device__ __forceinline__ int cell_begin(const Cell &C, const float2 *__restric
 // One step.  Returns 0 (more steps), 1 (done: w.m lines in the sink), or
 //   -1 undecided in MODE 0, -2 stack / output capacity, -3 node limit (never expected),
 //   -4 the scanner met a heavy bucket.
-template <int MODE, class P, class Stack, class Sc>
+template <int MODE, class P, class Stack, class Sc, class Snk>
 __device__ __forceinline__ int cell_step(const Cell &C, const float2 *__restrict__ sxy, Sc &sc,
-                                         Stack &st, int scap, Sink &sink, int ocap, Counters &K,
+                                         Stack &st, int scap, Snk &sink, int ocap, Counters &K,
                                          CellWalk &w) {
     const int phase = w.phase++;
     Dir d;
@@ -1124,9 +1132,9 @@ __device__ __forceinline__ int cell_step(const Cell &C, const float2 *__restrict
 
 // A whole cell.  Returns the number of lines written to the sink (>= 3), or the negative codes
 // of cell_step.
-template <int MODE, class P, class Stack, class Sc>
+template <int MODE, class P, class Stack, class Sc, class Snk>
 __device__ __forceinline__ int run_cell(const Cell &C, const float2 *__restrict__ sxy, Sc &sc,
-                                        Stack &st, int scap, Sink &sink, int ocap, Counters &K) {
+                                        Stack &st, int scap, Snk &sink, int ocap, Counters &K) {
     CellWalk w;
     if (cell_begin(C, sxy, sc, st, w) < 0) return -4;
     for (;;) {

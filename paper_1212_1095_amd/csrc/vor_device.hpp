@@ -171,6 +171,8 @@ struct Cell {       // per-cell constants
     int W, H;       // box extent (relative box [0, W] x [0, H])
     int ns;         // 0: X is the box; else X is the convex polygon of `sides`
     const SideRel *sides;
+    int grow;       // box sides pushed out by this many units (1: the enlarged box that holds a
+                    // site on the boundary of X strictly inside; 0 otherwise)
 };
 
 // Side code -> line in p's doubled frame: N.w <= 2 (c - N.p).  Box sides (k = -code - 1: 0
@@ -196,7 +198,7 @@ __device__ __forceinline__ Line side_line(const Cell &C, int code) {
     L.id = code;
     L.nx = vert ? 0 : sgn;
     L.ny = vert ? sgn : 0;
-    L.c = 2 * (int64_t)(far ? ext - v : v);
+    L.c = 2 * ((int64_t)(far ? ext - v : v) + C.grow);
     return L;
 }
 __device__ __forceinline__ Line site_line(const Cell &C, const float2 *sxy, int pos) {

@@ -82,6 +82,9 @@ struct PipeArgs {
     int *qcount4() const { return small + 7; }   // cells the list-only adaptive run hands on
     int *qcount3() const { return small + 8; }
     int *nlist;             // [TREE_LEVELS - 1][ncap] node ids of refinement levels 2..
+    unsigned char *bflag;   // [total] by sorted position: the site lies on the boundary of X
+    int *queue5;            // sorted positions of such sites (the boundary pass) [total]
+    int *qcount5() const { return small + 15; }
 };
 
 // stages: 0 grid build and refinement, 1 filtered cell pass, 2 adaptive pass, 3 exact / deep

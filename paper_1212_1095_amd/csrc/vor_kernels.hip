@@ -42,10 +42,14 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
     return (b & 7) * per + (b >> 3);
 }
 
+constexpr int KEY_BOUNDARY = 1 << 30;   // bucket key flag: the site lies on the boundary of X
+
 __global__ void k_clear(int *__restrict__ p, long long n, int *__restrict__ small, int nsmall,
-                        unsigned long long *__restrict__ stats) {
+                        unsigned long long *__restrict__ stats, unsigned *__restrict__ flags,
+                        long long nflags) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0;
+    if (i < nflags) flags[i] = 0u;
     if (i < nsmall) small[i] = 0;
     if (i < SL_COUNT) stats[i] = 0;
 }
@@ -58,35 +62,49 @@ __global__ void k_prep(const SetDesc *__restrict__ sets, int nsets, const int *_
     if (i >= total) return;
     const SetDesc S = sets[find_set(set_off, nsets, i)];
     long long rx = (long long)in_x[i] - S.x0, ry = (long long)in_y[i] - S.y0;
-    bool inside = rx > 0 && rx < S.W && ry > 0 && ry < S.H;
-    for (int e = 0; e < S.ns && inside; ++e) {   // strictly inside every side of a polygon X
+    // in the closed X; on its boundary when on a side (the cell of such a site is computed in
+    // an enlarged box and clipped to X, see k_cells_bnd)
+    bool inside = rx >= 0 && rx <= S.W && ry >= 0 && ry <= S.H;
+    bool onb = S.ns == 0 && (rx == 0 || rx == S.W || ry == 0 || ry == S.H);
+    for (int e = 0; e < S.ns && inside; ++e) {   // inside or on every side of a polygon X
         const SideRel s = sides[S.side_off + e];
-        inside = (int64_t)s.nx * rx + (int64_t)s.ny * ry < s.c;
+        const int64_t v = (int64_t)s.nx * rx + (int64_t)s.ny * ry;
+        inside = v <= s.c;
+        onb |= v == s.c;
     }
     if (!inside) {
         atomicOr(status, ST_DOMAIN);
-        rx = rx < 1 ? 1 : (rx > S.W - 1 ? S.W - 1 : rx);
-        ry = ry < 1 ? 1 : (ry > S.H - 1 ? S.H - 1 : ry);
+        rx = rx < 0 ? 0 : (rx > S.W ? S.W : rx);
+        ry = ry < 0 ? 0 : (ry > S.H ? S.H : ry);
+        onb = false;
     }
     xyid[i] = make_int2((int)rx, (int)ry);
     const int bx = min((int)rx / S.s, S.gx - 1), by = min((int)ry / S.s, S.gy - 1);
     const int b = S.bucket_off + by * S.gx + bx;
-    key[i] = b;
+    key[i] = b | (onb ? KEY_BOUNDARY : 0);   // bucket ids stay below 2^30
     atomicAdd(&bcnt[b], 1);
 }
 
-// Counting-sort scatter.  bcnt counts down to zero again, ready for the next call.
+// Counting-sort scatter.  bcnt counts down to zero again, ready for the next call.  Sites on
+// the boundary of X are flagged by sorted position and listed for the boundary pass.
 __global__ void k_scatter(const SetDesc *__restrict__ sets, int nsets, const int *__restrict__ set_off,
                           int total, const int2 *__restrict__ xyid, const int *__restrict__ key,
                           const int *__restrict__ bstart, int *__restrict__ bcnt,
-                          float2 *__restrict__ sxy, int *__restrict__ sid) {
+                          float2 *__restrict__ sxy, int *__restrict__ sid,
+                          unsigned char *__restrict__ bflag, int *__restrict__ queue5,
+                          int *__restrict__ qcount5) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= total) return;
-    const int b = key[i];
+    const int kb = key[i];
+    const int b = kb & ~KEY_BOUNDARY;
     const int pos = bstart[b] + atomicSub(&bcnt[b], 1) - 1;
     const int2 r = xyid[i];
     sxy[pos] = make_float2((float)r.x, (float)r.y);
     sid[pos] = i - set_off[find_set(set_off, nsets, i)];
+    if (kb & KEY_BOUNDARY) {   // the flags were cleared with the counters
+        bflag[pos] = 1;
+        queue5[atomicAdd(qcount5, 1)] = pos;
+    }
 }
 
 // Leaf bucket of the site at sorted position pos: its first sorted position.
@@ -341,6 +359,7 @@ __device__ __forceinline__ Cell make_cell(const SetDesc &S, float2 p,
     C.H = S.H;
     C.ns = POLY ? S.ns : 0;
     C.sides = POLY ? sides + S.side_off : nullptr;
+    C.grow = 0;
     return C;
 }
 
@@ -376,7 +395,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5, 8))) v
     int total, int *__restrict__ ocnt, int *__restrict__ olines, int *__restrict__ ovf,
     int *__restrict__ dcnt, int *__restrict__ queue, int *__restrict__ qcount,
     int *__restrict__ queue3, int *__restrict__ qcount3, unsigned long long *__restrict__ stats,
-    const int *__restrict__ status) {
+    const unsigned char *__restrict__ bflag, const int *__restrict__ status) {
     __shared__ int stk[SCAP][BLOCK];
     __shared__ int rlo[MAXROWS][BLOCK], rhi[MAXROWS][BLOCK];
     __shared__ unsigned long long sh[SL_COUNT];
@@ -386,7 +405,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5, 8))) v
     const int pos = xcd_block(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
     Counters K{};
     uint32_t edges = 0, deferred = 0;
-    if (pos < total) {
+    if (pos < total && !bflag[pos]) {   // sites on the boundary of X: the boundary pass
         const SetDesc S = sets[find_set(set_off, nsets, pos)];
         const Cell C = make_cell<POLY>(S, sxy[pos], sides);
         const int k = sid[pos];
@@ -438,7 +457,8 @@ __global__ __launch_bounds__(BLOCK, LONLY ? 4 : 3) void k_cells_tree(
     const int *__restrict__ queue3, const int *__restrict__ qcount3,
     int *__restrict__ queue, int *__restrict__ qcount, int *__restrict__ queue4,
     int *__restrict__ qcount4, int *__restrict__ tlist,
-    unsigned long long *__restrict__ stats, const int *__restrict__ status) {
+    unsigned long long *__restrict__ stats, const unsigned char *__restrict__ bflag,
+    const int *__restrict__ status) {
     __shared__ int stk[SCAP][BLOCK];
     __shared__ int fr[TFRAMES][3][BLOCK];
     __shared__ unsigned long long sh[SL_COUNT];
@@ -456,6 +476,7 @@ __global__ __launch_bounds__(BLOCK, LONLY ? 4 : 3) void k_cells_tree(
     uint32_t edges = 0, deferred = 0, handled = 0;
     for (int qi = blockIdx.x * BLOCK + threadIdx.x; qi < nq; qi += gridDim.x * BLOCK) {
         const int pos = qin[qi];
+        if (bflag[pos]) continue;   // the boundary pass takes it
         const SetDesc S = sets[find_set(set_off, nsets, pos)];
         const Cell C = make_cell(S, sxy[pos], sides);
         const int k = sid[pos];
@@ -520,7 +541,8 @@ __global__ __launch_bounds__(64) void k_cells_exact(
     int *__restrict__ ovf, int *__restrict__ pool, int *__restrict__ poolcnt, long long poolcap,
     const int *__restrict__ queue, const int *__restrict__ qcount, int *__restrict__ queue2,
     int *__restrict__ qcount2, int *__restrict__ wbuf, int dcap,
-    unsigned long long *__restrict__ stats, int *__restrict__ status) {
+    unsigned long long *__restrict__ stats, const unsigned char *__restrict__ bflag,
+    int *__restrict__ status) {
     __shared__ unsigned long long sh[SL_COUNT];
     __shared__ int larea[LCAP > 0 ? 2 * LCAP : 1];
     if (*status & (ST_DOMAIN | ST_DUP)) return;
@@ -535,6 +557,7 @@ __global__ __launch_bounds__(64) void k_cells_exact(
     uint32_t edges = 0;
     for (int qi = blockIdx.x; qi < nq; qi += gridDim.x) {
         const int pos = queue[qi];
+        if (bflag[pos]) continue;   // the boundary pass takes it
         const SetDesc S = sets[find_set(set_off, nsets, pos)];
         const Cell C = make_cell(S, sxy[pos], sides);
         const int k = sid[pos];
@@ -732,6 +755,176 @@ __global__ __launch_bounds__(64 * WIDE_WAVES) void k_cells_wide(
     }
     // every lane of a wave ran the same control flow: count it once; evaluations are split
     // across the lanes
+    if (lane != 0) {
+        K.rays = K.nodes = K.exact = K.shells = K.vt = K.xinc = 0;
+        edges = 0;
+    }
+    reduce_stats(K, edges, 0, 0, sh, stats);
+}
+
+// ------------------------------------------------------------------------------ boundary sites
+// Cells of sites on the boundary of X (the definition of a cell extends to them unchanged; the
+// problem statement of Section 2 notes it).  The projector needs a ray origin strictly inside
+// the region, so such a cell is computed in the box grown by one unit on every side, which holds
+// every site strictly inside (the embedding in a larger region of the paper's remark on a
+// non-polygonal X, Section 10: the cells in the larger region intersected with X are the cells
+// in X); the sites all lie in X's grid, so the scans and their certificates are unchanged.  The
+// cell is then intersected with X one side at a time, exactly: for the vertices of consecutive
+// lines the sign of side - vertex in 128-bit integers; an edge is kept when one of its ends is
+// strictly inside; the side's line goes in once where the part outside begins.
+constexpr int BND_BLOCKS = 64;     // one-wave workers of the boundary pass
+constexpr int BND_CAP = DCAP1;     // lines of such a cell in the grown box (more: capacity error)
+constexpr int BND_LIST = BND_CAP + 256 + 8;   // lines after the intersection, at most (a polygon
+                                                 // X has at most 256 sides)
+constexpr int BND_XCODE = 1024;    // an inserted side e of X is named -(e+1) - BND_XCODE until
+                                   // the output (grown-box sides keep -1..-4)
+
+__device__ __forceinline__ Line bnd_line(const Cell &Cg, const Cell &Cx,
+                                         const float2 *__restrict__ sxy, int id) {
+    if (id >= 0) return site_line(Cg, sxy, id);
+    if (id < -BND_XCODE) {
+        Line L = side_line(Cx, id + BND_XCODE);
+        L.id = id;
+        return L;
+    }
+    return side_line(Cg, id);
+}
+
+// Sign of line L at the vertex of the consecutive lines A, B (p's doubled frame): with
+// Den = cross(N_A, N_B) > 0 and the vertex Z / Den, sign(c_L Den - N_L . Z): +1 inside, 0 on,
+// -1 outside.  |c Den| < 2^103 and |N . Z| < 2^101.
+__device__ __forceinline__ int vertex_side(const Line &A, const Line &B, const Line &L) {
+    const int64_t Den = (int64_t)A.nx * B.ny - (int64_t)A.ny * B.nx;
+    const i128 Zx = (i128)A.c * B.ny - (i128)B.c * A.ny;
+    const i128 Zy = (i128)A.nx * B.c - (i128)B.nx * A.c;
+    const i128 v = (i128)L.c * Den - ((i128)L.nx * Zx + (i128)L.ny * Zy);
+    return v > 0 ? 1 : (v < 0 ? -1 : 0);
+}
+
+// The cyclic list lin[0..m) intersected with the half-plane of line `xs` into lout; sgn is
+// scratch for m vertex signs.  Returns the new count.
+__device__ int clip_side(const Cell &Cg, const Cell &Cx, const float2 *__restrict__ sxy,
+                         const int *lin, int m, int xs, int *lout, int *sgn) {
+    const Line H = bnd_line(Cg, Cx, sxy, xs);
+    bool out = false;
+    Line A = bnd_line(Cg, Cx, sxy, lin[0]);
+    const Line L0 = A;
+    for (int i = 0; i < m; ++i) {   // vertex i between lines i and i + 1
+        const Line B = i + 1 < m ? bnd_line(Cg, Cx, sxy, lin[i + 1]) : L0;
+        sgn[i] = vertex_side(A, B, H);
+        out |= sgn[i] < 0;
+        A = B;
+    }
+    if (!out) {
+        for (int i = 0; i < m; ++i) lout[i] = lin[i];
+        return m;
+    }
+    // edge t lies on line t, from vertex t - 1 to vertex t; start at a kept edge (one exists:
+    // a convex cell that meets the open half-plane has a vertex strictly inside it)
+    int t0 = 0;
+    while (t0 < m && max(sgn[(t0 + m - 1) % m], sgn[t0]) <= 0) ++t0;
+    if (t0 == m) return -1;
+    int k = 0;
+    bool put = false;
+    lout[k++] = lin[t0];
+    for (int j = 1; j < m; ++j) {
+        const int t = (t0 + j) % m, v = (t + m - 1) % m;
+        if (!put && sgn[v] < 0) {
+            lout[k++] = xs;
+            put = true;
+        }
+        if (max(sgn[v], sgn[t]) > 0) lout[k++] = lin[t];
+    }
+    if (!put) lout[k++] = xs;   // the part outside is at the vertex before edge t0
+    return k;
+}
+
+template <int MODE>
+__global__ __launch_bounds__(64) void k_cells_bnd(
+    const SetDesc *__restrict__ sets, int nsets, const int *__restrict__ set_off,
+    const SideRel *__restrict__ sides,
+    const float2 *__restrict__ sxy, const int *__restrict__ sid, const int *__restrict__ bstart,
+    int *__restrict__ ocnt, int *__restrict__ olines, int *__restrict__ dcnt,
+    int *__restrict__ ovf, int *__restrict__ pool, int *__restrict__ poolcnt, long long poolcap,
+    const int *__restrict__ queue, const int *__restrict__ qcount,
+    unsigned long long *__restrict__ stats, int *__restrict__ status) {
+    __shared__ unsigned long long sh[SL_COUNT];
+    __shared__ int area[2 * BND_CAP];
+    __shared__ int la[BND_LIST], lb[BND_LIST], sg[BND_LIST];
+    if (*status & (ST_DOMAIN | ST_DUP)) return;
+    const int nq = *qcount;
+    if ((int)blockIdx.x >= nq) return;
+    if (threadIdx.x < SL_COUNT) sh[threadIdx.x] = 0;
+    __syncthreads();
+    const int lane = threadIdx.x;
+    Counters K{};
+    uint32_t edges = 0;
+    for (int qi = blockIdx.x; qi < nq; qi += gridDim.x) {
+        const int pos = queue[qi];
+        const SetDesc S = sets[find_set(set_off, nsets, pos)];
+        const Cell Cx = make_cell(S, sxy[pos], sides);   // X itself
+        Cell Cg = Cx;                                     // the grown box
+        Cg.ns = 0;
+        Cg.sides = nullptr;
+        Cg.grow = 1;
+        const int k = sid[pos];
+        const int g = S.site_off + k;
+        GridScan<Coop, GlobalRows, false> sc{GlobalRows{0}, bstart, false};
+        GStack st{area, 0};
+        PosSink sink{area + BND_CAP};
+        const int r = run_cell<MODE, Coop>(Cg, sxy, sc, st, BND_CAP, sink, BND_CAP, K);
+        if (r < 0) {
+            if (lane == 0) atomicOr(status, r == -2 ? ST_CAPACITY : ST_INTERNAL);
+            continue;
+        }
+        // the grown-box cell intersected with X (lane 0; a few lines and sides)
+        int m = 0, up = 0, off = -1;
+        if (lane == 0) {
+            m = r;
+            for (int t = 0; t < m; ++t) la[t] = area[BND_CAP + t];
+            int *cur = la, *nxt = lb;
+            const int ns = Cx.ns > 0 ? Cx.ns : 4;
+            for (int e = 0; e < ns && m > 0; ++e) {
+                if (m + 1 > BND_LIST) {
+                    m = -2;
+                    break;
+                }
+                m = clip_side(Cg, Cx, sxy, cur, m, -(e + 1) - BND_XCODE, nxt, sg);
+                int *t = cur;
+                cur = nxt;
+                nxt = t;
+            }
+            // names -> output: site ids, sides of X; no grown-box side may remain
+            for (int t = 0; t < m; ++t) {
+                const int id = cur[t];
+                int v;
+                if (id >= 0) v = sid[id];
+                else if (id < -BND_XCODE) v = id + BND_XCODE;
+                else {
+                    m = -1;
+                    break;
+                }
+                la[t] = v;
+                up += v > k;
+            }
+            if (m > KOUT) {
+                off = atomicAdd(poolcnt, m);
+                if ((long long)off + m > poolcap) m = -2;
+            }
+            if (m < 0) atomicOr(status, m == -2 ? ST_CAPACITY : ST_INTERNAL);
+        }
+        m = __shfl(m, 0, 64);
+        off = __shfl(off, 0, 64);
+        if (m < 0) continue;
+        int *dst = off >= 0 ? pool + off : olines + (size_t)g * KOUT;
+        for (int t = lane; t < m; t += 64) dst[t] = la[t];
+        if (lane == 0) {
+            ovf[g] = off;
+            ocnt[g] = m;
+            dcnt[g] = up;
+            edges += (uint32_t)m;
+        }
+    }
     if (lane != 0) {
         K.rays = K.nodes = K.exact = K.shells = K.vt = K.xinc = 0;
         edges = 0;
@@ -1114,20 +1307,24 @@ static void launch_fast(const PipeArgs &a, hipStream_t st) {
         k_cells_fast<BLOCK, true><<<nb, BLOCK, 0, st>>>(
             a.sets, a.nsets, a.set_off, a.sides, a.sxy, a.sid, a.bstart, a.total, a.ocnt,
             a.olines, a.ovf, a.dcnt, a.queue, a.qcount(), a.queue3, a.qcount3(), a.stats,
-            a.status());
+            a.bflag, a.status());
     else
         k_cells_fast<BLOCK, false><<<nb, BLOCK, 0, st>>>(
             a.sets, a.nsets, a.set_off, a.sides, a.sxy, a.sid, a.bstart, a.total, a.ocnt,
             a.olines, a.ovf, a.dcnt, a.queue, a.qcount(), a.queue3, a.qcount3(), a.stats,
-            a.status());
+            a.bflag, a.status());
 }
 
 template <int MODE>
 static void launch_exact(const PipeArgs &a, hipStream_t st) {
+    // cells of sites on the boundary of X
+    k_cells_bnd<MODE><<<BND_BLOCKS, 64, 0, st>>>(
+        a.sets, a.nsets, a.set_off, a.sides, a.sxy, a.sid, a.bstart, a.ocnt, a.olines, a.dcnt,
+        a.ovf, a.pool, a.poolcnt(), a.poolcap, a.queue5, a.qcount5(), a.stats, a.status_rw());
     k_cells_exact<MODE, DCAP1><<<a.exact_blocks, 64, 0, st>>>(
         a.sets, a.nsets, a.set_off, a.sides, a.sxy, a.sid, a.bstart, a.ocnt, a.olines, a.dcnt, a.ovf,
         a.pool, a.poolcnt(), a.poolcap, a.queue, a.qcount(), a.queue2,
-        a.qcount2(), a.wbuf, DCAP1, a.stats, a.status_rw());
+        a.qcount2(), a.wbuf, DCAP1, a.stats, a.bflag, a.status_rw());
     // deep cells: few workgroups, the subwedges of each cell spread over their waves
     k_cells_wide<MODE><<<DEEP_BLOCKS, 64 * WIDE_WAVES, 0, st>>>(
         a.sets, a.nsets, a.set_off, a.sides, a.sxy, a.sid, a.bstart, a.ocnt, a.olines, a.dcnt,
@@ -1140,14 +1337,17 @@ void launch_stage(const PipeArgs &a, hipStream_t st, int stage) {
     if (stage == 0) {
         // clear counters (no memset nodes: the sequence is captured as a graph)
         const long long n = a.gtot;
-        const long long big = n > 64 ? n : 64;
-        k_clear<<<nblk(big, 256), 256, 0, st>>>(a.bcnt, n, a.small, SMALL_INTS, a.stats);
+        const long long nf = ((long long)a.total + 3) / 4;   // boundary flags as 32-bit words
+        const long long big = std::max(std::max(n, nf), 64LL);
+        k_clear<<<nblk(big, 256), 256, 0, st>>>(a.bcnt, n, a.small, SMALL_INTS, a.stats,
+                                                (unsigned *)a.bflag, nf);
         // grid build (Method 11.5), then adaptive refinement of crowded buckets
         k_prep<<<nblk(T, 256), 256, 0, st>>>(a.sets, a.nsets, a.set_off, a.sides, a.in_x,
                                               a.in_y, T, a.xyid, a.key, a.bcnt, a.status());
         launch_scan(a.bcnt, a.gtot, a.bstart, a.scan_tmp, a.status(), 0, st);
         k_scatter<<<nblk(T, 256), 256, 0, st>>>(a.sets, a.nsets, a.set_off, T, a.xyid, a.key,
-                                                 a.bstart, a.bcnt, a.sxy, a.sid);
+                                                 a.bstart, a.bcnt, a.sxy, a.sid, a.bflag,
+                                                 a.queue5, a.qcount5());
         k_tree_mark0<<<nblk(a.gtot + 1, 256), 256, 0, st>>>(a.sets, a.nsets, a.gtot, a.bstart,
                                                             a.tchild, a.bcnt, a.nodes, a.ncap,
                                                             a.rootcnt(), a.status());
@@ -1180,11 +1380,11 @@ void launch_stage(const PipeArgs &a, hipStream_t st, int stage) {
             k_cells_tree<TREE_PASS_BLOCK, true><<<nb, TREE_PASS_BLOCK, 0, st>>>(
                 a.sets, a.nsets, a.set_off, a.sides, a.sxy, a.sid, a.bstart, a.tchild, a.nodes, a.tref,
                 a.ocnt, a.olines, a.ovf, a.dcnt, a.queue3, a.qcount3(), a.queue, a.qcount(),
-                a.queue4, a.qcount4(), a.tlist, a.stats, a.status());
+                a.queue4, a.qcount4(), a.tlist, a.stats, a.bflag, a.status());
             k_cells_tree<TREE_PASS_BLOCK, false><<<nb, TREE_PASS_BLOCK, 0, st>>>(
                 a.sets, a.nsets, a.set_off, a.sides, a.sxy, a.sid, a.bstart, a.tchild, a.nodes, a.tref,
                 a.ocnt, a.olines, a.ovf, a.dcnt, a.queue3, a.qcount3(), a.queue, a.qcount(),
-                a.queue4, a.qcount4(), a.tlist, a.stats, a.status());
+                a.queue4, a.qcount4(), a.tlist, a.stats, a.bflag, a.status());
         }
     } else if (stage == 3) {
         if (a.exact_only) launch_exact<2>(a, st);

@@ -191,7 +191,8 @@ int run_sizes(long long T, long long gtot, long long sides, int K, size_t nsides
     b[B_BSTART] = b[B_TCHILD] = 4ull * (gtot + 1 + tabcap);
     b[B_NODES] = sizeof(TNode) * ncap;
     b[B_TXY] = 8ull * T;
-    b[B_TID] = b[B_QUEUE3] = b[B_QUEUE4] = 4ull * T;
+    b[B_TID] = b[B_QUEUE3] = b[B_QUEUE4] = b[B_QUEUE5] = 4ull * T;
+    b[B_BFLAG] = 4ull * ((T + 3) / 4);   // cleared as 32-bit words
     b[B_TREF] = 4ull * (gtot + 1);
     b[B_NLIST] = 4ull * (TREE_LEVELS - 1) * ncap;
     b[B_SXY] = 8ull * T;
@@ -239,6 +240,8 @@ void fill_args(PipeArgs &a, void *const p[B_COUNT], const RunSizes &z, bool any_
     a.queue4 = (int *)p[B_QUEUE4];
     a.tref = (int *)p[B_TREF];
     a.nlist = (int *)p[B_NLIST];
+    a.bflag = (unsigned char *)p[B_BFLAG];
+    a.queue5 = (int *)p[B_QUEUE5];
     a.sxy = (float2 *)p[B_SXY];
     a.sid = (int *)p[B_SID];
     a.ocnt = (int *)p[B_OCNT];

@@ -185,13 +185,13 @@ def test_paper_counter_bounds(ctx):
 
 
 def test_input_error_on_the_first_call(vor):
-    """A fresh context whose first call has a site on the boundary of X: the grid is built, the
+    """A fresh context whose first call has a site outside X: the grid is built, the
     refinement is skipped because the error is already flagged, and no later kernel may walk the
     unwritten refinement slots; the call reports VOR_E_DOMAIN and the next call is exact."""
-    for box, x, y in [((0, 0, 100, 100), [0, 5, 7], [6, 7, 8]),
-                      ((0, 0, 1 << 20, 1 << 20), [3, 1 << 20, 9], [4, 5, 1 << 19])]:
+    for box, x, y in [((0, 0, 100, 100), [-1, 5, 7], [6, 7, 8]),
+                      ((0, 0, 1 << 20, 1 << 20), [3, (1 << 20) + 1, 9], [4, 5, 1 << 19])]:
         with vor.Context(device=0) as c:
-            say(f"first call with a site on the boundary of {box}")
+            say(f"first call with a site outside {box}")
             with pytest.raises(vor.VorError) as e:
                 c.compute(np.array(x, np.int32), np.array(y, np.int32), box)
             assert e.value.status == vor.VOR_E_DOMAIN
@@ -203,9 +203,9 @@ def test_errors(vor):
     with vor.Context() as c:
         box = (0, 0, 100, 100)
         for x, y, code in [([5, 5], [6, 6], vor.VOR_E_DUPLICATE),
-                           ([0, 5], [6, 7], vor.VOR_E_DOMAIN),
-                           ([100, 5], [6, 7], vor.VOR_E_DOMAIN),
-                           ([5, 50], [6, 100], vor.VOR_E_DOMAIN)]:
+                           ([-1, 5], [6, 7], vor.VOR_E_DOMAIN),
+                           ([101, 5], [6, 7], vor.VOR_E_DOMAIN),
+                           ([5, 50], [6, 101], vor.VOR_E_DOMAIN)]:
             say(f"error case {x} {y}")
             with pytest.raises(vor.VorError) as e:
                 c.compute(np.array(x, np.int32), np.array(y, np.int32), box)

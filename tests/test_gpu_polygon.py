@@ -133,7 +133,7 @@ def test_polygon_errors(vor):
                              ([0, 100, 30, 0], [0, 0, 30, 100], vor.VOR_E_INVAL),  # not convex
                              ([0, 60, -40, 40, -60], [100, -80, 30, 30, -80],
                               vor.VOR_E_INVAL),                                     # pentagram
-                             ([0, 100, 0], [0, 0, 25], vor.VOR_E_DOMAIN)]:          # site outside
+                             ([0, 100, 0], [0, 0, 20], vor.VOR_E_DOMAIN)]:          # site outside
             with pytest.raises(vor.VorError) as e:
                 c.compute(x, y, (0, 0, 100, 100),
                           region=(np.array(vx, np.int32), np.array(vy, np.int32)))
