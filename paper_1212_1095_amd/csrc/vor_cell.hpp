@@ -243,16 +243,14 @@ template <int W>
 __device__ __forceinline__ void eval_range(const Cell &C, const float2 *__restrict__ sxy, int pos,
                                            int end, float dx, float dy, int ex1, int ex2, Best &b,
                                            Counters &K) {
-    for (; pos + W < end; pos += 2 * W) {
-        const float2 a0 = sxy[pos], a1 = sxy[pos + W];
+    if (pos < end) K.evals += (uint32_t)((end - pos + W - 1) / W);
+    const float2 *q = sxy + pos;   // one pointer for both loads of a trip
+    for (; pos + W < end; pos += 2 * W, q += 2 * W) {
+        const float2 a0 = q[0], a1 = q[W];
         eval_at(C, a0, pos, dx, dy, ex1, ex2, b);
         eval_at(C, a1, pos + W, dx, dy, ex1, ex2, b);
-        K.evals += 2;
     }
-    if (pos < end) {
-        eval_site(C, sxy, pos, dx, dy, ex1, ex2, b);
-        ++K.evals;
-    }
+    if (pos < end) eval_at(C, q[0], pos, dx, dy, ex1, ex2, b);
 }
 
 // Row ranges of the cell's warm-start block (up to MAXROWS rows, h <= 2), loaded once per
