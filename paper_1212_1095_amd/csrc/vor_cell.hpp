@@ -462,15 +462,22 @@ struct GridScan {
                                             Counters &K) {
         Best b{FINF, FINF, NO_TAG};
         const Rect A = block_rect(C);
+        // A vertex ray (tcap bounds its endpoint) starts from its own rectangle S_I when that
+        // lies in the block: the rectangles of smaller bounds nest inside it, so the scan
+        // never grows, and the block's other sites are farther from the target than p.
+        const Rect O0 = first_rect(C, A, tcap, dx, dy);
         if (P::W == 1 && BR.nrows <= MAXROWS) {
-            for (int r = 0; r < BR.nrows; ++r) {
+            for (int y = O0.y0; y <= O0.y1; ++y) {
                 int pos, end;
-                BR.get(C, bstart, r, pos, end);
+                BR.get(C, bstart, y - A.y0, pos, end);
+                const int base = C.boff + y * C.gx;
+                if (O0.x0 != A.x0) pos = bstart[base + O0.x0];
+                if (O0.x1 != A.x1) end = bstart[base + O0.x1 + 1];
                 eval_range<P::W>(C, sxy, pos + P::lane(), end, dx, dy, ex1, ex2, b, K);
             }
         } else {
-            scan_rect_f32<P, DETECT>(C, sxy, bstart, A, Rect{1, 0, 1, 0}, dx, dy, ex1, ex2, b, K,
-                                     heavy);
+            scan_rect_f32<P, DETECT>(C, sxy, bstart, O0, Rect{1, 0, 1, 0}, dx, dy, ex1, ex2, b,
+                                     K, heavy);
         }
         P::reduce(b);
         consider_sides(C, dx, dy, ex1, ex2, b);
@@ -478,7 +485,7 @@ struct GridScan {
         float U = upper_of(C, sxy, b.w, dx, dy);
         float Uw = U;
         Rect R = need_rect(C, fminf(U, tcap), dx, dy);
-        Rect O = A;
+        Rect O = O0;
         while (!(DETECT && heavy) && !rect_inside(R, O)) {
             const Rect N = grow_rect(O, R);
             scan_rect_f32<P, DETECT>(C, sxy, bstart, N, O, dx, dy, ex1, ex2, b, K, heavy);
@@ -509,7 +516,7 @@ struct GridScan {
     __device__ __forceinline__ void exact_all(const Cell &C, const float2 *__restrict__ sxy,
                                               const Dir &d, float tu_hi, int ex1, int ex2,
                                               XBest &xb, Counters &K) {
-        const Rect A = block_rect(C);
+        const Rect A = first_rect(C, block_rect(C), tu_hi, d.fx, d.fy);
         exact_rect<false, P>(C, sxy, bstart, d, A, Rect{1, 0, 1, 0}, FINF, ex1, ex2, xb, K);
         P::reduce(xb);
         exact_sides(C, d, FINF, false, ex1, ex2, xb);
@@ -811,7 +818,7 @@ struct TreeScan {
             return ScanOut{};
         }
         Best b{FINF, FINF, NO_TAG};
-        float T0 = FINF;
+        float T0 = tcap;   // a vertex ray skips the sites outside the disk of its bound
         visit_f32<false>(C, sxy, Q0, NO_RECT, T0, tcap, dx, dy, ex1, ex2, b, K);
         P::reduce(b);
         consider_sides(C, dx, dy, ex1, ex2, b);
@@ -889,8 +896,8 @@ struct TreeScan {
     __device__ __forceinline__ void exact_all(const Cell &C, const float2 *__restrict__ sxy,
                                               const Dir &d, float tu_hi, int ex1, int ex2,
                                               XBest &xb, Counters &K) {
-        const Disk all{0.0f, 0.0f, FINF};
-        visit_exact<false>(C, sxy, d, Q0, NO_RECT, all, FINF, ex1, ex2, xb, K);
+        visit_exact<false>(C, sxy, d, Q0, NO_RECT, need_disk(C, tu_hi, d.fx, d.fy), FINF, ex1,
+                           ex2, xb, K);
         P::reduce(xb);
         exact_sides(C, d, FINF, false, ex1, ex2, xb);
         Rect O = Q0;

@@ -348,6 +348,15 @@ __device__ __forceinline__ Rect block_rect(const Cell &C) {
                 min(C.by + C.h, C.gy - 1)};
 }
 
+// The first rectangle a scan covers: the block A, or, when tcap bounds the endpoint parameter
+// (a vertex ray), the rectangle S_I of that bound if it lies inside A.
+__device__ __forceinline__ Rect first_rect(const Cell &C, const Rect &A, float tcap, float dx,
+                                           float dy) {
+    if (!(tcap < FINF)) return A;
+    const Rect R0 = need_rect(C, tcap, dx, dy);
+    return rect_inside(R0, A) ? R0 : A;
+}
+
 // The next scanned rectangle: the bounding box of the scanned rectangle A and the needed
 // rectangle R, but at most A widened by its own size on each side (a poor first bound gives
 // a huge R; the region then grows geometrically and the bound tightens on the way).
