@@ -229,7 +229,7 @@ __device__ __forceinline__ void consider_sides(const Cell &C, float dx, float dy
 __device__ __forceinline__ void eval_at(const Cell &C, float2 a, int pos, float dx, float dy,
                                         int ex1, int ex2, Best &b) {
     const float ex = a.x - C.pxf, ey = a.y - C.pyf;
-    float key = key_lo_line(site_q(ex, ey), ex, ey, dx, dy);
+    float key = key_lo_scan(ex, ey, dx, dy);
     key = (pos == ex1 || pos == ex2) ? FINF : key;
     consider(key, pos, b);
 }

@@ -108,6 +108,21 @@ __device__ __forceinline__ float key_lo_line(float c, float nx, float ny, float 
     const float key = c * __builtin_amdgcn_rcpf(up);
     return up > 0.0f ? key : FINF;
 }
+// The same bound for a site in the argmin scans, without the test: up = max(., 0) is never -0
+// (the fma adds +0 or more to den), so a line with up <= 0 gets c / +0 = +inf, and q carries an
+// added 2^-100 so that the site p itself (delta = 0, den = 0) gets 2^-100 / +0 = +inf rather than
+// NaN.  For every other site q >= 1, where 2^-100 is far below half an ulp: q still rounds to a
+// neighbour of the exact |delta|^2 within half an ulp (only an exact tie may round the other
+// way), so the error bounds above hold unchanged.
+constexpr float Q_TINY = 0x1p-100f;
+__device__ __forceinline__ float key_lo_scan(float ex, float ey, float dx, float dy) {
+    const float q = fmaf(ex, ex, fmaf(ey, ey, Q_TINY));
+    const float mx = ex * dx, my = ey * dy;
+    const float den = mx + my;
+    const float S = fabsf(mx) + fabsf(my);
+    const float up = fmaxf(fmaf(GAMMA, S, den), 0.0f);
+    return q * __builtin_amdgcn_rcpf(up);
+}
 // Upper bound key (+inf unless N.d is certainly > 0).
 __device__ __forceinline__ float key_hi_line(float c, float nx, float ny, float dx, float dy) {
     const float mx = nx * dx, my = ny * dy;
