@@ -83,6 +83,7 @@ struct PipeArgs {
     int *qcount3() const { return small + 8; }
     int *nlist;             // [TREE_LEVELS - 1][ncap] node ids of refinement levels 2..
     unsigned char *bflag;   // [total] by sorted position: the site lies on the boundary of X
+    unsigned char *hand;    // [total] by sorted position: the filtered pass handed the cell on
     int *queue5;            // sorted positions of such sites (the boundary pass) [total]
     int *qcount5() const { return small + 15; }
 };

@@ -9,7 +9,8 @@
 //             the distinctness remark in Appendix 2, done per leaf)
 //   cells     the projector algorithm per cell, FP32 filtered; undecided cells are queued,
 //             cells whose scans meet a crowded bucket are handed to the adaptive pass
-//   adaptive  those cells again, scanning the refined buckets by coordinate rectangles
+//   adaptive  those cells again: on local grids of their own density (chunks of consecutive
+//             cells), then the rest by scanning the refined buckets by coordinate rectangles
 //   exact     queued cells again with exact fallback (or every cell, exact-only precision)
 //   deep      cells deeper than the exact pass's per-worker capacity
 //   scans     line counts -> CSR offsets, Delaunay counts (from the cell passes) -> offsets
@@ -22,6 +23,7 @@
 
 #include "vor_cell.hpp"
 #include "vor_internal.h"
+#include "vor_local.hpp"
 #include "vor_tree.hpp"
 
 namespace vor {
@@ -363,9 +365,10 @@ __device__ __forceinline__ Cell make_cell(const SetDesc &S, float2 p,
     return C;
 }
 
+// tree: cells taken by the adaptive pass; adaptive: the evaluations are the adaptive pass's.
 __device__ __forceinline__ void reduce_stats(const Counters &K, uint32_t edges, uint32_t deferred,
                                              uint32_t tree, unsigned long long *sh,
-                                             unsigned long long *stats) {
+                                             unsigned long long *stats, bool adaptive = false) {
     atomicAdd(&sh[SL_RAYS], (unsigned long long)K.rays);
     atomicAdd(&sh[SL_NODES], (unsigned long long)K.nodes);
     atomicAdd(&sh[SL_EVALS], (unsigned long long)K.evals);
@@ -376,10 +379,8 @@ __device__ __forceinline__ void reduce_stats(const Counters &K, uint32_t edges, 
     atomicAdd(&sh[SL_VTESTS], (unsigned long long)(K.vt & 0xFFFFu));
     atomicAdd(&sh[SL_XINC], (unsigned long long)K.xinc);
     atomicAdd(&sh[SL_VRAYS], (unsigned long long)(K.vt >> 16));
-    if (tree) {
-        atomicAdd(&sh[SL_TREE], (unsigned long long)tree);
-        atomicAdd(&sh[SL_TEVALS], (unsigned long long)K.evals);
-    }
+    if (tree) atomicAdd(&sh[SL_TREE], (unsigned long long)tree);
+    if (adaptive) atomicAdd(&sh[SL_TEVALS], (unsigned long long)K.evals);
     __syncthreads();
     if (threadIdx.x < SL_COUNT && sh[threadIdx.x]) atomicAdd(&stats[threadIdx.x], sh[threadIdx.x]);
 }
@@ -395,7 +396,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5, 8))) v
     int total, int *__restrict__ ocnt, int *__restrict__ olines, int *__restrict__ ovf,
     int *__restrict__ dcnt, int *__restrict__ queue, int *__restrict__ qcount,
     int *__restrict__ queue3, int *__restrict__ qcount3, unsigned long long *__restrict__ stats,
-    const unsigned char *__restrict__ bflag, const int *__restrict__ status) {
+    const unsigned char *__restrict__ bflag, unsigned char *__restrict__ hand,
+    const int *__restrict__ status) {
     __shared__ int stk[SCAP][BLOCK];
     __shared__ int rlo[MAXROWS][BLOCK], rhi[MAXROWS][BLOCK];
     __shared__ unsigned long long sh[SL_COUNT];
@@ -405,6 +407,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5, 8))) v
     const int pos = xcd_block(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
     Counters K{};
     uint32_t edges = 0, deferred = 0;
+    bool handed = false;
     if (pos < total && !bflag[pos]) {   // sites on the boundary of X: the boundary pass
         const SetDesc S = sets[find_set(set_off, nsets, pos)];
         const Cell C = make_cell<POLY>(S, sxy[pos], sides);
@@ -423,57 +426,265 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5, 8))) v
             ocnt[g] = -1;
             if (r == -4) {
                 queue3[atomicAdd(qcount3, 1)] = pos;
+                handed = true;
             } else {
                 queue[atomicAdd(qcount, 1)] = pos;
                 deferred = 1;
             }
         }
     }
+    if (pos < total) hand[pos] = handed;   // every position written: no clearing needed
     reduce_stats(K, edges, deferred, 0, sh, stats);
 }
 
-// Adaptive pass: the cells handed on by the filtered pass, one thread per cell over a
-// persistent grid, scanning the refined buckets (TreeScan).  It runs twice: first with list
-// scans only (LONLY; FP32 decisions only; the cells whose rays leave their list's region or
-// meet an uncertified decision go to queue4), then with the full scanner over queue4, which
-// decides uncertified rays exactly in the lane.  The list-only run keeps every lane in the same
-// flat loop and fits four waves per SIMD (a few spills), the full run three.  Cells over the
-// work budget or the stack / line capacity go to the exact pass.
+// Adaptive pass, first part: the handed-over cells (hand[pos], or every cell with `all`) in
+// chunks of LOC_BLOCK consecutive sorted positions, one workgroup per chunk and one thread per
+// cell, on local grids (vor_local.hpp).  A group of the chunk's cells (at first all of them)
+// takes as its region RW the bounding box of its cells widened by LOC_MARGIN local spacings;
+// the workgroup gathers the leaves that meet RW level by level, copies the sites inside RW to
+// LDS and buckets them at LOC_SPB sites per bucket; then every thread of the group walks its
+// cell (FP32 decisions).  A region with more than LOC_CAP sites (a group that spans distant
+// parts of the tree order) splits the group in halves, down to LOC_MINGROUP cells.  Cells whose
+// rays leave RW or meet an uncertified decision go to queue4 (the tree scans), as do the cells
+// of a group that cannot be split further and cells of a second set in the chunk; cells over the
+// stack / line capacity go to the exact pass.
+__global__ __launch_bounds__(LOC_BLOCK) void k_cells_local(
+    const SetDesc *__restrict__ sets, int nsets, const int *__restrict__ set_off,
+    const SideRel *__restrict__ sides, const float2 *__restrict__ sxy,
+    const int *__restrict__ sid, const int *__restrict__ tstart, const int *__restrict__ tchild,
+    const TNode *__restrict__ nodes, const int *__restrict__ tref, int total,
+    const unsigned char *__restrict__ hand, int all, const int *__restrict__ qcount3,
+    int *__restrict__ ocnt, int *__restrict__ olines, int *__restrict__ ovf,
+    int *__restrict__ dcnt, int *__restrict__ queue, int *__restrict__ qcount,
+    int *__restrict__ queue4, int *__restrict__ qcount4,
+    unsigned long long *__restrict__ stats, const unsigned char *__restrict__ bflag,
+    const int *__restrict__ status) {
+    __shared__ float2 lxy[LOC_CAP];
+    __shared__ int lpos[LOC_CAP];
+    __shared__ int lstart[LOC_BCAP + 1];
+    // leaf ranges of the gather (first position, full flag, prefix); then the sort's counters
+    __shared__ int raux[3 * LOC_RCAP];
+    // the gather's frontier and node fields; then the gathered sites, unsorted; then the
+    // walks' stacks and block rows
+    __shared__ int work[(SCAP + 2 * MAXROWS) * LOC_BLOCK];
+    __shared__ unsigned long long sh[SL_COUNT];
+    __shared__ unsigned long long s_rc;
+    __shared__ int s_set, s_ncell, s_bb[4], s_cnt, s_fail, s_nf[2], s_wsum[LOC_BLOCK / 64];
+    __shared__ int s_gsp, s_glo[8], s_ghi[8], s_lo, s_hi;
+    static_assert(3 * LOC_CAP <= (SCAP + 2 * MAXROWS) * LOC_BLOCK, "gather staging fits");
+    static_assert(11 * LOC_NF <= (SCAP + 2 * MAXROWS) * LOC_BLOCK, "gather frontier fits");
+    if (*status) return;
+    if (*qcount3 == 0) return;   // nothing handed over
+    const int tid = threadIdx.x;
+    if (tid < SL_COUNT) sh[tid] = 0;
+    float2 *const txy = reinterpret_cast<float2 *>(work);
+    int *const tpos = work + 2 * LOC_CAP;
+    const RangeList RL{raux, raux + LOC_RCAP, raux + 2 * LOC_RCAP, &s_rc, &s_fail};
+    const Tree T{tstart, tchild, nodes, tref};
+    Counters K{};
+    uint32_t edges = 0, deferred = 0, handled = 0;
+    const int nchunks = (total + LOC_BLOCK - 1) / LOC_BLOCK;
+    for (int c = blockIdx.x; c < nchunks; c += gridDim.x) {
+        const int pos = c * LOC_BLOCK + tid;
+        const bool cand = pos < total && (all || hand[pos]) && !bflag[pos];
+        // every thread is past the previous chunk here, and takes the same branch
+        if (!__syncthreads_or(cand)) continue;
+        const int set = cand ? find_set(set_off, nsets, pos) : nsets;
+        handled += cand;
+        if (tid == 0) {
+            s_set = nsets;
+            s_gsp = 1;
+            s_glo[0] = 0;
+            s_ghi[0] = LOC_BLOCK;
+        }
+        __syncthreads();
+        if (cand) atomicMin(&s_set, set);
+        __syncthreads();
+        const int cs = s_set;   // the chunk's set: the smallest among its cells
+        if (cand && set != cs) queue4[atomicAdd(qcount4, 1)] = pos;
+        const SetDesc S = sets[cs];
+        for (;;) {
+            if (s_gsp == 0) break;   // uniform: the stack changes only before a barrier
+            __syncthreads();         // every thread has read it
+            if (tid == 0) {
+                --s_gsp;
+                s_lo = s_glo[s_gsp];
+                s_hi = s_ghi[s_gsp];
+                s_ncell = 0;
+                s_bb[0] = s_bb[2] = INT32_MAX;
+                s_bb[1] = s_bb[3] = INT32_MIN;
+                s_fail = 0;
+                s_cnt = 0;
+                s_rc = 0;
+                s_nf[0] = 0;
+            }
+            __syncthreads();
+            const int glo = s_lo, ghi = s_hi;
+            const bool mine = cand && set == cs && tid >= glo && tid < ghi;
+            const float2 p = mine ? sxy[pos] : make_float2(0.0f, 0.0f);
+            if (mine) {
+                atomicAdd(&s_ncell, 1);
+                atomicMin(&s_bb[0], (int)p.x);
+                atomicMax(&s_bb[1], (int)p.x);
+                atomicMin(&s_bb[2], (int)p.y);
+                atomicMax(&s_bb[3], (int)p.y);
+            }
+            __syncthreads();
+            if (s_ncell == 0) continue;   // uniform
+            // the region: the cells' box widened by LOC_MARGIN spacings of their own density
+            const float bw = (float)(s_bb[1] - s_bb[0] + 1), bh = (float)(s_bb[3] - s_bb[2] + 1);
+            const int mg = (int)ceilf(LOC_MARGIN * sqrtf(bw * bh / (float)s_ncell)) + 2;
+            const Rect RW{max(s_bb[0] - mg, 0), min(s_bb[1] + mg, S.W), max(s_bb[2] - mg, 0),
+                          min(s_bb[3] + mg, S.H)};
+            gather_leaves(S, T, RW, RL, work, s_nf, s_wsum);
+            __syncthreads();
+            const int nr = min((int)(s_rc & 0xffffffffull), LOC_RCAP);
+            const long long ntot = (long long)(s_rc >> 32);
+            bool fail = s_fail || ntot > 4 * LOC_CAP;
+            if (!fail) {
+                // copy the sites inside RW (unsorted) to the staging arrays
+                for (int i = tid; i < (int)ntot; i += LOC_BLOCK) {
+                    int lo = 0, hi = nr - 1;   // the range holding flat index i
+                    while (lo < hi) {
+                        const int mid = (lo + hi + 1) >> 1;
+                        if (RL.ofs[mid] <= i) lo = mid; else hi = mid - 1;
+                    }
+                    const int q = RL.lo[lo] + (i - RL.ofs[lo]);
+                    const float2 a = sxy[q];
+                    if (RL.full[lo] || in_rect(RW, a.x, a.y)) {
+                        const int slot = atomicAdd(&s_cnt, 1);
+                        if (slot < LOC_CAP) {
+                            txy[slot] = a;
+                            tpos[slot] = q;
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+            const int nl = s_cnt;
+            fail = fail || nl > LOC_CAP;
+            if (fail) {
+                // split the group, or hand its cells on
+                const bool split = ghi - glo > LOC_MINGROUP;
+                if (split && tid == 0) {
+                    const int mid = (glo + ghi) >> 1;
+                    s_glo[s_gsp] = mid;
+                    s_ghi[s_gsp] = ghi;
+                    s_glo[s_gsp + 1] = glo;
+                    s_ghi[s_gsp + 1] = mid;
+                    s_gsp += 2;
+                }
+                if (!split && mine) queue4[atomicAdd(qcount4, 1)] = pos;
+                __syncthreads();
+                continue;
+            }
+            // local buckets at about LOC_SPB sites each, at most LOC_BCAP of them
+            const int rw = RW.x1 - RW.x0 + 1, rh = RW.y1 - RW.y0 + 1;
+            int sb = max(1, (int)ceilf(sqrtf((float)rw * (float)rh * LOC_SPB / (float)nl)));
+            int gx = (rw + sb - 1) / sb, gy = (rh + sb - 1) / sb;
+            while ((long long)gx * gy > LOC_BCAP) {
+                sb += sb / 4 + 1;
+                gx = (rw + sb - 1) / sb;
+                gy = (rh + sb - 1) / sb;
+            }
+            const int nb = gx * gy, ox = RW.x0, oy = RW.y0;
+            // counting sort of the staged sites by local bucket
+            for (int b2 = tid; b2 <= nb; b2 += LOC_BLOCK) lstart[b2] = 0;
+            for (int b2 = tid; b2 < nb; b2 += LOC_BLOCK) raux[b2] = 0;   // fill counters
+            __syncthreads();
+            for (int i = tid; i < nl; i += LOC_BLOCK) {
+                const int bx = ((int)txy[i].x - ox) / sb, by = ((int)txy[i].y - oy) / sb;
+                atomicAdd(&lstart[by * gx + bx], 1);
+            }
+            __syncthreads();
+            {
+                // exclusive scan of the nb <= 4 LOC_BLOCK counts, four per thread
+                int v[4], sum = 0;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int b2 = 4 * tid + k;
+                    v[k] = b2 < nb ? lstart[b2] : 0;
+                    sum += v[k];
+                }
+                int tot;
+                int before = block_exscan(sum, s_wsum, tot);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int b2 = 4 * tid + k;
+                    if (b2 < nb) lstart[b2] = before;
+                    before += v[k];
+                }
+                if (tid == 0) lstart[nb] = tot;   // = nl
+            }
+            __syncthreads();
+            for (int i = tid; i < nl; i += LOC_BLOCK) {
+                const float2 a = txy[i];
+                const int bk = (((int)a.y - oy) / sb) * gx + ((int)a.x - ox) / sb;
+                const int slot = lstart[bk] + atomicAdd(&raux[bk], 1);
+                lxy[slot] = a;
+                lpos[slot] = tpos[i];
+            }
+            __syncthreads();
+            if (mine) {
+                const Cell C = make_cell(S, p, sides);
+                const LocalGrid G{lxy, lstart, RW, ox, oy, sb, gx, gy};
+                const Cell CL = local_cell(C, G);
+                const int k = sid[pos];
+                const int g = S.site_off + k;
+                int(*stk)[LOC_BLOCK] = reinterpret_cast<int(*)[LOC_BLOCK]>(work);
+                int(*rlo)[LOC_BLOCK] = reinterpret_cast<int(*)[LOC_BLOCK]>(work + SCAP * LOC_BLOCK);
+                int(*rhi)[LOC_BLOCK] =
+                    reinterpret_cast<int(*)[LOC_BLOCK]>(work + (SCAP + MAXROWS) * LOC_BLOCK);
+                LdsStack<LOC_BLOCK> st{stk, 0};
+                LocalScan<LOC_BLOCK> sc{G, LdsRows<LOC_BLOCK>{rlo, rhi, 0}, false};
+                LocalSink sink{olines + (size_t)g * KOUT, sid, lpos, k};
+                const int r = run_cell<0, Solo>(CL, lxy, sc, st, SCAP, sink, KOUT, K);
+                if (r >= 0) {
+                    ovf[g] = -1;
+                    ocnt[g] = r;
+                    dcnt[g] = sink.up;
+                    edges += (uint32_t)r;
+                } else if (r == -4 || r == -1) {
+                    queue4[atomicAdd(qcount4, 1)] = pos;
+                } else {
+                    queue[atomicAdd(qcount, 1)] = pos;
+                    ++deferred;
+                }
+            }
+            __syncthreads();   // the next group reuses the LDS
+        }
+    }
+    __syncthreads();
+    reduce_stats(K, edges, deferred, handled, sh, stats, true);
+}
 
-// Below this many handed-over cells the adaptive pass is one full run over queue3 (the
-// list-only run returns at once): two short runs would each cost the latency of their slowest
-// lane (a polygon with 6.5k handed-over cells: 4.2 ms in two runs, 1.7 ms in one), while a large
-// hand-over gains from the list-only run.
-constexpr int TREE_SPLIT_MIN = 65536;
-
-template <int BLOCK, bool LONLY>
-__global__ __launch_bounds__(BLOCK, LONLY ? 4 : 3) void k_cells_tree(
+// Adaptive pass, second part: the cells the local grids handed on (queue4), one thread per
+// cell over a persistent grid, scanning the refined buckets (TreeScan) with a per-cell candidate
+// list and exact decisions in the lane.  Cells over the work budget or the stack / line capacity
+// go to the exact pass.
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK, 3) void k_cells_tree(
     const SetDesc *__restrict__ sets, int nsets, const int *__restrict__ set_off,
     const SideRel *__restrict__ sides,
     const float2 *__restrict__ sxy, const int *__restrict__ sid, const int *__restrict__ tstart,
     const int *__restrict__ tchild, const TNode *__restrict__ nodes, const int *__restrict__ tref,
     int *__restrict__ ocnt,
     int *__restrict__ olines, int *__restrict__ ovf, int *__restrict__ dcnt,
-    const int *__restrict__ queue3, const int *__restrict__ qcount3,
-    int *__restrict__ queue, int *__restrict__ qcount, int *__restrict__ queue4,
-    int *__restrict__ qcount4, int *__restrict__ tlist,
+    int *__restrict__ queue, int *__restrict__ qcount, const int *__restrict__ queue4,
+    const int *__restrict__ qcount4, int *__restrict__ tlist,
     unsigned long long *__restrict__ stats, const unsigned char *__restrict__ bflag,
     const int *__restrict__ status) {
     __shared__ int stk[SCAP][BLOCK];
     __shared__ int fr[TFRAMES][3][BLOCK];
     __shared__ unsigned long long sh[SL_COUNT];
     if (*status) return;
-    // few handed-over cells: one full run over them (two runs would add their latencies)
-    const int n3 = *qcount3;
-    const bool direct = n3 < TREE_SPLIT_MIN;
-    if (LONLY && direct) return;
-    const int nq = (LONLY || direct) ? n3 : *qcount4;
-    const int *const qin = (LONLY || direct) ? queue3 : queue4;
+    const int nq = *qcount4;
+    const int *const qin = queue4;
     if ((int)(blockIdx.x * BLOCK) >= nq) return;
     if (threadIdx.x < SL_COUNT) sh[threadIdx.x] = 0;
     __syncthreads();
     Counters K{};
-    uint32_t edges = 0, deferred = 0, handled = 0;
+    uint32_t edges = 0, deferred = 0;
     for (int qi = blockIdx.x * BLOCK + threadIdx.x; qi < nq; qi += gridDim.x * BLOCK) {
         const int pos = qin[qi];
         if (bflag[pos]) continue;   // the boundary pass takes it
@@ -482,27 +693,24 @@ __global__ __launch_bounds__(BLOCK, LONLY ? 4 : 3) void k_cells_tree(
         const int k = sid[pos];
         const int g = S.site_off + k;
         LdsStack<BLOCK> st{stk, 0};
-        TreeScan<Solo, LdsFrames<BLOCK>, GlobalList<TREE_LIST>, LONLY> sc{
+        TreeScan<Solo, LdsFrames<BLOCK>, GlobalList<TREE_LIST>> sc{
             Tree{tstart, tchild, nodes, tref}, LdsFrames<BLOCK>{fr},
             GlobalList<TREE_LIST>{tlist + blockIdx.x * BLOCK + threadIdx.x,
                                   (int)(gridDim.x * BLOCK)},
             Rect{}, false, Rect{}, 0, false};
         Sink sink{olines + (size_t)g * KOUT, sid, k};
-        const int r = run_cell<LONLY ? 0 : 1, Solo>(C, sxy, sc, st, SCAP, sink, KOUT, K);
-        handled += LONLY || direct;   // counted once
+        const int r = run_cell<1, Solo>(C, sxy, sc, st, SCAP, sink, KOUT, K);
         if (r >= 0) {
             ovf[g] = -1;
             ocnt[g] = r;
             dcnt[g] = sink.up;
             edges += (uint32_t)r;
-        } else if (LONLY && (r == -4 || r == -1)) {
-            queue4[atomicAdd(qcount4, 1)] = pos;
         } else {
             queue[atomicAdd(qcount, 1)] = pos;
             ++deferred;
         }
     }
-    reduce_stats(K, edges, deferred, handled, sh, stats);
+    reduce_stats(K, edges, deferred, 0, sh, stats, true);
 }
 
 // Every cell into a queue, in bucket order.
@@ -1307,12 +1515,12 @@ static void launch_fast(const PipeArgs &a, hipStream_t st) {
         k_cells_fast<BLOCK, true><<<nb, BLOCK, 0, st>>>(
             a.sets, a.nsets, a.set_off, a.sides, a.sxy, a.sid, a.bstart, a.total, a.ocnt,
             a.olines, a.ovf, a.dcnt, a.queue, a.qcount(), a.queue3, a.qcount3(), a.stats,
-            a.bflag, a.status());
+            a.bflag, a.hand, a.status());
     else
         k_cells_fast<BLOCK, false><<<nb, BLOCK, 0, st>>>(
             a.sets, a.nsets, a.set_off, a.sides, a.sxy, a.sid, a.bstart, a.total, a.ocnt,
             a.olines, a.ovf, a.dcnt, a.queue, a.qcount(), a.queue3, a.qcount3(), a.stats,
-            a.bflag, a.status());
+            a.bflag, a.hand, a.status());
 }
 
 template <int MODE>
@@ -1375,16 +1583,20 @@ void launch_stage(const PipeArgs &a, hipStream_t st, int stage) {
     } else if (stage == 2) {
         // adaptive pass over the cells that met crowded buckets
         if (!(a.exact_only || a.coop_all)) {
+            // local grids over chunks of consecutive cells (every cell with tree_all, else the
+            // handed-over ones), then the tree scans for what they hand on
+            const long long nch = ((long long)T + LOC_BLOCK - 1) / LOC_BLOCK;
+            const unsigned lb = (unsigned)std::max(1LL, std::min(nch, (long long)LOC_GRID_MAX));
+            k_cells_local<<<lb, LOC_BLOCK, 0, st>>>(
+                a.sets, a.nsets, a.set_off, a.sides, a.sxy, a.sid, a.bstart, a.tchild, a.nodes,
+                a.tref, T, a.hand, a.tree_all ? 1 : 0, a.qcount3(), a.ocnt, a.olines, a.ovf,
+                a.dcnt, a.queue, a.qcount(), a.queue4, a.qcount4(), a.stats, a.bflag, a.status());
             // the list buffer holds TREE_LIST entries for each thread of this grid
             const unsigned nb = (unsigned)tree_pass_blocks(T);
-            k_cells_tree<TREE_PASS_BLOCK, true><<<nb, TREE_PASS_BLOCK, 0, st>>>(
+            k_cells_tree<TREE_PASS_BLOCK><<<nb, TREE_PASS_BLOCK, 0, st>>>(
                 a.sets, a.nsets, a.set_off, a.sides, a.sxy, a.sid, a.bstart, a.tchild, a.nodes, a.tref,
-                a.ocnt, a.olines, a.ovf, a.dcnt, a.queue3, a.qcount3(), a.queue, a.qcount(),
-                a.queue4, a.qcount4(), a.tlist, a.stats, a.bflag, a.status());
-            k_cells_tree<TREE_PASS_BLOCK, false><<<nb, TREE_PASS_BLOCK, 0, st>>>(
-                a.sets, a.nsets, a.set_off, a.sides, a.sxy, a.sid, a.bstart, a.tchild, a.nodes, a.tref,
-                a.ocnt, a.olines, a.ovf, a.dcnt, a.queue3, a.qcount3(), a.queue, a.qcount(),
-                a.queue4, a.qcount4(), a.tlist, a.stats, a.bflag, a.status());
+                a.ocnt, a.olines, a.ovf, a.dcnt, a.queue, a.qcount(), a.queue4, a.qcount4(),
+                a.tlist, a.stats, a.bflag, a.status());
         }
     } else if (stage == 3) {
         if (a.exact_only) launch_exact<2>(a, st);

@@ -137,6 +137,7 @@ size_t footprint_bytes(uint64_t total, uint64_t gtot, bool vertices, uint64_t si
     b += (3 * total + 1024) * 8;                                    // sub-bucket tables
     b += 4ull * TREE_LIST * TREE_PASS_BLOCK * tree_pass_blocks((long long)total);   // lists
     b += (TREE_LEVELS * (total / (TREE_C1 + 1)) + 64) * (sizeof(TNode) + 4 * (TREE_LEVELS - 1));
+    b += 2 * (total + 4);                                           // boundary, hand-over flags
     return b;
 }
 
@@ -193,6 +194,7 @@ int run_sizes(long long T, long long gtot, long long sides, int K, size_t nsides
     b[B_TXY] = 8ull * T;
     b[B_TID] = b[B_QUEUE3] = b[B_QUEUE4] = b[B_QUEUE5] = 4ull * T;
     b[B_BFLAG] = 4ull * ((T + 3) / 4);   // cleared as 32-bit words
+    b[B_HAND] = 4ull * ((T + 3) / 4);
     b[B_TREF] = 4ull * (gtot + 1);
     b[B_NLIST] = 4ull * (TREE_LEVELS - 1) * ncap;
     b[B_SXY] = 8ull * T;
@@ -242,6 +244,7 @@ void fill_args(PipeArgs &a, void *const p[B_COUNT], const RunSizes &z, bool any_
     a.nlist = (int *)p[B_NLIST];
     a.bflag = (unsigned char *)p[B_BFLAG];
     a.queue5 = (int *)p[B_QUEUE5];
+    a.hand = (unsigned char *)p[B_HAND];
     a.sxy = (float2 *)p[B_SXY];
     a.sid = (int *)p[B_SID];
     a.ocnt = (int *)p[B_OCNT];

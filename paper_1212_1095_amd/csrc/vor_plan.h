@@ -14,7 +14,7 @@ enum BufId {
     B_SETS, B_SETOFF, B_INX, B_INY, B_XYID, B_KEY, B_BCNT, B_BSTART, B_SXY, B_SID, B_OCNT,
     B_OLINES, B_OVF, B_POOL, B_QUEUE, B_QUEUE2, B_WBUF, B_WBUF2, B_CELLOFF, B_NBR, B_VTX,
     B_DCNT, B_DELOFF, B_DEL, B_SCANTMP, B_SMALL, B_STATS, B_TCHILD, B_NODES, B_TXY,
-    B_TID, B_QUEUE3, B_TREF, B_NLIST, B_SIDES, B_TLIST, B_QUEUE4, B_BFLAG, B_QUEUE5, B_COUNT
+    B_TID, B_QUEUE3, B_TREF, B_NLIST, B_SIDES, B_TLIST, B_QUEUE4, B_BFLAG, B_QUEUE5, B_HAND, B_COUNT
 };
 
 struct HostSet {   // validated description of one input set
