@@ -937,19 +937,21 @@ struct GStack {
     __device__ __forceinline__ int pop() { return s[--depth]; }
 };
 
-// Output sink: stores the line's label (local site index or side code).
-// Output of a cell walk: the lines as site ids (side codes unchanged), plus the count of
-// neighbours with a larger id than the cell's own (k), i.e. the cell's Delaunay edges (i, j),
-// i < j (Section 7).
+// Output of a cell walk: the lines as sorted positions (side codes unchanged), entry m at
+// dst[m * stride] (the filtered passes store entry-major by the cell's own sorted position, so
+// that the rows a wavefront writes are complete in L2 before they are written back), plus the
+// count of neighbours with a larger id than the cell's own (k), i.e. the cell's Delaunay edges
+// (i, j), i < j (Section 7).
 struct Sink {
     int *dst;
+    long long stride;
     const int *sid;
     int k;
     int up = 0;
     int lastup = 0;
     __device__ __forceinline__ void put(int m, int id) {
+        dst[m * stride] = id;
         const int v = id >= 0 ? sid[id] : id;
-        dst[m] = v;
         lastup = v > k;
         up += lastup;
     }

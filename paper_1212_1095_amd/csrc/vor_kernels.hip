@@ -415,9 +415,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5, 8))) v
         const int g = S.site_off + k;
         LdsStack<BLOCK> st{stk, 0};
         GridScan<Solo, LdsRows<BLOCK>, true> sc{LdsRows<BLOCK>{rlo, rhi, 0}, bstart, false};
-        Sink sink{olines + (size_t)g * KOUT, sid, k};
+        Sink sink{olines + pos, total, sid, k};
         const int r = run_cell<0, Solo>(C, sxy, sc, st, SCAP, sink, KOUT, K);
-        ovf[g] = -1;
+        ovf[pos] = -1;
         if (r >= 0) {
             ocnt[g] = r;
             dcnt[g] = sink.up;
@@ -607,7 +607,7 @@ __global__ __launch_bounds__(LOC_BLOCK) void k_cells_local(
                     sum += v[k];
                 }
                 int tot;
-                int before = block_exscan(sum, s_wsum, tot);
+                int before = block_exscan<LOC_BLOCK>(sum, s_wsum, tot);
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
                     const int b2 = 4 * tid + k;
@@ -637,10 +637,10 @@ __global__ __launch_bounds__(LOC_BLOCK) void k_cells_local(
                     reinterpret_cast<int(*)[LOC_BLOCK]>(work + (SCAP + MAXROWS) * LOC_BLOCK);
                 LdsStack<LOC_BLOCK> st{stk, 0};
                 LocalScan<LOC_BLOCK> sc{G, LdsRows<LOC_BLOCK>{rlo, rhi, 0}, false};
-                LocalSink sink{olines + (size_t)g * KOUT, sid, lpos, k};
+                LocalSink sink{olines + pos, total, sid, lpos, k};
                 const int r = run_cell<0, Solo>(CL, lxy, sc, st, SCAP, sink, KOUT, K);
                 if (r >= 0) {
-                    ovf[g] = -1;
+                    ovf[pos] = -1;
                     ocnt[g] = r;
                     dcnt[g] = sink.up;
                     edges += (uint32_t)r;
@@ -668,7 +668,7 @@ __global__ __launch_bounds__(BLOCK, 3) void k_cells_tree(
     const SideRel *__restrict__ sides,
     const float2 *__restrict__ sxy, const int *__restrict__ sid, const int *__restrict__ tstart,
     const int *__restrict__ tchild, const TNode *__restrict__ nodes, const int *__restrict__ tref,
-    int *__restrict__ ocnt,
+    int total, int *__restrict__ ocnt,
     int *__restrict__ olines, int *__restrict__ ovf, int *__restrict__ dcnt,
     int *__restrict__ queue, int *__restrict__ qcount, const int *__restrict__ queue4,
     const int *__restrict__ qcount4, int *__restrict__ tlist,
@@ -698,10 +698,10 @@ __global__ __launch_bounds__(BLOCK, 3) void k_cells_tree(
             GlobalList<TREE_LIST>{tlist + blockIdx.x * BLOCK + threadIdx.x,
                                   (int)(gridDim.x * BLOCK)},
             Rect{}, false, Rect{}, 0, false};
-        Sink sink{olines + (size_t)g * KOUT, sid, k};
+        Sink sink{olines + pos, total, sid, k};
         const int r = run_cell<1, Solo>(C, sxy, sc, st, SCAP, sink, KOUT, K);
         if (r >= 0) {
-            ovf[g] = -1;
+            ovf[pos] = -1;
             ocnt[g] = r;
             dcnt[g] = sink.up;
             edges += (uint32_t)r;
@@ -729,7 +729,7 @@ __device__ __forceinline__ int coop_cell(const Cell &C, const float2 *__restrict
                                          const int *__restrict__ sid, int k, Sc &sc, int *area,
                                          int dcap, Counters &K, int &up) {
     GStack st{area, 0};
-    Sink sink{area + dcap, sid, k};
+    Sink sink{area + dcap, 1, sid, k};
     const int r = run_cell<MODE, Coop>(C, sxy, sc, st, dcap, sink, dcap, K);
     up = sink.up;
     return r;
@@ -745,7 +745,7 @@ __global__ __launch_bounds__(64) void k_cells_exact(
     const SetDesc *__restrict__ sets, int nsets, const int *__restrict__ set_off,
     const SideRel *__restrict__ sides,
     const float2 *__restrict__ sxy, const int *__restrict__ sid, const int *__restrict__ bstart,
-    int *__restrict__ ocnt, int *__restrict__ olines, int *__restrict__ dcnt,
+    int total, int *__restrict__ ocnt, int *__restrict__ olines, int *__restrict__ dcnt,
     int *__restrict__ ovf, int *__restrict__ pool, int *__restrict__ poolcnt, long long poolcap,
     const int *__restrict__ queue, const int *__restrict__ qcount, int *__restrict__ queue2,
     int *__restrict__ qcount2, int *__restrict__ wbuf, int dcap,
@@ -795,10 +795,11 @@ __global__ __launch_bounds__(64) void k_cells_exact(
                 continue;
             }
         }
-        int *dst = off >= 0 ? pool + off : olines + (size_t)g * KOUT;
-        for (int t = lane; t < r; t += 64) dst[t] = src[t];
+        int *dst = off >= 0 ? pool + off : olines + pos;
+        const long long stride = off >= 0 ? 1 : total;
+        for (int t = lane; t < r; t += 64) dst[t * stride] = src[t];
         if (lane == 0) {
-            ovf[g] = off;
+            ovf[pos] = off;
             ocnt[g] = r;
             dcnt[g] = up;
         }
@@ -827,7 +828,7 @@ __global__ __launch_bounds__(64 * WIDE_WAVES) void k_cells_wide(
     const SetDesc *__restrict__ sets, int nsets, const int *__restrict__ set_off,
     const SideRel *__restrict__ sides,
     const float2 *__restrict__ sxy, const int *__restrict__ sid, const int *__restrict__ bstart,
-    int *__restrict__ ocnt, int *__restrict__ olines, int *__restrict__ dcnt,
+    int total, int *__restrict__ ocnt, int *__restrict__ olines, int *__restrict__ dcnt,
     int *__restrict__ ovf, int *__restrict__ pool, int *__restrict__ poolcnt, long long poolcap,
     const int *__restrict__ queue, const int *__restrict__ qcount, int *__restrict__ wbuf,
     unsigned long long *__restrict__ stats, int *__restrict__ status) {
@@ -921,20 +922,19 @@ __global__ __launch_bounds__(64 * WIDE_WAVES) void k_cells_wide(
         // the cyclic list of distinct lines, counter-clockwise from corner 0 (into F[0])
         if (threadIdx.x == 0) {
             int m = 0, up = 0, last = INT32_MIN, c = 0;
-            const int first = cline[0] >= 0 ? sid[cline[0]] : cline[0];
+            const int first = cline[0];
             do {
-                const int id = cline[c];
-                const int v = id >= 0 ? sid[id] : id;
-                if (v != last) {
-                    F[0][m++] = v;
-                    up += v > k;
-                    last = v;
+                const int id = cline[c];   // sorted position or side code
+                if (id != last) {
+                    F[0][m++] = id;
+                    up += (id >= 0 ? sid[id] : id) > k;
+                    last = id;
                 }
                 c = nxt[c];
             } while (c != 0);
             if (m > 1 && last == first) {
                 --m;
-                up -= last > k;
+                up -= (last >= 0 ? sid[last] : last) > k;
             }
             int off = -1;
             if (m > KOUT) {
@@ -952,10 +952,11 @@ __global__ __launch_bounds__(64 * WIDE_WAVES) void k_cells_wide(
         __syncthreads();
         const int m = s_m, off = s_off;
         if (m < 0) continue;
-        int *dst = off >= 0 ? pool + off : olines + (size_t)g * KOUT;
-        for (int t = threadIdx.x; t < m; t += blockDim.x) dst[t] = F[0][t];
+        int *dst = off >= 0 ? pool + off : olines + pos;
+        const long long stride = off >= 0 ? 1 : total;
+        for (int t = threadIdx.x; t < m; t += blockDim.x) dst[t * stride] = F[0][t];
         if (threadIdx.x == 0) {
-            ovf[g] = off;
+            ovf[pos] = off;
             ocnt[g] = m;
             dcnt[g] = s_up;
             edges += (uint32_t)m;
@@ -1052,7 +1053,7 @@ __global__ __launch_bounds__(64) void k_cells_bnd(
     const SetDesc *__restrict__ sets, int nsets, const int *__restrict__ set_off,
     const SideRel *__restrict__ sides,
     const float2 *__restrict__ sxy, const int *__restrict__ sid, const int *__restrict__ bstart,
-    int *__restrict__ ocnt, int *__restrict__ olines, int *__restrict__ dcnt,
+    int total, int *__restrict__ ocnt, int *__restrict__ olines, int *__restrict__ dcnt,
     int *__restrict__ ovf, int *__restrict__ pool, int *__restrict__ poolcnt, long long poolcap,
     const int *__restrict__ queue, const int *__restrict__ qcount,
     unsigned long long *__restrict__ stats, int *__restrict__ status) {
@@ -1102,18 +1103,18 @@ __global__ __launch_bounds__(64) void k_cells_bnd(
                 cur = nxt;
                 nxt = t;
             }
-            // names -> output: site ids, sides of X; no grown-box side may remain
+            // names -> output: sorted positions, sides of X; no grown-box side may remain
             for (int t = 0; t < m; ++t) {
                 const int id = cur[t];
                 int v;
-                if (id >= 0) v = sid[id];
+                if (id >= 0) v = id;
                 else if (id < -BND_XCODE) v = id + BND_XCODE;
                 else {
                     m = -1;
                     break;
                 }
                 la[t] = v;
-                up += v > k;
+                up += (v >= 0 ? sid[v] : v) > k;
             }
             if (m > KOUT) {
                 off = atomicAdd(poolcnt, m);
@@ -1124,10 +1125,11 @@ __global__ __launch_bounds__(64) void k_cells_bnd(
         m = __shfl(m, 0, 64);
         off = __shfl(off, 0, 64);
         if (m < 0) continue;
-        int *dst = off >= 0 ? pool + off : olines + (size_t)g * KOUT;
-        for (int t = lane; t < m; t += 64) dst[t] = la[t];
+        int *dst = off >= 0 ? pool + off : olines + pos;
+        const long long stride = off >= 0 ? 1 : total;
+        for (int t = lane; t < m; t += 64) dst[t * stride] = la[t];
         if (lane == 0) {
-            ovf[g] = off;
+            ovf[pos] = off;
             ocnt[g] = m;
             dcnt[g] = up;
             edges += (uint32_t)m;
@@ -1281,74 +1283,93 @@ __device__ __forceinline__ Rat pair_vertex(const SetDesc &S, const SideRel *__re
     return v;
 }
 
-constexpr int EMIT_BLOCK = 256;   // cells per block (consecutive ids)
+constexpr int EMIT_BLOCK = 256;   // cells per block (consecutive sorted positions)
 constexpr int EMIT_ECAP = 2048;   // CSR entries staged per block (mean about 6 per cell)
-constexpr int EMIT_PER = EMIT_ECAP / EMIT_BLOCK;   // staged entries per thread, at most
-static_assert(EMIT_ECAP % EMIT_BLOCK == 0, "whole rounds of staged entries per thread");
+static_assert(EMIT_BLOCK <= 256, "a byte names a block's cell");
+
+// Line t of the cell at sorted position pos: sorted position of the neighbour's site, or side code
+// (the cell passes store entry-major by position; cells with more than KOUT lines in the pool).
+__device__ __forceinline__ int cell_line(const int *__restrict__ olines,
+                                         const int *__restrict__ pool, long long total, int pos,
+                                         int of, int t) {
+    return of >= 0 ? pool[of + t] : olines[(long long)t * total + pos];
+}
 
 // Cell by cell (blocks whose entries exceed the LDS capacity: cells with very many edges).
 // Returns false, writing nothing, when the neighbours > k are not the dn the cell pass counted.
 template <bool VERT>
-__device__ bool emit_cell(const SetDesc &S, const SideRel *__restrict__ sides, int so, int k,
-                          int2 p, const int *__restrict__ src,
-                          int m, int dn, long long base, long long dbase,
-                          const int2 *__restrict__ xyid, int *__restrict__ nbr,
+__device__ bool emit_cell(const SetDesc &S, const SideRel *__restrict__ sides, int k, int2 p,
+                          const int *__restrict__ olines, const int *__restrict__ pool,
+                          long long total, int pos, int of, int m, int dn, long long base,
+                          long long dbase, const int *__restrict__ sid,
+                          const float2 *__restrict__ sxy, int *__restrict__ nbr,
                           Rat *__restrict__ vtx, unsigned *__restrict__ del) {
-    int r = 0, up = 0;
+    auto id = [&](int t) {
+        const int q = cell_line(olines, pool, total, pos, of, t);
+        return q >= 0 ? sid[q] : q;
+    };
+    auto xy = [&](int t) {
+        const int q = cell_line(olines, pool, total, pos, of, t);
+        return q >= 0 ? make_int2((int)sxy[q].x, (int)sxy[q].y) : make_int2(0, 0);
+    };
+    int r = 0, up = 0, rid = id(0);
     for (int t = 0; t < m; ++t) {
-        r = (uint32_t)src[t] < (uint32_t)src[r] ? t : r;
-        up += src[t] > k;
+        const int j = id(t);
+        if ((uint32_t)j < (uint32_t)rid) {
+            r = t;
+            rid = j;
+        }
+        up += j > k;
     }
     if (up != dn) return false;
-    for (int t = 0; t < m; ++t) nbr[base + t] = src[(r + t) % m];
+    for (int t = 0; t < m; ++t) nbr[base + t] = id((r + t) % m);
     if (VERT)
         for (int t = 0; t < m; ++t) {
-            const int a = src[(r + t) % m], b = src[(r + t + 1) % m];
-            const int2 qa = a >= 0 ? xyid[so + a] : make_int2(0, 0);
-            const int2 qb = b >= 0 ? xyid[so + b] : make_int2(0, 0);
-            vtx[base + t] = pair_vertex(S, sides, p, a, qa, b, qb);
+            const int ta = (r + t) % m, tb = (r + t + 1) % m;
+            vtx[base + t] = pair_vertex(S, sides, p, id(ta), xy(ta), id(tb), xy(tb));
         }
     for (int t = 0; t < m; ++t) {   // Delaunay pairs: rank of each neighbour > k
-        const int j = src[t];
+        const int j = id(t);
         if (j <= k) continue;
         int rank = 0;
-        for (int u = 0; u < m; ++u) rank += src[u] > k && src[u] < j;
+        for (int u = 0; u < m; ++u) {
+            const int v = id(u);
+            rank += v > k && v < j;
+        }
         del[2 * (dbase + rank)] = (unsigned)k;
         del[2 * (dbase + rank) + 1] = (unsigned)j;
     }
     return true;
 }
 
-// Output of 256 consecutive cells: the canonical rotation of each cell's lines (the entry
-// smallest as uint32 first), the neighbour ids, the pair-form vertices (Section 6) and the
-// Delaunay pairs (k, j), k < j, ascending (Section 7).  The block's lines are read entry by
-// entry (consecutive threads, consecutive entries) into LDS; the rotation and the Delaunay
-// order are found there; each entry then writes its CSR slot, its vertex and its Delaunay pair.
-// A block whose entries exceed the LDS capacity works cell by cell instead.
+// Output of 256 consecutive cells in sorted order: the canonical rotation of each cell's lines
+// (the entry smallest as uint32 first), the neighbour ids, the pair-form vertices (Section 6)
+// and the Delaunay pairs (k, j), k < j, ascending (Section 7).  Taking the cells in sorted order
+// keeps the neighbours' sites of a block within a few rows of buckets, so their ids and
+// coordinates come from cache; the block's lines are read entry by entry into LDS, the rotation
+// and the Delaunay order are found there, and each entry then writes its CSR slot (at the cell's
+// offset by id), its vertex and its Delaunay pair.  A block whose entries exceed the LDS
+// capacity works cell by cell instead.
 template <bool VERT>
 __global__ __launch_bounds__(EMIT_BLOCK) void k_emit(
     const SetDesc *__restrict__ sets, int nsets, const int *__restrict__ set_off,
-    const SideRel *__restrict__ sides, int total,
-    const int *__restrict__ ocnt, const int *__restrict__ olines, const int *__restrict__ ovf,
-    const int *__restrict__ pool, const int *__restrict__ dcnt, const int *__restrict__ cell_off,
-    long long cap, const int *__restrict__ del_off, long long del_cap,
-    const int2 *__restrict__ xyid, int *__restrict__ nbr, Rat *__restrict__ vtx,
-    unsigned *__restrict__ del, int *__restrict__ status) {
+    const SideRel *__restrict__ sides, int total, const int *__restrict__ sid,
+    const float2 *__restrict__ sxy, const int *__restrict__ olines, const int *__restrict__ ovf,
+    const int *__restrict__ pool, const int *__restrict__ cell_off, long long cap,
+    const int *__restrict__ del_off, long long del_cap, int *__restrict__ nbr,
+    Rat *__restrict__ vtx, unsigned *__restrict__ del, int *__restrict__ status) {
     __shared__ int lin[EMIT_ECAP];
     __shared__ unsigned char own[EMIT_ECAP];
     __shared__ int2 qc[VERT ? EMIT_ECAP : 1];
     __shared__ int clo[EMIT_BLOCK + 1];
-    __shared__ const int *crow[EMIT_BLOCK];
-    __shared__ int cdl[EMIT_BLOCK];
-    __shared__ int crot[EMIT_BLOCK];
-    __shared__ int cset[EMIT_BLOCK];
-    __shared__ int cso[EMIT_BLOCK];
+    __shared__ long long cbase[EMIT_BLOCK], cdel[EMIT_BLOCK];
+    __shared__ int ck[EMIT_BLOCK], cof[EMIT_BLOCK], crot[EMIT_BLOCK], cset[EMIT_BLOCK];
     __shared__ int2 pc[EMIT_BLOCK];
-    __shared__ int bad, stop;
+    __shared__ int bad, stop, s_wsum[EMIT_BLOCK / 64];
     const int tid = threadIdx.x;
-    const int g0 = blockIdx.x * EMIT_BLOCK;
-    const int nc = min(EMIT_BLOCK, total - g0);
-    const int g = g0 + tid;
+    const int pos0 = blockIdx.x * EMIT_BLOCK;
+    const int nc = min(EMIT_BLOCK, total - pos0);
+    const int pos = pos0 + tid;
     if (tid == 0) {
         stop = *status;   // one read, so that every wave of the block takes the same branch
         bad = 0;
@@ -1361,83 +1382,65 @@ __global__ __launch_bounds__(EMIT_BLOCK) void k_emit(
     }
     __syncthreads();
     if (stop) return;
-    const long long E0 = cell_off[g0], E1 = cell_off[g0 + nc];
-    const long long D0 = del_off[g0], D1 = del_off[g0 + nc];
-    const bool staged = E1 - E0 >= 0 && E1 - E0 <= EMIT_ECAP && D1 >= D0;
-    const int ne = staged ? (int)(E1 - E0) : 0;
-    if (tid == 0) clo[nc] = ne;   // read after the next barrier
-    // per cell: offsets, checks, where its lines are
-    int s = 0, k = 0, m = 0, dn = 0;
+    // per cell: its id, offsets and line source
+    int s = 0, k = 0, m = 0, dn = 0, of = -1;
     long long base = 0, dbase = 0;
-    const int *src = nullptr;
     int2 p = make_int2(0, 0);
     if (tid < nc) {
-        s = find_set(set_off, nsets, g);
-        k = g - set_off[s];
-        m = ocnt[g];
+        s = find_set(set_off, nsets, pos);
+        k = sid[pos];
+        const int g = set_off[s] + k;
         base = cell_off[g];
-        dn = dcnt[g];
+        m = cell_off[g + 1] - (int)base;
         dbase = del_off[g];
-        const int of = ovf[g];
-        if (m < 3 || base + m > cap || cell_off[g + 1] != base + m || dn < 0 ||
-            dbase + dn > del_cap || del_off[g + 1] != dbase + dn || (of < 0 && m > KOUT) ||
-            (staged && (base < E0 || base + m > E1))) {
+        dn = del_off[g + 1] - (int)dbase;
+        of = ovf[pos];
+        const float2 a = sxy[pos];
+        p = make_int2((int)a.x, (int)a.y);
+        if (m < 3 || base + m > cap || dn < 0 || dbase + dn > del_cap || (of < 0 && m > KOUT)) {
             bad = 1;
             m = 0;
-        } else {
-            src = of >= 0 ? pool + of : olines + (size_t)g * KOUT;
-            p = xyid[g];
-            if (staged) {
-                const int lo = (int)(base - E0);
-                clo[tid] = lo;
-                crow[tid] = src;
-                cdl[tid] = (int)(dbase - D0);
-                cset[tid] = s;
-                cso[tid] = set_off[s];
-                pc[tid] = p;
-                for (int t = 0; t < m; ++t) own[lo + t] = (unsigned char)tid;
-            }
         }
     }
-    __syncthreads();
+    int ne;
+    const int lo = block_exscan<EMIT_BLOCK>(m, s_wsum, ne);
+    const bool staged = ne <= EMIT_ECAP;   // uniform
     if (bad) {
         if (tid == 0) atomicOr(status, ST_INTERNAL);
         return;
     }
     if (!staged) {
         if (tid < nc &&
-            !emit_cell<VERT>(sets[s], sides, set_off[s], k, p, src, m, dn, base, dbase, xyid, nbr,
-                             vtx, del))
+            !emit_cell<VERT>(sets[s], sides, k, p, olines, pool, total, pos, of, m, dn, base,
+                             dbase, sid, sxy, nbr, vtx, del))
             atomicOr(status, ST_INTERNAL);
         return;
     }
-    // per entry: the line, and the coordinates of its site.  All of a thread's line reads are
-    // issued before any is used, then all of its coordinate gathers: two round trips to memory
-    // instead of two per entry.
-    {
-        int jj[EMIT_PER];
-#pragma unroll
-        for (int i = 0; i < EMIT_PER; ++i) {
-            const int e = tid + i * EMIT_BLOCK;
-            jj[i] = 0;
-            if (e < ne) {
-                const int o = own[e];
-                jj[i] = crow[o][e - clo[o]];
-            }
-        }
-#pragma unroll
-        for (int i = 0; i < EMIT_PER; ++i) {
-            const int e = tid + i * EMIT_BLOCK;
-            if (e < ne) {
-                lin[e] = jj[i];
-                if (VERT) qc[e] = jj[i] >= 0 ? xyid[cso[own[e]] + jj[i]] : make_int2(0, 0);
-            }
+    if (tid < nc) {
+        clo[tid] = lo;
+        cbase[tid] = base;
+        cdel[tid] = dbase;
+        ck[tid] = k;
+        cof[tid] = of;
+        cset[tid] = s;
+        pc[tid] = p;
+        for (int t = 0; t < m; ++t) own[lo + t] = (unsigned char)tid;
+    }
+    if (tid == 0) clo[nc] = ne;
+    __syncthreads();
+    // per entry: the line's site id and coordinates
+    for (int e = tid; e < ne; e += EMIT_BLOCK) {
+        const int o = own[e];
+        const int q = cell_line(olines, pool, total, pos0 + o, cof[o], e - clo[o]);
+        lin[e] = q >= 0 ? sid[q] : q;
+        if (VERT) {
+            const float2 a = q >= 0 ? sxy[q] : make_float2(0.0f, 0.0f);
+            qc[e] = make_int2((int)a.x, (int)a.y);
         }
     }
     __syncthreads();
     // per cell: rotation, and the count of neighbours > k against the cell pass's count
     if (tid < nc) {
-        const int lo = clo[tid];
         int r = 0, up = 0;
         for (int t = 0; t < m; ++t) {
             const int a = lin[lo + t];
@@ -1457,20 +1460,21 @@ __global__ __launch_bounds__(EMIT_BLOCK) void k_emit(
     uint2 *__restrict__ del2 = reinterpret_cast<uint2 *>(del);
     for (int e = tid; e < ne; e += EMIT_BLOCK) {
         const int o = own[e];
-        const int lo = clo[o], mo = clo[o + 1] - lo, u = e - lo;
+        const int lo2 = clo[o], mo = clo[o + 1] - lo2, u = e - lo2;
         int t = u - crot[o];
         t += t < 0 ? mo : 0;
         const int j = lin[e];
-        nbr[E0 + lo + t] = j;
+        const long long b0 = cbase[o];
+        nbr[b0 + t] = j;
         if (VERT) {
-            const int e2 = u + 1 == mo ? lo : e + 1;
-            vtx[E0 + lo + t] = pair_vertex(sets[cset[o]], sides, pc[o], j, qc[e], lin[e2], qc[e2]);
+            const int e2 = u + 1 == mo ? lo2 : e + 1;
+            vtx[b0 + t] = pair_vertex(sets[cset[o]], sides, pc[o], j, qc[e], lin[e2], qc[e2]);
         }
-        const int ko = g0 + o - set_off[cset[o]];
+        const int ko = ck[o];
         if (j > ko) {
             int rank = 0;
-            for (int v = lo; v < lo + mo; ++v) rank += lin[v] > ko && lin[v] < j;
-            del2[D0 + cdl[o] + rank] = make_uint2((unsigned)ko, (unsigned)j);
+            for (int v = lo2; v < lo2 + mo; ++v) rank += lin[v] > ko && lin[v] < j;
+            del2[cdel[o] + rank] = make_uint2((unsigned)ko, (unsigned)j);
         }
     }
 }
@@ -1527,16 +1531,16 @@ template <int MODE>
 static void launch_exact(const PipeArgs &a, hipStream_t st) {
     // cells of sites on the boundary of X
     k_cells_bnd<MODE><<<BND_BLOCKS, 64, 0, st>>>(
-        a.sets, a.nsets, a.set_off, a.sides, a.sxy, a.sid, a.bstart, a.ocnt, a.olines, a.dcnt,
-        a.ovf, a.pool, a.poolcnt(), a.poolcap, a.queue5, a.qcount5(), a.stats, a.status_rw());
+        a.sets, a.nsets, a.set_off, a.sides, a.sxy, a.sid, a.bstart, a.total, a.ocnt, a.olines,
+        a.dcnt, a.ovf, a.pool, a.poolcnt(), a.poolcap, a.queue5, a.qcount5(), a.stats, a.status_rw());
     k_cells_exact<MODE, DCAP1><<<a.exact_blocks, 64, 0, st>>>(
-        a.sets, a.nsets, a.set_off, a.sides, a.sxy, a.sid, a.bstart, a.ocnt, a.olines, a.dcnt, a.ovf,
-        a.pool, a.poolcnt(), a.poolcap, a.queue, a.qcount(), a.queue2,
+        a.sets, a.nsets, a.set_off, a.sides, a.sxy, a.sid, a.bstart, a.total, a.ocnt, a.olines,
+        a.dcnt, a.ovf, a.pool, a.poolcnt(), a.poolcap, a.queue, a.qcount(), a.queue2,
         a.qcount2(), a.wbuf, DCAP1, a.stats, a.bflag, a.status_rw());
     // deep cells: few workgroups, the subwedges of each cell spread over their waves
     k_cells_wide<MODE><<<DEEP_BLOCKS, 64 * WIDE_WAVES, 0, st>>>(
-        a.sets, a.nsets, a.set_off, a.sides, a.sxy, a.sid, a.bstart, a.ocnt, a.olines, a.dcnt,
-        a.ovf, a.pool, a.poolcnt(), a.poolcap, a.queue2, a.qcount2(), a.wbuf2, a.stats,
+        a.sets, a.nsets, a.set_off, a.sides, a.sxy, a.sid, a.bstart, a.total, a.ocnt, a.olines,
+        a.dcnt, a.ovf, a.pool, a.poolcnt(), a.poolcap, a.queue2, a.qcount2(), a.wbuf2, a.stats,
         a.status_rw());
 }
 
@@ -1595,7 +1599,7 @@ void launch_stage(const PipeArgs &a, hipStream_t st, int stage) {
             const unsigned nb = (unsigned)tree_pass_blocks(T);
             k_cells_tree<TREE_PASS_BLOCK><<<nb, TREE_PASS_BLOCK, 0, st>>>(
                 a.sets, a.nsets, a.set_off, a.sides, a.sxy, a.sid, a.bstart, a.tchild, a.nodes, a.tref,
-                a.ocnt, a.olines, a.ovf, a.dcnt, a.queue, a.qcount(), a.queue4, a.qcount4(),
+                T, a.ocnt, a.olines, a.ovf, a.dcnt, a.queue, a.qcount(), a.queue4, a.qcount4(),
                 a.tlist, a.stats, a.bflag, a.status());
         }
     } else if (stage == 3) {
@@ -1607,14 +1611,13 @@ void launch_stage(const PipeArgs &a, hipStream_t st, int stage) {
         launch_scan(a.dcnt, T, a.del_off, a.scan_tmp, a.status(), 1, st);
         if (a.with_vertices)
             k_emit<true><<<nblk(T, EMIT_BLOCK), EMIT_BLOCK, 0, st>>>(
-                a.sets, a.nsets, a.set_off, a.sides, T, a.ocnt, a.olines, a.ovf, a.pool, a.dcnt,
-                a.cell_off, a.nbr_cap, a.del_off, a.del_cap, a.xyid, a.nbr, (Rat *)a.vtx, a.del,
+                a.sets, a.nsets, a.set_off, a.sides, T, a.sid, a.sxy, a.olines, a.ovf, a.pool,
+                a.cell_off, a.nbr_cap, a.del_off, a.del_cap, a.nbr, (Rat *)a.vtx, a.del,
                 a.status_rw());
         else
             k_emit<false><<<nblk(T, EMIT_BLOCK), EMIT_BLOCK, 0, st>>>(
-                a.sets, a.nsets, a.set_off, a.sides, T, a.ocnt, a.olines, a.ovf, a.pool, a.dcnt,
-                a.cell_off, a.nbr_cap, a.del_off, a.del_cap, a.xyid, a.nbr, nullptr, a.del,
-                a.status_rw());
+                a.sets, a.nsets, a.set_off, a.sides, T, a.sid, a.sxy, a.olines, a.ovf, a.pool,
+                a.cell_off, a.nbr_cap, a.del_off, a.del_cap, a.nbr, nullptr, a.del, a.status_rw());
         if (a.check_symmetry)
             k_symmetry<<<nblk(T, 256), 256, 0, st>>>(a.sets, a.nsets, a.set_off, T, a.cell_off,
                                                       a.nbr, a.stats, a.status());

@@ -22,7 +22,7 @@ constexpr int LOC_BCAP = 1024;      // local buckets at most (= 4 per thread, se
 constexpr int LOC_RCAP = 384;       // leaf ranges of the region at most
 constexpr float LOC_SPB = 1.5f;     // sites per local bucket
 constexpr float LOC_MARGIN = 2.5f;  // region margin in local spacings
-constexpr int LOC_GRID_MAX = 4096;  // workgroups of the pass at most (then each takes several chunks)
+constexpr int LOC_GRID_MAX = 4096;  // workgroups at most (then each takes several chunks)
 constexpr int LOC_NF = LOC_BLOCK;   // refined nodes per level of a region's gather at most
 constexpr int LOC_GBMAX = 4096;     // grid buckets of a region at most
 constexpr int LOC_MINGROUP = 32;    // a region that overflows is split down to this many cells
@@ -133,26 +133,30 @@ struct LocalScan {
                                               const Dir &, float, int, int, XBest &, Counters &) {}
 };
 
-// Output of a walk over local ids: the lines as site ids (through the chunk's sorted positions),
-// and the count of neighbours with a larger id than the cell's own (its Delaunay edges).
+// Output of a walk over local ids: the lines as sorted positions (through the chunk's table),
+// entry m at dst[m * stride] as in Sink, and the count of neighbours with a larger id than the
+// cell's own (its Delaunay edges).
 struct LocalSink {
     int *dst;
+    long long stride;
     const int *sid;
     const int *lpos;   // sorted position of each local site (LDS)
     int k;
     int up = 0;
     int lastup = 0;
     __device__ __forceinline__ void put(int m, int id) {
-        const int v = id >= 0 ? sid[lpos[id]] : id;
-        dst[m] = v;
+        const int q = id >= 0 ? lpos[id] : id;
+        dst[m * stride] = q;
+        const int v = q >= 0 ? sid[q] : q;
         lastup = v > k;
         up += lastup;
     }
     __device__ __forceinline__ void drop_last() { up -= lastup; }
 };
 
-// Exclusive prefix sum of one value per thread over the workgroup (LOC_BLOCK threads); `total`
-// gets the sum.  Every thread calls it (two barriers); wsum: LOC_BLOCK / 64 ints of LDS.
+// Exclusive prefix sum of one value per thread over a workgroup of B threads; `total` gets
+// the sum.  Every thread calls it (two barriers); wsum: B / 64 ints of LDS.
+template <int B>
 __device__ __forceinline__ int block_exscan(int v, int *wsum, int &total) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     int incl = v;
@@ -166,7 +170,7 @@ __device__ __forceinline__ int block_exscan(int v, int *wsum, int &total) {
     int before = incl - v;
     total = 0;
 #pragma unroll
-    for (int w = 0; w < LOC_BLOCK / 64; ++w) {
+    for (int w = 0; w < B / 64; ++w) {
         before += w < wv ? wsum[w] : 0;
         total += wsum[w];
     }
@@ -255,7 +259,7 @@ __device__ __forceinline__ void gather_leaves(const SetDesc &S, const Tree &T, c
         }
         if (tid == 0) nfront[cur ^ 1] = 0;
         int tot;
-        const int o = block_exscan(cnt, wsum, tot);
+        const int o = block_exscan<LOC_BLOCK>(cnt, wsum, tot);
         if (tid < nf) nofs[tid] = o;
         __syncthreads();
         for (int idx = tid; idx < tot; idx += LOC_BLOCK) {
