@@ -563,10 +563,8 @@ struct GlobalList {
 // Adaptive buckets: regions are rectangles in coordinates; a pass over N \ O visits the leaves
 // that meet it (and the disk of the current bound) and evaluates exactly the sites inside N and
 // outside O.  With a list (LS::K > 0, one lane per cell) the sites of the growing region G are
-// kept and later rays start from them.  LONLY: a ray that the list does not certify stops the
-// walk (heavy), so that every lane runs the same flat list loop; such cells take a second pass
-// with the full scanner.
-template <class P, class FS, class LS = NoList, bool LONLY = false>
+// kept and later rays start from them.
+template <class P, class FS, class LS = NoList>
 struct TreeScan {
     Tree T;
     FS fs;
@@ -769,8 +767,7 @@ struct TreeScan {
         Rect R = need_crect(C, Tr, dx, dy);
         Rect O = G;
         bool grow = true;   // O is still the list's region: the list may follow it
-        if (LONLY && !rect_inside(R, O)) heavy = true;
-        if (!LONLY && !rect_inside(R, O)) {
+        if (!rect_inside(R, O)) {
             probe(C, sxy, dx, dy, ex1, ex2, Tr, b, K);
             Uw = upper_of(C, sxy, b.w, dx, dy);
             U = fminf(U, Uw);
@@ -813,10 +810,6 @@ struct TreeScan {
                                             float dx, float dy, int ex1, int ex2, float tcap,
                                             Counters &K) {
         if (LS::K > 0 && cached) return scan_cached(C, sxy, dx, dy, ex1, ex2, tcap, K);
-        if (LONLY) {
-            heavy = true;
-            return ScanOut{};
-        }
         Best b{FINF, FINF, NO_TAG};
         float T0 = tcap;   // a vertex ray skips the sites outside the disk of its bound
         visit_f32<false>(C, sxy, Q0, NO_RECT, T0, tcap, dx, dy, ex1, ex2, b, K);

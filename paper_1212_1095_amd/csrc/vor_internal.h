@@ -83,7 +83,7 @@ struct PipeArgs {
     int *nodecnt() const { return small + 4; }   // nodes below the roots
     int *tabcnt() const { return small + 5; }
     int *rootcnt() const { return small + 6; }   // refined grid buckets (tree roots)
-    int *qcount4() const { return small + 7; }   // cells the list-only adaptive run hands on
+    int *qcount4() const { return small + 7; }   // cells the local grids hand to the tree scans
     int *qcount3() const { return small + 8; }
     int *nlist;             // [TREE_LEVELS - 1][ncap] node ids of refinement levels 2..
     unsigned char *bflag;   // [total] by sorted position: the site lies on the boundary of X
