@@ -136,6 +136,31 @@ __device__ __forceinline__ float key_hi_line(float c, float nx, float ny, float 
 __device__ __forceinline__ float site_q(float ex, float ey) { return fmaf(ex, ex, ey * ey); }
 #pragma clang fp contract(fast)
 
+// ------------------------------------------------------------------------------ workgroup scan
+// Exclusive prefix sum of one value per thread over a workgroup of B threads; `total` gets
+// the sum.  Every thread calls it (two barriers); wsum: B / 64 ints of LDS.
+template <int B>
+__device__ __forceinline__ int block_exscan(int v, int *wsum, int &total) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int incl = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int o = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += o;
+    }
+    if (lane == 63) wsum[wv] = incl;
+    __syncthreads();
+    int before = incl - v;
+    total = 0;
+#pragma unroll
+    for (int w = 0; w < B / 64; ++w) {
+        before += w < wv ? wsum[w] : 0;
+        total += wsum[w];
+    }
+    __syncthreads();
+    return before;
+}
+
 // ------------------------------------------------------------------------------ exact helpers
 __device__ __forceinline__ double u128_to_double(u128 m) {
     return (double)(uint64_t)(m >> 64) * 18446744073709551616.0 + (double)(uint64_t)m;

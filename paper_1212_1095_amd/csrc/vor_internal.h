@@ -105,6 +105,9 @@ void lloyd_round(int n, int *qx, int *qy, const int *cx, const int *cy,
                  unsigned long long *keys, int *cnt, unsigned cap, int *flag, hipStream_t st);
 void lloyd_moved(int n, const int *qx, const int *qy, const int *cx, const int *cy, int *moved,
                  hipStream_t st);
-long long scan_tmp_ints(long long n);
+// Prefix sums: SCAN_ITEMS values per thread of a SCAN_BLOCK-thread block; the per-tile partial
+// sums (one int per tile, plus one) live in scan_tmp.
+constexpr int SCAN_BLOCK = 256, SCAN_ITEMS = 4, SCAN_TILE = SCAN_BLOCK * SCAN_ITEMS;
+inline long long scan_tmp_ints(long long n) { return (n + SCAN_TILE - 1) / SCAN_TILE + 1; }
 
 }  // namespace vor

@@ -1145,33 +1145,7 @@ __global__ __launch_bounds__(64) void k_cells_bnd(
 // ------------------------------------------------------------------------------ scan
 // Exclusive scan of n int32 values (>= 0) into out[0..n], out[n] = total.  Three launches:
 // block sums, a single-block scan of the sums, per-block scan plus offset.
-constexpr int SCAN_BLOCK = 256, SCAN_ITEMS = 4, SCAN_TILE = SCAN_BLOCK * SCAN_ITEMS;
 
-__device__ __forceinline__ int block_excl_scan(int v, int *sh, int &total) {
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    int x = v;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int y = __shfl_up(x, o, 64);
-        if (lane >= o) x += y;
-    }
-    if (lane == 63) sh[wid] = x;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int acc = 0;
-        for (int i = 0; i < SCAN_BLOCK / 64; ++i) {
-            const int t = sh[i];
-            sh[i] = acc;
-            acc += t;
-        }
-        sh[SCAN_BLOCK / 64] = acc;
-    }
-    __syncthreads();
-    total = sh[SCAN_BLOCK / 64];
-    const int r = x - v + sh[wid];
-    __syncthreads();
-    return r;
-}
 
 __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_reduce(const int *__restrict__ in, long long n,
                                                             int *__restrict__ bsum,
@@ -1185,7 +1159,7 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_reduce(const int *__restric
     for (int t = 0; t < SCAN_ITEMS; ++t)
         if (base + t < n) v += in[base + t];
     int total;
-    (void)block_excl_scan(v, sh, total);
+    (void)block_exscan<SCAN_BLOCK>(v, sh, total);
     if (threadIdx.x == 0) bsum[blockIdx.x] = total;
 }
 
@@ -1198,7 +1172,7 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_top(int *__restrict__ bsum,
         const int i = base + threadIdx.x;
         const int v = i < nb ? bsum[i] : 0;
         int total;
-        const int e = block_excl_scan(v, sh, total);
+        const int e = block_exscan<SCAN_BLOCK>(v, sh, total);
         if (i < nb) bsum[i] = e + carry;
         carry += total;
     }
@@ -1220,7 +1194,7 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_apply(const int *__restrict
         s += v[t];
     }
     int total;
-    int e = block_excl_scan(s, sh, total) + bsum[blockIdx.x];
+    int e = block_exscan<SCAN_BLOCK>(s, sh, total) + bsum[blockIdx.x];
 #pragma unroll
     for (int t = 0; t < SCAN_ITEMS; ++t) {
         if (base + t < n) out[base + t] = e;
@@ -1510,7 +1484,6 @@ void launch_scan(const int *in, long long n, int *out, int *tmp, const int *stat
     k_scan_apply<<<nb, SCAN_BLOCK, 0, st>>>(in, n, tmp, out, status, gate);
 }
 
-long long scan_tmp_ints(long long n) { return (long long)nblk(n, SCAN_TILE) + 1; }
 
 template <int BLOCK>
 static void launch_fast(const PipeArgs &a, hipStream_t st) {

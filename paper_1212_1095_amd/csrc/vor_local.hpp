@@ -154,30 +154,6 @@ struct LocalSink {
     __device__ __forceinline__ void drop_last() { up -= lastup; }
 };
 
-// Exclusive prefix sum of one value per thread over a workgroup of B threads; `total` gets
-// the sum.  Every thread calls it (two barriers); wsum: B / 64 ints of LDS.
-template <int B>
-__device__ __forceinline__ int block_exscan(int v, int *wsum, int &total) {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    int incl = v;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const int o = __shfl_up(incl, off, 64);
-        if (lane >= off) incl += o;
-    }
-    if (lane == 63) wsum[wv] = incl;
-    __syncthreads();
-    int before = incl - v;
-    total = 0;
-#pragma unroll
-    for (int w = 0; w < B / 64; ++w) {
-        before += w < wv ? wsum[w] : 0;
-        total += wsum[w];
-    }
-    __syncthreads();
-    return before;
-}
-
 // Leaf ranges of a region: first sorted position, the full flag (every site of the leaf lies in
 // the region) and the prefix of the range lengths, appended in parallel.  One 64-bit LDS
 // counter holds (sites so far << 32 | ranges so far), so a range's slot and its prefix come
