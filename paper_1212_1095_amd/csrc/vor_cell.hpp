@@ -136,6 +136,11 @@ struct Coop {
     }
 };
 
+// The projector's corner ray i (0, 1, 2): (7, -4), (0, 1), (-7, -4), counter-clockwise, gaps < pi.
+__device__ __forceinline__ Dir corner_dir(int i) {
+    return make_dir(i == 1 ? 0 : (i == 0 ? 7 : -7), i == 1 ? 1 : -4);
+}
+
 // ------------------------------------------------------------------------------ FP32 scan
 struct ScanOut {
     Best b;
@@ -440,16 +445,68 @@ __device__ __forceinline__ void exact_sides(const Cell &C, const Dir &d, float T
 // (scan), the exact argmin over the region a scan certified (exact), and the exact argmin with
 // its own certification (exact_all, every decision exact).
 
+// The first-pass summaries of the three corner rays (one lane per cell): the rays have fixed
+// directions and scan the same block, so one pass over the block evaluates every candidate for
+// all three (sharing its load, offset and q).  LdsCorners keeps the summaries in nine LDS
+// columns that are free during the corner phase -- the top of the cell's stack, which stays
+// empty until the third corner ray has returned; NoCorners: every ray scans on its own.
+struct NoCorners {
+    static constexpr bool ON = false;
+    __device__ __forceinline__ void put(int, const Best &) {}
+    __device__ __forceinline__ Best get(int) const { return Best{FINF, FINF, NO_TAG}; }
+};
+template <int BLOCK>
+struct LdsCorners {
+    static constexpr bool ON = true;
+    int (*s)[BLOCK];   // nine rows
+    __device__ __forceinline__ void put(int c, const Best &b) {
+        s[3 * c][threadIdx.x] = __float_as_int(b.k1);
+        s[3 * c + 1][threadIdx.x] = __float_as_int(b.k2);
+        s[3 * c + 2][threadIdx.x] = b.w;
+    }
+    __device__ __forceinline__ Best get(int c) const {
+        return Best{__int_as_float(s[3 * c][threadIdx.x]), __int_as_float(s[3 * c + 1][threadIdx.x]),
+                    s[3 * c + 2][threadIdx.x]};
+    }
+};
+
 // Uniform bucket grid: regions are rectangles of buckets, rows are contiguous ranges.
-template <class P, class Rows, bool DETECT>
+template <class P, class Rows, bool DETECT, class CS = NoCorners>
 struct GridScan {
     Rows BR;
     const int *bstart;
     bool heavy;
+    CS cs;
+    int pre_n = -1;   // candidates of the corner pass (-1: none)
 
-    __device__ __forceinline__ void load(const Cell &C, const float2 *__restrict__) {
+    __device__ __forceinline__ void load(const Cell &C, const float2 *__restrict__ sxy) {
         const int longest = BR.load(C, bstart);
         heavy = DETECT && longest > SEG_HEAVY;
+        if (CS::ON && P::W == 1 && !heavy && BR.nrows <= MAXROWS) corners(C, sxy);
+    }
+
+    // The corner rays' pass over the block (no lines are excluded for them).
+    __device__ __forceinline__ void corners(const Cell &C, const float2 *__restrict__ sxy) {
+        const Dir d0 = corner_dir(0), d1 = corner_dir(1), d2 = corner_dir(2);
+        Best b0{FINF, FINF, NO_TAG}, b1 = b0, b2 = b0;
+        int n = 0;
+        for (int r = 0; r < BR.nrows; ++r) {
+            int pos, end;
+            BR.get(C, bstart, r, pos, end);
+            n += end - pos;
+            for (; pos < end; ++pos) {
+                const float2 a = sxy[pos];
+                const float ex = a.x - C.pxf, ey = a.y - C.pyf;
+                const float q = site_q_scan(ex, ey);
+                consider(key_lo_scan_q(q, ex, ey, d0.fx, d0.fy), pos, b0);
+                consider(key_lo_scan_q(q, ex, ey, d1.fx, d1.fy), pos, b1);
+                consider(key_lo_scan_q(q, ex, ey, d2.fx, d2.fy), pos, b2);
+            }
+        }
+        cs.put(0, b0);
+        cs.put(1, b1);
+        cs.put(2, b2);
+        pre_n = n;
     }
 
     // FP32 argmin (Method 11.6): the cell's block of shells 0..h (a warm start that bounds the
@@ -457,16 +514,20 @@ struct GridScan {
     // inside the scanned rectangle, grow the scanned rectangle towards it (at most doubling per
     // step); the rectangles of later, nearer bounds nest inside the earlier ones, so the final
     // scanned rectangle certifies the endpoint.
+    // corner: the corner ray's index (0..2) in the walk's first three steps, else -1.
     __device__ __forceinline__ ScanOut scan(const Cell &C, const float2 *__restrict__ sxy,
                                             float dx, float dy, int ex1, int ex2, float tcap,
-                                            Counters &K) {
+                                            Counters &K, int corner = -1) {
         Best b{FINF, FINF, NO_TAG};
         const Rect A = block_rect(C);
         // A vertex ray (tcap bounds its endpoint) starts from its own rectangle S_I when that
         // lies in the block: the rectangles of smaller bounds nest inside it, so the scan
         // never grows, and the block's other sites are farther from the target than p.
         const Rect O0 = first_rect(C, A, tcap, dx, dy);
-        if (P::W == 1 && BR.nrows <= MAXROWS) {
+        if (CS::ON && corner >= 0 && pre_n >= 0) {
+            b = cs.get(corner);   // the block, from the corner pass (O0 = A: no bound)
+            K.evals += (uint32_t)pre_n;
+        } else if (P::W == 1 && BR.nrows <= MAXROWS) {
             for (int y = O0.y0; y <= O0.y1; ++y) {
                 int pos, end;
                 BR.get(C, bstart, y - A.y0, pos, end);
@@ -808,7 +869,7 @@ struct TreeScan {
 
     __device__ __forceinline__ ScanOut scan(const Cell &C, const float2 *__restrict__ sxy,
                                             float dx, float dy, int ex1, int ex2, float tcap,
-                                            Counters &K) {
+                                            Counters &K, int = -1) {
         if (LS::K > 0 && cached) return scan_cached(C, sxy, dx, dy, ex1, ex2, tcap, K);
         Best b{FINF, FINF, NO_TAG};
         float T0 = tcap;   // a vertex ray skips the sites outside the disk of its bound
@@ -972,7 +1033,7 @@ struct PosSink {
 template <int MODE, class P, class Sc>
 __device__ __forceinline__ int ray(const Cell &C, Sc &sc, const float2 *__restrict__ sxy,
                                    const Dir &d, int64_t Den, int ex1, int ex2, Line &out,
-                                   Counters &K) {
+                                   Counters &K, int corner = -1) {
     const bool vmode = Den > 0;
     float tu_hi = FINF, tu_lo = FINF;
     if (vmode) {
@@ -988,7 +1049,7 @@ __device__ __forceinline__ int ray(const Cell &C, Sc &sc, const float2 *__restri
         sc.exact_all(C, sxy, d, tu_hi, ex1, ex2, xb, K);
     } else {
         // one scan variant for both kinds of rays (lanes of a wave may differ in kind)
-        const ScanOut s = sc.scan(C, sxy, d.fx, d.fy, ex1, ex2, vmode ? tu_hi : FINF, K);
+        const ScanOut s = sc.scan(C, sxy, d.fx, d.fy, ex1, ex2, vmode ? tu_hi : FINF, K, corner);
         if (sc.heavy) return -4;
         if (vmode && s.b.k1 * CERT_DN > tu_hi) return 1;
         const float uw = s.Uw * CERT_UP;
@@ -1035,10 +1096,6 @@ __device__ __forceinline__ void split_dir(const Line &L1, const Line &L2, Dir &d
     }
 }
 
-// The projector's corner ray i (0, 1, 2): (7, -4), (0, 1), (-7, -4), counter-clockwise, gaps < pi.
-__device__ __forceinline__ Dir corner_dir(int i) {
-    return make_dir(i == 1 ? 0 : (i == 0 ? 7 : -7), i == 1 ? 1 : -4);
-}
 
 // ------------------------------------------------------------------------------ one cell
 // The walk over a cell's subedges as a resumable state: cell_begin, then cell_step until it
@@ -1093,7 +1150,7 @@ __device__ __forceinline__ int cell_step(const Cell &C, const float2 *__restrict
         else split_dir(cur, R, d, Den, ex1, ex2);
     }
     if (!leaf) {
-        const int r = ray<MODE, P, Sc>(C, sc, sxy, d, Den, ex1, ex2, L3, K);
+        const int r = ray<MODE, P, Sc>(C, sc, sxy, d, Den, ex1, ex2, L3, K, phase < 3 ? phase : -1);
         if (r < 0) return r == -4 ? -4 : -1;
         leaf = (r == 1);
         // a shot ray (Lemma on shot rays) yields a corner; a ray that confirms a vertex is the

@@ -115,13 +115,18 @@ __device__ __forceinline__ float key_lo_line(float c, float nx, float ny, float 
 // neighbour of the exact |delta|^2 within half an ulp (only an exact tie may round the other
 // way), so the error bounds above hold unchanged.
 constexpr float Q_TINY = 0x1p-100f;
-__device__ __forceinline__ float key_lo_scan(float ex, float ey, float dx, float dy) {
-    const float q = fmaf(ex, ex, fmaf(ey, ey, Q_TINY));
+__device__ __forceinline__ float site_q_scan(float ex, float ey) {
+    return fmaf(ex, ex, fmaf(ey, ey, Q_TINY));
+}
+__device__ __forceinline__ float key_lo_scan_q(float q, float ex, float ey, float dx, float dy) {
     const float mx = ex * dx, my = ey * dy;
     const float den = mx + my;
     const float S = fabsf(mx) + fabsf(my);
     const float up = fmaxf(fmaf(GAMMA, S, den), 0.0f);
     return q * __builtin_amdgcn_rcpf(up);
+}
+__device__ __forceinline__ float key_lo_scan(float ex, float ey, float dx, float dy) {
+    return key_lo_scan_q(site_q_scan(ex, ey), ex, ey, dx, dy);
 }
 // Upper bound key (+inf unless N.d is certainly > 0).
 __device__ __forceinline__ float key_hi_line(float c, float nx, float ny, float dx, float dy) {

@@ -414,7 +414,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5, 8))) v
         const int k = sid[pos];
         const int g = S.site_off + k;
         LdsStack<BLOCK> st{stk, 0};
-        GridScan<Solo, LdsRows<BLOCK>, true> sc{LdsRows<BLOCK>{rlo, rhi, 0}, bstart, false};
+        // the corner rays' summaries in the stack's top nine rows (empty in the corner phase)
+        static_assert(SCAP >= 9, "the stack holds the corner summaries");
+        GridScan<Solo, LdsRows<BLOCK>, true, LdsCorners<BLOCK>> sc{
+            LdsRows<BLOCK>{rlo, rhi, 0}, bstart, false, LdsCorners<BLOCK>{&stk[SCAP - 9]}};
         Sink sink{olines + pos, total, sid, k};
         const int r = run_cell<0, Solo>(C, sxy, sc, st, SCAP, sink, KOUT, K);
         ovf[pos] = -1;

@@ -83,7 +83,7 @@ struct LocalScan {
 
     __device__ __forceinline__ ScanOut scan(const Cell &C, const float2 *__restrict__ sxy,
                                             float dx, float dy, int ex1, int ex2, float tcap,
-                                            Counters &K) {
+                                            Counters &K, int = -1) {
         Best b{FINF, FINF, NO_TAG};
         const Rect A = block_rect(C);
         Rect O0 = A;
