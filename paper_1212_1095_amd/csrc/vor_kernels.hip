@@ -639,7 +639,8 @@ __global__ __launch_bounds__(LOC_BLOCK) void k_cells_local(
                 int(*rhi)[LOC_BLOCK] =
                     reinterpret_cast<int(*)[LOC_BLOCK]>(work + (SCAP + MAXROWS) * LOC_BLOCK);
                 LdsStack<LOC_BLOCK> st{stk, 0};
-                LocalScan<LOC_BLOCK> sc{G, LdsRows<LOC_BLOCK>{rlo, rhi, 0}, false};
+                LocalScan<LOC_BLOCK> sc{G, LdsRows<LOC_BLOCK>{rlo, rhi, 0}, false,
+                                        LdsCorners<LOC_BLOCK>{stk + SCAP - 9}};
                 LocalSink sink{olines + pos, total, sid, lpos, k};
                 const int r = run_cell<0, Solo>(CL, lxy, sc, st, SCAP, sink, KOUT, K);
                 if (r >= 0) {

@@ -75,15 +75,42 @@ struct LocalScan {
     LocalGrid G;
     LdsRows<BLOCK> BR;
     bool heavy;
+    LdsCorners<BLOCK> cs;   // the corner rays' summaries (the stack's top rows, as GridScan)
+    int pre_n = -1;
 
-    __device__ __forceinline__ void load(const Cell &C, const float2 *__restrict__) {
+    __device__ __forceinline__ void load(const Cell &C, const float2 *__restrict__ sxy) {
         BR.load(C, G.start);   // at most 5 rows (h = 2)
         heavy = false;
+        corners(C, sxy);
+    }
+
+    // The corner rays' pass over the block (as GridScan::corners).
+    __device__ __forceinline__ void corners(const Cell &C, const float2 *__restrict__ sxy) {
+        const Dir d0 = corner_dir(0), d1 = corner_dir(1), d2 = corner_dir(2);
+        Best b0{FINF, FINF, NO_TAG}, b1 = b0, b2 = b0;
+        int n = 0;
+        for (int r = 0; r < BR.nrows; ++r) {
+            int pos, end;
+            BR.get(C, G.start, r, pos, end);
+            n += end - pos;
+            for (; pos < end; ++pos) {
+                const float2 a = sxy[pos];
+                const float ex = a.x - C.pxf, ey = a.y - C.pyf;
+                const float q = site_q_scan(ex, ey);
+                consider(key_lo_scan_q(q, ex, ey, d0.fx, d0.fy), pos, b0);
+                consider(key_lo_scan_q(q, ex, ey, d1.fx, d1.fy), pos, b1);
+                consider(key_lo_scan_q(q, ex, ey, d2.fx, d2.fy), pos, b2);
+            }
+        }
+        cs.put(0, b0);
+        cs.put(1, b1);
+        cs.put(2, b2);
+        pre_n = n;
     }
 
     __device__ __forceinline__ ScanOut scan(const Cell &C, const float2 *__restrict__ sxy,
                                             float dx, float dy, int ex1, int ex2, float tcap,
-                                            Counters &K, int = -1) {
+                                            Counters &K, int corner = -1) {
         Best b{FINF, FINF, NO_TAG};
         const Rect A = block_rect(C);
         Rect O0 = A;
@@ -92,13 +119,18 @@ struct LocalScan {
             const Rect R0 = need_rect_local(C, G, tcap, dx, dy, out0);
             if (!out0 && rect_inside(R0, A)) O0 = R0;
         }
-        for (int y = O0.y0; y <= O0.y1; ++y) {
-            int pos, end;
-            BR.get(C, G.start, y - A.y0, pos, end);
-            const int base = y * C.gx;
-            if (O0.x0 != A.x0) pos = G.start[base + O0.x0];
-            if (O0.x1 != A.x1) end = G.start[base + O0.x1 + 1];
-            eval_range<1>(C, sxy, pos, end, dx, dy, ex1, ex2, b, K);
+        if (corner >= 0 && pre_n >= 0) {
+            b = cs.get(corner);   // the block, from the corner pass (no bound: O0 = A)
+            K.evals += (uint32_t)pre_n;
+        } else {
+            for (int y = O0.y0; y <= O0.y1; ++y) {
+                int pos, end;
+                BR.get(C, G.start, y - A.y0, pos, end);
+                const int base = y * C.gx;
+                if (O0.x0 != A.x0) pos = G.start[base + O0.x0];
+                if (O0.x1 != A.x1) end = G.start[base + O0.x1 + 1];
+                eval_range<1>(C, sxy, pos, end, dx, dy, ex1, ex2, b, K);
+            }
         }
         consider_sides(C, dx, dy, ex1, ex2, b);
         K.shells++;
