@@ -465,8 +465,9 @@ __global__ __launch_bounds__(LOC_BLOCK) void k_cells_local(
     __shared__ float2 lxy[LOC_CAP];
     __shared__ int lpos[LOC_CAP];
     __shared__ int lstart[LOC_BCAP + 1];
-    // leaf ranges of the gather (first position, full flag, prefix); then the sort's counters
-    __shared__ int raux[3 * LOC_RCAP];
+    // leaf ranges of the gather (first position or its complement, prefix); then the sort's
+    // fill counters
+    __shared__ int raux[2 * LOC_RCAP];
     // the gather's frontier and node fields; then the gathered sites, unsorted; then the
     // walks' stacks and block rows
     __shared__ int work[(SCAP + 2 * MAXROWS) * LOC_BLOCK];
@@ -482,7 +483,7 @@ __global__ __launch_bounds__(LOC_BLOCK) void k_cells_local(
     if (tid < SL_COUNT) sh[tid] = 0;
     float2 *const txy = reinterpret_cast<float2 *>(work);
     int *const tpos = work + 2 * LOC_CAP;
-    const RangeList RL{raux, raux + LOC_RCAP, raux + 2 * LOC_RCAP, &s_rc, &s_fail};
+    const RangeList RL{raux, raux + LOC_RCAP, &s_rc, &s_fail};
     const Tree T{tstart, tchild, nodes, tref};
     Counters K{};
     uint32_t edges = 0, deferred = 0, handled = 0;
@@ -552,9 +553,10 @@ __global__ __launch_bounds__(LOC_BLOCK) void k_cells_local(
                         const int mid = (lo + hi + 1) >> 1;
                         if (RL.ofs[mid] <= i) lo = mid; else hi = mid - 1;
                     }
-                    const int q = RL.lo[lo] + (i - RL.ofs[lo]);
+                    const int l0 = RL.lo[lo];
+                    const int q = (l0 < 0 ? ~l0 : l0) + (i - RL.ofs[lo]);
                     const float2 a = sxy[q];
-                    if (RL.full[lo] || in_rect(RW, a.x, a.y)) {
+                    if (l0 < 0 || in_rect(RW, a.x, a.y)) {
                         const int slot = atomicAdd(&s_cnt, 1);
                         if (slot < LOC_CAP) {
                             txy[slot] = a;

@@ -19,15 +19,15 @@ namespace vor {
 constexpr int LOC_BLOCK = 256;      // cells per chunk (threads of a workgroup)
 constexpr int LOC_CAP = 1280;       // sites of a chunk's region at most
 constexpr int LOC_BCAP = 1024;      // local buckets at most (= 4 per thread, see the scan)
-constexpr int LOC_RCAP = 384;       // leaf ranges of the region at most
+constexpr int LOC_RCAP = 768;       // leaf ranges of the region at most
 constexpr float LOC_SPB = 1.5f;     // sites per local bucket
 constexpr float LOC_MARGIN = 2.5f;  // region margin in local spacings
 constexpr int LOC_GRID_MAX = 4096;  // workgroups at most (then each takes several chunks)
-constexpr int LOC_NF = LOC_BLOCK;   // refined nodes per level of a region's gather at most
+constexpr int LOC_NF = 2 * LOC_BLOCK;   // refined nodes per level of a region's gather at most
 constexpr int LOC_GBMAX = 4096;     // grid buckets of a region at most
 constexpr int LOC_MINGROUP = 32;    // a region that overflows is split down to this many cells
 static_assert(LOC_BCAP == 4 * LOC_BLOCK, "the bucket scan gives each thread four buckets");
-static_assert(3 * LOC_RCAP >= LOC_BCAP, "the fill counters reuse the range table");
+static_assert(2 * LOC_RCAP >= LOC_BCAP, "the fill counters reuse the range table");
 
 // The local grid of a chunk.  Coordinates stay relative to the set's box origin.
 struct LocalGrid {
@@ -186,15 +186,15 @@ struct LocalSink {
     __device__ __forceinline__ void drop_last() { up -= lastup; }
 };
 
-// Leaf ranges of a region: first sorted position, the full flag (every site of the leaf lies in
-// the region) and the prefix of the range lengths, appended in parallel.  One 64-bit LDS
-// counter holds (sites so far << 32 | ranges so far), so a range's slot and its prefix come
-// from the same atomic and the prefixes grow with the slots.
+// Leaf ranges of a region: first sorted position (bitwise complemented when every site of the
+// leaf lies in the region: no per-site test) and the prefix of the range lengths, appended in
+// parallel.  One 64-bit LDS counter holds (sites so far << 32 | ranges so far), so a range's
+// slot and its prefix come from the same atomic and the prefixes grow with the slots.
 struct RangeList {
-    int *lo, *full, *ofs;       // LOC_RCAP each (LDS)
+    int *lo, *ofs;              // LOC_RCAP each (LDS)
     unsigned long long *rc;     // the counter (LDS)
     int *fail;                  // set on overflow (LDS)
-    __device__ __forceinline__ void add(int a, int b, bool f) const {
+    __device__ __forceinline__ void add(int a, int b, bool full) const {
         if (a >= b) return;
         const unsigned long long old = atomicAdd(rc, ((unsigned long long)(b - a) << 32) | 1ull);
         const int slot = (int)(old & 0xffffffffull);
@@ -202,8 +202,7 @@ struct RangeList {
             *fail = 1;
             return;
         }
-        lo[slot] = a;
-        full[slot] = f;
+        lo[slot] = full ? ~a : a;
         ofs[slot] = (int)(old >> 32);
     }
 };
@@ -213,7 +212,8 @@ struct RangeList {
 // ones (one round of loads per level instead of a depth-first walk of dependent loads).  The
 // leaves go to `R`; `*fail` is set when a level holds more than LOC_NF refined nodes or the
 // region more than LOC_GBMAX grid buckets.  Every thread calls it (barriers); the LDS scratch
-// `nodeinfo` holds 2 LOC_NF frontier ids and 9 LOC_NF node fields.
+// `nodeinfo` holds 2 LOC_NF frontier ids and 9 LOC_NF node fields (nodes 2t and 2t + 1 are
+// thread t's).
 __device__ __forceinline__ void gather_leaves(const SetDesc &S, const Tree &T, const Rect &RW,
                                               const RangeList &R, int *nodeinfo, int *nfront,
                                               int *wsum) {
@@ -247,28 +247,32 @@ __device__ __forceinline__ void gather_leaves(const SetDesc &S, const Tree &T, c
         const int cur = lv & 1;
         const int nf = nfront[cur];
         if (nf == 0 || *R.fail) return;   // uniform: read after a barrier
-        int cnt = 0;
-        if (tid < nf) {
-            const TNode t = T.nodes[front[cur][tid]];
+        int cnt[2] = {0, 0};
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int a = 2 * tid + h;
+            if (a >= nf) continue;
+            const TNode t = T.nodes[front[cur][a]];
             // the children that meet RW (the sites' square is m ss wide from (ox, oy))
             const int i0 = max(RW.x0 - t.ox, 0) / t.ss, j0 = max(RW.y0 - t.oy, 0) / t.ss;
             const int i1 = RW.x1 < t.ox ? -1 : min((RW.x1 - t.ox) / t.ss, t.m - 1);
             const int j1 = RW.y1 < t.oy ? -1 : min((RW.y1 - t.oy) / t.ss, t.m - 1);
             const int ni = i1 - i0 + 1, nj = j1 - j0 + 1;
-            cnt = ni > 0 && nj > 0 ? ni * nj : 0;
-            ntab[tid] = t.tab;
-            nm[tid] = t.m;
-            nox[tid] = t.ox;
-            noy[tid] = t.oy;
-            nss[tid] = t.ss;
-            ni0[tid] = i0;
-            nj0[tid] = j0;
-            nni[tid] = max(ni, 1);
+            cnt[h] = ni > 0 && nj > 0 ? ni * nj : 0;
+            ntab[a] = t.tab;
+            nm[a] = t.m;
+            nox[a] = t.ox;
+            noy[a] = t.oy;
+            nss[a] = t.ss;
+            ni0[a] = i0;
+            nj0[a] = j0;
+            nni[a] = max(ni, 1);
         }
         if (tid == 0) nfront[cur ^ 1] = 0;
         int tot;
-        const int o = block_exscan<LOC_BLOCK>(cnt, wsum, tot);
-        if (tid < nf) nofs[tid] = o;
+        const int o = block_exscan<LOC_BLOCK>(cnt[0] + cnt[1], wsum, tot);
+        if (2 * tid < nf) nofs[2 * tid] = o;
+        if (2 * tid + 1 < nf) nofs[2 * tid + 1] = o + cnt[0];
         __syncthreads();
         for (int idx = tid; idx < tot; idx += LOC_BLOCK) {
             int a = 0, b = nf - 1;   // the node holding child idx
