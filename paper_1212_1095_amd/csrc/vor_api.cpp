@@ -79,6 +79,7 @@ struct Workspace {
     DevBuf b[B_COUNT];
     HostBuf h_in, h_small;
     std::vector<SideRel> sides_h;   // side table of the sets being launched
+    std::vector<char> up_cache;     // set descriptors, side table, set offsets last uploaded
     DevBuf lcx, lcy, lqx, lqy, lkeys, lcnt, lflag;   // Lloyd iterations
     HostBuf h_lloyd;
     hipStream_t stream = nullptr;
@@ -283,15 +284,25 @@ int launch(vor_ctx *ctx, Workspace &ws, const std::vector<HostSet> &sets, bool v
         in_x = ws.b[B_INX].as<int>();
         in_y = ws.b[B_INY].as<int>();
     }
-    e = hipMemcpyAsync(ws.b[B_SETS].p, descs.data(), sizeof(SetDesc) * K, hipMemcpyHostToDevice,
-                       ws.stream);
-    if (e == hipSuccess && !ws.sides_h.empty())
-        e = hipMemcpyAsync(ws.b[B_SIDES].p, ws.sides_h.data(), sizeof(SideRel) * ws.sides_h.size(),
-                           hipMemcpyHostToDevice, ws.stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(ws.b[B_SETOFF].p, set_off.data(), 4ull * (K + 1),
-                           hipMemcpyHostToDevice, ws.stream);
-    if (e != hipSuccess) return VOR_E_DEVICE;
+    // set descriptors, side table and set offsets: uploaded when they differ from what these
+    // buffers last received (repeated calls on one shape skip the copies)
+    const size_t nd = sizeof(SetDesc) * K, ns = sizeof(SideRel) * ws.sides_h.size();
+    std::vector<char> up(nd + ns + 4ull * (K + 1));
+    std::memcpy(up.data(), descs.data(), nd);
+    if (ns) std::memcpy(up.data() + nd, ws.sides_h.data(), ns);
+    std::memcpy(up.data() + nd + ns, set_off.data(), 4ull * (K + 1));
+    if (grew || up != ws.up_cache) {
+        ws.up_cache.clear();   // valid again only once every copy was issued
+        e = hipMemcpyAsync(ws.b[B_SETS].p, descs.data(), nd, hipMemcpyHostToDevice, ws.stream);
+        if (e == hipSuccess && ns)
+            e = hipMemcpyAsync(ws.b[B_SIDES].p, ws.sides_h.data(), ns, hipMemcpyHostToDevice,
+                               ws.stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(ws.b[B_SETOFF].p, set_off.data(), 4ull * (K + 1),
+                               hipMemcpyHostToDevice, ws.stream);
+        if (e != hipSuccess) return VOR_E_DEVICE;
+        ws.up_cache.swap(up);
+    }
 
     void *ptrs[B_COUNT];
     for (int id = 0; id < B_COUNT; ++id) ptrs[id] = ws.b[id].p;
@@ -350,19 +361,9 @@ int launch(vor_ctx *ctx, Workspace &ws, const std::vector<HostSet> &sets, bool v
     }
     ws.used_graph = launched;
     if ((e = hipEventRecord(ws.ev1, ws.stream)) != hipSuccess) return VOR_E_DEVICE;
-    // small summary: status words, stats, totals
-    if (ws.h_small.ensure(4 * SMALL_INTS + 8 * SL_COUNT + 16) != hipSuccess) return VOR_E_NOMEM;
-    char *hs = (char *)ws.h_small.p;
-    e = hipMemcpyAsync(hs, a.small, 4 * SMALL_INTS, hipMemcpyDeviceToHost, ws.stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(hs + 4 * SMALL_INTS, a.stats, 8 * SL_COUNT, hipMemcpyDeviceToHost,
-                           ws.stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(hs + 4 * SMALL_INTS + 8 * SL_COUNT, a.cell_off + T, 4,
-                           hipMemcpyDeviceToHost, ws.stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(hs + 4 * SMALL_INTS + 8 * SL_COUNT + 4, a.del_off + T, 4,
-                           hipMemcpyDeviceToHost, ws.stream);
+    // small summary in one copy: status words, totals, counters
+    if (ws.h_small.ensure(SUMMARY_BYTES) != hipSuccess) return VOR_E_NOMEM;
+    e = hipMemcpyAsync(ws.h_small.p, a.small, SUMMARY_BYTES, hipMemcpyDeviceToHost, ws.stream);
     return e == hipSuccess ? VOR_OK : VOR_E_DEVICE;
 }
 
@@ -380,8 +381,8 @@ Summary read_summary(Workspace &ws) {
     const int *sm = (const int *)hs;
     s.status = sm[0];
     std::memcpy(s.stats, hs + 4 * SMALL_INTS, 8 * SL_COUNT);
-    s.edges = *(const int *)(hs + 4 * SMALL_INTS + 8 * SL_COUNT);
-    s.dels = *(const int *)(hs + 4 * SMALL_INTS + 8 * SL_COUNT + 4);
+    s.edges = sm[16];   // PipeArgs::tot_entries
+    s.dels = sm[17];    // PipeArgs::tot_dels
     s.ms = s.cells_ms = s.exact_ms = 0.0f;
     for (auto &x : s.stage_ms) x = 0.0f;
     (void)hipEventElapsedTime(&s.ms, ws.ev0, ws.ev1);

@@ -8,7 +8,7 @@ namespace vor {
 struct SetDesc;
 struct SideRel;
 struct TNode;
-constexpr int SMALL_INTS = 16;   // status, queue counters, pool / tree counters, spare
+constexpr int SMALL_INTS = 20;   // status, queue counters, pool / tree counters, totals, spare
 constexpr int DEEP_BLOCKS = 4;   // workgroups of the deep-cell pass (one cell each at a time)
 constexpr int WIDE_WAVES = 8;    // waves of such a workgroup (subwedges resolved in parallel)
 constexpr int WIDE_CAP = 65536 + 64;   // corners of one deep cell (a cell has at most 65536
@@ -90,6 +90,10 @@ struct PipeArgs {
     unsigned char *hand;    // [total] by sorted position: the filtered pass handed the cell on
     int *queue5;            // sorted positions of such sites (the boundary pass) [total]
     int *qcount5() const { return small + 15; }
+    // the run's totals (entries, Delaunay pairs) beside the counters, so that one copy brings
+    // back status, counters and totals; the device counters follow the SMALL_INTS words
+    int *tot_entries() const { return small + 16; }
+    int *tot_dels() const { return small + 17; }
 };
 
 // stages: 0 grid build and refinement, 1 filtered cell pass, 2 adaptive pass, 3 exact / deep

@@ -1188,7 +1188,7 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_apply(const int *__restrict
                                                            const int *__restrict__ bsum,
                                                            int *__restrict__ out,
                                                            const int *__restrict__ status,
-                                                           int gate) {
+                                                           int gate, int *__restrict__ tot) {
     __shared__ int sh[SCAN_BLOCK / 64 + 1];
     if (gate && *status) return;
     const long long base = (long long)blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
@@ -1205,7 +1205,10 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_apply(const int *__restrict
     for (int t = 0; t < SCAN_ITEMS; ++t) {
         if (base + t < n) out[base + t] = e;
         e += v[t];
-        if (base + t == n - 1) out[n] = e;
+        if (base + t == n - 1) {
+            out[n] = e;
+            if (tot) *tot = e;
+        }
     }
 }
 
@@ -1482,12 +1485,13 @@ __global__ void k_symmetry(const SetDesc *__restrict__ sets, int nsets,
 // ------------------------------------------------------------------------------ launchers
 static inline unsigned nblk(long long n, int b) { return (unsigned)((n + b - 1) / b); }
 
+// Exclusive prefix sums of in[0..n) into out[0..n], the total also into *tot when given.
 void launch_scan(const int *in, long long n, int *out, int *tmp, const int *status, int gate,
-                 hipStream_t st) {
+                 hipStream_t st, int *tot = nullptr) {
     const unsigned nb = nblk(n, SCAN_TILE);
     k_scan_reduce<<<nb, SCAN_BLOCK, 0, st>>>(in, n, tmp, status, gate);
     k_scan_top<<<1, SCAN_BLOCK, 0, st>>>(tmp, (int)nb, status, gate);
-    k_scan_apply<<<nb, SCAN_BLOCK, 0, st>>>(in, n, tmp, out, status, gate);
+    k_scan_apply<<<nb, SCAN_BLOCK, 0, st>>>(in, n, tmp, out, status, gate, tot);
 }
 
 
@@ -1586,8 +1590,8 @@ void launch_stage(const PipeArgs &a, hipStream_t st, int stage) {
         else launch_exact<1>(a, st);
     } else {
         // CSR offsets and Delaunay offsets, then neighbours, vertices and Delaunay pairs
-        launch_scan(a.ocnt, T, a.cell_off, a.scan_tmp, a.status(), 1, st);
-        launch_scan(a.dcnt, T, a.del_off, a.scan_tmp, a.status(), 1, st);
+        launch_scan(a.ocnt, T, a.cell_off, a.scan_tmp, a.status(), 1, st, a.tot_entries());
+        launch_scan(a.dcnt, T, a.del_off, a.scan_tmp, a.status(), 1, st, a.tot_dels());
         if (a.with_vertices)
             k_emit<true><<<nblk(T, EMIT_BLOCK), EMIT_BLOCK, 0, st>>>(
                 a.sets, a.nsets, a.set_off, a.sides, T, a.sid, a.sxy, a.olines, a.ovf, a.pool,

@@ -109,24 +109,22 @@ extern "C" int vor_compute_noalloc(int32_t device, void *stream, const vor_set *
     a.vtx = vtx;
     a.del = del;
     launch_pipeline(a, st);
-    // status, counters and totals back to the host
-    int small[SMALL_INTS];
-    unsigned long long sl[SL_COUNT];
-    int tot[2] = {0, 0};
+    // status, totals and counters back to the host, one copy
+    alignas(8) unsigned char sum[SUMMARY_BYTES];
     e = hipGetLastError();
-    if (e == hipSuccess) e = hipMemcpyAsync(small, a.small, sizeof(small), hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(sl, a.stats, sizeof(sl), hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(&tot[0], a.cell_off + n, 4, hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(&tot[1], a.del_off + n, 4, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(sum, a.small, SUMMARY_BYTES, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         return VOR_E_DEVICE;
     }
+    const int *small = (const int *)sum;
+    unsigned long long sl[SL_COUNT];
+    std::memcpy(sl, sum + 4 * SMALL_INTS, sizeof(sl));
     rc = map_status(small[0]);
     if (rc != VOR_OK) return rc;
-    *entries = (uint64_t)tot[0];
-    *m = (uint64_t)tot[1];
+    *entries = (uint64_t)small[16];   // PipeArgs::tot_entries
+    *m = (uint64_t)small[17];         // PipeArgs::tot_dels
     if (stats) fill_stats(*stats, sl);
     return VOR_OK;
 }

@@ -207,8 +207,8 @@ int run_sizes(long long T, long long gtot, long long sides, int K, size_t nsides
     b[B_VTX] = vertices ? sizeof(vor_rat) * E : 16;
     b[B_DEL] = 8ull * D;
     b[B_SCANTMP] = 4ull * stmp;
-    b[B_SMALL] = 4ull * SMALL_INTS;
-    b[B_STATS] = 8ull * SL_COUNT;
+    b[B_SMALL] = SUMMARY_BYTES;   // the small words and the counters together
+    b[B_STATS] = 8;
     b[B_SIDES] = sizeof(SideRel) * std::max<size_t>(1, nsides);
     b[B_TLIST] = 4ull * TREE_LIST * TREE_PASS_BLOCK * tree_pass_blocks(T);
     return VOR_OK;
@@ -268,7 +268,7 @@ void fill_args(PipeArgs &a, void *const p[B_COUNT], const RunSizes &z, bool any_
     a.del_cap = z.D;
     a.scan_tmp = (int *)p[B_SCANTMP];
     a.small = (int *)p[B_SMALL];
-    a.stats = (unsigned long long *)p[B_STATS];
+    a.stats = (unsigned long long *)((char *)p[B_SMALL] + 4 * SMALL_INTS);
     a.block = tune.block;
     a.tree_all = tune.scan_path == VOR_PATH_TREE;
     a.exact_only = exact_only;

@@ -53,6 +53,11 @@ int check_set(const vor_set *s, HostSet &h);
 // Uniform grid of Method 11.5 with about `rho` sites per square bucket (area: of X).
 void choose_grid(const vor_box &b, uint32_t n, float rho, int hw, SetDesc &d, double area = 0);
 
+// The words read back after a run, one copy: SMALL_INTS status / counter / total words, then
+// the device counters (stats) right after them in the same buffer.
+constexpr size_t SUMMARY_BYTES = 4 * SMALL_INTS + 8 * SL_COUNT;
+static_assert((4 * SMALL_INTS) % 8 == 0, "the counters follow the small words 8-byte aligned");
+
 // Device status word -> VOR status.
 int map_status(int st);
 
