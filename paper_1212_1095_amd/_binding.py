@@ -264,7 +264,7 @@ def _to_result(rp, device: bool = False) -> Result:
     vtx = None
     if r.vtx and E:
         buf = (C.c_char * (E * _RAT.itemsize)).from_address(r.vtx)
-        vtx = np.frombuffer(bytes(buf), dtype=_RAT).copy()
+        vtx = np.frombuffer(buf, dtype=_RAT).copy()   # one copy out of the library's result
     m = int(r.m)
     dele = (np.ctypeslib.as_array(C.cast(r.del_, C.POINTER(C.c_uint32)), (2 * m,)).copy()
             .reshape(m, 2) if m else np.zeros((0, 2), np.uint32))

@@ -77,7 +77,7 @@ struct HostBuf {   // pinned staging
 
 struct Workspace {
     DevBuf b[B_COUNT];
-    HostBuf h_in, h_small;
+    HostBuf h_in, h_small, h_out;   // pinned staging: inputs, summary, a run's outputs
     std::vector<SideRel> sides_h;   // side table of the sets being launched
     std::vector<char> up_cache;     // set descriptors, side table, set offsets last uploaded
     DevBuf lcx, lcy, lqx, lqy, lkeys, lcnt, lflag;   // Lloyd iterations
@@ -116,6 +116,8 @@ struct Workspace {
         drop_graph();
         for (auto &x : b) x.release();
         h_in.release();
+        h_out.release();
+        up_cache.clear();
     }
     void destroy() {
         if (stream) (void)hipStreamSynchronize(stream);
@@ -124,6 +126,7 @@ struct Workspace {
         for (DevBuf *x : {&lcx, &lcy, &lqx, &lqy, &lkeys, &lcnt, &lflag}) x->release();
         h_in.release();
         h_small.release();
+        h_out.release();
         h_lloyd.release();
         if (ev0) (void)hipEventDestroy(ev0);
         if (ev1) (void)hipEventDestroy(ev1);
@@ -401,19 +404,28 @@ Summary read_summary(Workspace &ws) {
 // Copy the results of every set back to host ResultBoxes (after the stream is idle).
 int collect_host(Workspace &ws, const PipeArgs &a, const std::vector<SetDesc> &descs,
                  const Summary &sm, bool vertices, std::vector<vor_result *> &outs) {
+    // the run's output arrays in one pinned staging buffer (direct DMA, reused across calls),
+    // then each set's slices into its own result
     const long long T = a.total;
-    std::vector<int> off(T + 1), doff(T + 1);
-    std::vector<int> nbr(sm.edges);
-    std::vector<vor_rat> vtx(vertices ? sm.edges : 0);
-    std::vector<uint32_t> del(2 * sm.dels);
-    hipError_t e = hipMemcpy(off.data(), a.cell_off, 4ull * (T + 1), hipMemcpyDeviceToHost);
-    if (e == hipSuccess) e = hipMemcpy(doff.data(), a.del_off, 4ull * (T + 1), hipMemcpyDeviceToHost);
-    if (e == hipSuccess && sm.edges)
-        e = hipMemcpy(nbr.data(), a.nbr, 4ull * sm.edges, hipMemcpyDeviceToHost);
-    if (e == hipSuccess && vertices && sm.edges)
-        e = hipMemcpy(vtx.data(), a.vtx, sizeof(vor_rat) * sm.edges, hipMemcpyDeviceToHost);
-    if (e == hipSuccess && sm.dels)
-        e = hipMemcpy(del.data(), a.del, 8ull * sm.dels, hipMemcpyDeviceToHost);
+    const size_t b_off = 4ull * (T + 1), b_nbr = 4ull * sm.edges;
+    const size_t b_vtx = vertices ? sizeof(vor_rat) * sm.edges : 0, b_del = 8ull * sm.dels;
+    if (ws.h_out.ensure(2 * b_off + b_nbr + b_vtx + b_del) != hipSuccess) return VOR_E_NOMEM;
+    char *hp = (char *)ws.h_out.p;
+    const int *off = (const int *)hp;
+    const int *doff = (const int *)(hp + b_off);
+    const int *nbr = (const int *)(hp + 2 * b_off);
+    const vor_rat *vtx = (const vor_rat *)(hp + 2 * b_off + b_nbr);
+    const uint32_t *del = (const uint32_t *)(hp + 2 * b_off + b_nbr + b_vtx);
+    hipError_t e = hipMemcpyAsync((void *)off, a.cell_off, b_off, hipMemcpyDeviceToHost, ws.stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync((void *)doff, a.del_off, b_off, hipMemcpyDeviceToHost, ws.stream);
+    if (e == hipSuccess && b_nbr)
+        e = hipMemcpyAsync((void *)nbr, a.nbr, b_nbr, hipMemcpyDeviceToHost, ws.stream);
+    if (e == hipSuccess && b_vtx)
+        e = hipMemcpyAsync((void *)vtx, a.vtx, b_vtx, hipMemcpyDeviceToHost, ws.stream);
+    if (e == hipSuccess && b_del)
+        e = hipMemcpyAsync((void *)del, a.del, b_del, hipMemcpyDeviceToHost, ws.stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ws.stream);
     if (e != hipSuccess) return VOR_E_DEVICE;
     const int K = (int)descs.size();
     outs.assign(K, nullptr);
@@ -425,10 +437,10 @@ int collect_host(Workspace &ws, const PipeArgs &a, const std::vector<SetDesc> &d
         const int e0 = off[so], e1 = off[so + n];
         box->off.resize(n + 1);
         for (int t = 0; t <= n; ++t) box->off[t] = (uint32_t)(off[so + t] - e0);
-        box->nbr.assign(nbr.begin() + e0, nbr.begin() + e1);
-        if (vertices) box->vtx.assign(vtx.begin() + e0, vtx.begin() + e1);
+        box->nbr.assign(nbr + e0, nbr + e1);
+        if (vertices) box->vtx.assign(vtx + e0, vtx + e1);
         const int d0 = doff[so], d1 = doff[so + n];
-        box->del.assign(del.begin() + 2ll * d0, del.begin() + 2ll * d1);
+        box->del.assign(del + 2ll * d0, del + 2ll * d1);
         r->n = (uint32_t)n;
         r->cell_off = box->off.data();
         r->nbr = box->nbr.data();
