@@ -239,7 +239,33 @@ class Result:
 _RAT = np.dtype([("x_lo", "<u8"), ("x_hi", "<i8"), ("y_lo", "<u8"), ("y_hi", "<i8"), ("d", "<i8")])
 
 
-def _to_result(rp, device: bool = False) -> Result:
+class _Owned:
+    """Holds a library result: vor_result_free runs once neither this object nor any array that
+    views the result's memory is referenced."""
+    __slots__ = ("rp",)
+
+    def __init__(self, rp):
+        self.rp = rp
+
+    def __del__(self):
+        try:
+            lib().vor_result_free(self.rp)
+        except Exception:
+            pass
+
+
+def _view(owner, addr, dtype, count):
+    """count items of dtype at a library-owned host address, without a copy; the array keeps
+    `owner` (and so the memory) alive."""
+    dt = np.dtype(dtype)
+    buf = (C.c_char * (count * dt.itemsize)).from_address(addr)
+    buf._owner = owner
+    return np.frombuffer(buf, dtype=dt)
+
+
+def _to_result(rp, device: bool = False, owner: _Owned | None = None) -> Result:
+    """Result of a vor_result.  With `owner` (host results), the arrays view the library's memory
+    and keep it alive; without, they are copies."""
     r = rp.contents
     n = int(r.n)
     st = Stats(*[int(getattr(r.stats, f)) for f, _ in vor_stats._fields_])
@@ -257,21 +283,30 @@ def _to_result(rp, device: bool = False) -> Result:
                       np.zeros((0, 2), np.uint32), st, float(r.device_ms), int(r.status),
                       float(r.cells_ms), float(r.exact_ms), float(r.grid_ms), float(r.emit_ms),
                       int(r.graph_replayed), float(r.adaptive_ms))
-    off = np.ctypeslib.as_array(C.cast(r.cell_off, C.POINTER(C.c_uint32)), (n + 1,)).copy()
+
+    def arr(ptr, dtype, count):
+        addr = C.cast(ptr, C.c_void_p).value
+        if owner is not None:
+            return _view(owner, addr, dtype, count)
+        dt = np.dtype(dtype)
+        return np.frombuffer((C.c_char * (count * dt.itemsize)).from_address(addr), dt).copy()
+
+    off = arr(r.cell_off, np.uint32, n + 1)
     E = int(off[-1])
-    nbr = (np.ctypeslib.as_array(C.cast(r.nbr, C.POINTER(C.c_int32)), (E,)).copy()
-           if E else np.zeros(0, np.int32))
-    vtx = None
-    if r.vtx and E:
-        buf = (C.c_char * (E * _RAT.itemsize)).from_address(r.vtx)
-        vtx = np.frombuffer(buf, dtype=_RAT).copy()   # one copy out of the library's result
+    nbr = arr(r.nbr, np.int32, E) if E else np.zeros(0, np.int32)
+    vtx = arr(r.vtx, _RAT, E) if (r.vtx and E) else None
     m = int(r.m)
-    dele = (np.ctypeslib.as_array(C.cast(r.del_, C.POINTER(C.c_uint32)), (2 * m,)).copy()
-            .reshape(m, 2) if m else np.zeros((0, 2), np.uint32))
+    dele = arr(r.del_, np.uint32, 2 * m).reshape(m, 2) if m else np.zeros((0, 2), np.uint32)
     return Result(n, off, nbr, vtx, dele, st, float(r.device_ms), int(r.status),
                   float(r.cells_ms), float(r.exact_ms), float(r.grid_ms), float(r.emit_ms),
                   int(r.graph_replayed), float(r.adaptive_ms), float(r.t_submit),
                   float(r.t_admit), float(r.t_done))
+
+
+def _own_result(rp) -> Result:
+    """Result of a host vor_result whose ownership passes to Python: its arrays view the
+    library's memory, freed when the last of them (and the Result) is gone."""
+    return _to_result(rp, owner=_Owned(rp))
 
 
 def vor_result_free(rp) -> None:
@@ -288,8 +323,10 @@ def vor_compute(ctx, x, y, box, device_ptrs=False, keep_raw=False, device_result
     _check(lib().vor_compute(ctx, C.byref(s), C.byref(rp)), "vor_compute")
     if keep_raw:
         return rp
+    if not device_result:
+        return _own_result(rp)
     try:
-        return _to_result(rp, device_result)
+        return _to_result(rp, True)
     finally:
         lib().vor_result_free(rp)
 
@@ -305,10 +342,7 @@ def vor_result_to_host(ctx, res: Result) -> Result:
     r.status = res.status
     rp = C.POINTER(vor_result)()
     _check(lib().vor_result_to_host(ctx, C.byref(r), C.byref(rp)), "vor_result_to_host")
-    try:
-        out = _to_result(rp)
-    finally:
-        lib().vor_result_free(rp)
+    out = _own_result(rp)
     out.stats, out.device_ms, out.cells_ms = res.stats, res.device_ms, res.cells_ms
     out.exact_ms, out.grid_ms, out.emit_ms = res.exact_ms, res.grid_ms, res.emit_ms
     out.graph_replayed, out.adaptive_ms = res.graph_replayed, res.adaptive_ms
@@ -351,8 +385,7 @@ def vor_compute_batch(ctx, sets):
     res = []
     for o in outs:
         if o:
-            res.append(_to_result(o))
-            lib().vor_result_free(o)
+            res.append(_own_result(o))
         else:
             res.append(None)
     return rc, res
@@ -370,10 +403,7 @@ def vor_poll(ctx, ticket: int):
     rp = C.POINTER(vor_result)()
     rc = lib().vor_poll(ctx, C.c_uint64(ticket), C.byref(rp))
     if rc == VOR_OK:
-        try:
-            return rc, _to_result(rp)
-        finally:
-            lib().vor_result_free(rp)
+        return rc, _own_result(rp)
     return rc, None
 
 

@@ -75,9 +75,27 @@ struct HostBuf {   // pinned staging
 };
 
 
+// The host results of one run: the output arrays copied straight from HBM into one block that
+// every set's result points into.  Each result holds a reference; a block whose only holder is
+// its workspace's cache is free and the next run writes into it again.
+struct OutBlock {
+    void *p = nullptr;
+    size_t cap = 0;
+    bool pinned = false;
+    ~OutBlock() {
+        if (!p) return;
+        if (pinned)
+            (void)hipHostFree(p);
+        else
+            std::free(p);
+    }
+};
+constexpr int OUT_CACHE = 2;   // pinned blocks kept per workspace (one held, one filling)
+
 struct Workspace {
     DevBuf b[B_COUNT];
-    HostBuf h_in, h_small, h_out;   // pinned staging: inputs, summary, a run's outputs
+    HostBuf h_in, h_small;          // pinned staging: inputs, summary
+    std::shared_ptr<OutBlock> out_cache[OUT_CACHE];
     std::vector<SideRel> sides_h;   // side table of the sets being launched
     std::vector<char> up_cache;     // set descriptors, side table, set offsets last uploaded
     DevBuf lcx, lcy, lqx, lqy, lkeys, lcnt, lflag;   // Lloyd iterations
@@ -116,7 +134,7 @@ struct Workspace {
         drop_graph();
         for (auto &x : b) x.release();
         h_in.release();
-        h_out.release();
+        for (auto &o : out_cache) o.reset();
         up_cache.clear();
     }
     void destroy() {
@@ -126,7 +144,7 @@ struct Workspace {
         for (DevBuf *x : {&lcx, &lcy, &lqx, &lqy, &lkeys, &lcnt, &lflag}) x->release();
         h_in.release();
         h_small.release();
-        h_out.release();
+        for (auto &o : out_cache) o.reset();
         h_lloyd.release();
         if (ev0) (void)hipEventDestroy(ev0);
         if (ev1) (void)hipEventDestroy(ev1);
@@ -146,6 +164,7 @@ struct ResultBox {   // vor_result plus the storage it points to
     std::vector<int32_t> nbr;
     std::vector<vor_rat> vtx;
     std::vector<uint32_t> del;
+    std::shared_ptr<OutBlock> block;   // a run's shared host block (instead of the vectors)
 };
 
 vor_result *new_result(ResultBox *&box) {
@@ -401,21 +420,63 @@ Summary read_summary(Workspace &ws) {
 }
 
 
-// Copy the results of every set back to host ResultBoxes (after the stream is idle).
+// A block of at least `bytes` for a run's host results: a free cached pinned block, else a new
+// pinned block in a free or empty cache slot, else (every cached block still held by results,
+// or pinned memory short) a pageable block of this run's own.
+std::shared_ptr<OutBlock> take_out_block(Workspace &ws, size_t bytes) {
+    try {
+        for (auto &o : ws.out_cache)
+            if (o && o.use_count() == 1 && o->cap >= bytes) {
+                // the last holder's release happened before this read: its reads are done
+                std::atomic_thread_fence(std::memory_order_acquire);
+                return o;
+            }
+        for (auto &o : ws.out_cache) {
+            if (o && o.use_count() != 1) continue;
+            o.reset();
+            auto nb = std::make_shared<OutBlock>();
+            const size_t want = bytes + bytes / 8;
+            if (hipHostMalloc(&nb->p, want, hipHostMallocDefault) != hipSuccess) {
+                (void)hipGetLastError();
+                nb->p = nullptr;
+                break;
+            }
+            nb->cap = want;
+            nb->pinned = true;
+            o = nb;
+            return o;
+        }
+        auto nb = std::make_shared<OutBlock>();
+        nb->p = std::malloc(bytes);
+        if (!nb->p) return nullptr;
+        nb->cap = bytes;
+        return nb;
+    } catch (...) {
+        return nullptr;
+    }
+}
+
+// Copy the results of every set back to the host (after the stream is idle): the run's output
+// arrays by DMA into one host block, each set's offsets rebased to its first entry, and every
+// set's result pointing at its slices of the block.
 int collect_host(Workspace &ws, const PipeArgs &a, const std::vector<SetDesc> &descs,
                  const Summary &sm, bool vertices, std::vector<vor_result *> &outs) {
-    // the run's output arrays in one pinned staging buffer (direct DMA, reused across calls),
-    // then each set's slices into its own result
     const long long T = a.total;
+    const int K = (int)descs.size();
+    auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
     const size_t b_off = 4ull * (T + 1), b_nbr = 4ull * sm.edges;
     const size_t b_vtx = vertices ? sizeof(vor_rat) * sm.edges : 0, b_del = 8ull * sm.dels;
-    if (ws.h_out.ensure(2 * b_off + b_nbr + b_vtx + b_del) != hipSuccess) return VOR_E_NOMEM;
-    char *hp = (char *)ws.h_out.p;
+    const size_t o_doff = up(b_off), o_nbr = o_doff + up(b_off), o_vtx = o_nbr + up(b_nbr);
+    const size_t o_del = o_vtx + up(b_vtx), o_rel = o_del + up(b_del);
+    std::shared_ptr<OutBlock> blk = take_out_block(ws, o_rel + 4ull * (T + K));
+    if (!blk) return VOR_E_NOMEM;
+    char *hp = (char *)blk->p;
     const int *off = (const int *)hp;
-    const int *doff = (const int *)(hp + b_off);
-    const int *nbr = (const int *)(hp + 2 * b_off);
-    const vor_rat *vtx = (const vor_rat *)(hp + 2 * b_off + b_nbr);
-    const uint32_t *del = (const uint32_t *)(hp + 2 * b_off + b_nbr + b_vtx);
+    const int *doff = (const int *)(hp + o_doff);
+    const int32_t *nbr = (const int32_t *)(hp + o_nbr);
+    const vor_rat *vtx = (const vor_rat *)(hp + o_vtx);
+    const uint32_t *del = (const uint32_t *)(hp + o_del);
+    uint32_t *rel = (uint32_t *)(hp + o_rel);   // set i's n+1 offsets at site_off + i
     hipError_t e = hipMemcpyAsync((void *)off, a.cell_off, b_off, hipMemcpyDeviceToHost, ws.stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync((void *)doff, a.del_off, b_off, hipMemcpyDeviceToHost, ws.stream);
@@ -427,26 +488,49 @@ int collect_host(Workspace &ws, const PipeArgs &a, const std::vector<SetDesc> &d
         e = hipMemcpyAsync((void *)del, a.del, b_del, hipMemcpyDeviceToHost, ws.stream);
     if (e == hipSuccess) e = hipStreamSynchronize(ws.stream);
     if (e != hipSuccess) return VOR_E_DEVICE;
-    const int K = (int)descs.size();
+    // rebasing: pieces of at most 2^20 offsets, spread over a few threads for large runs
+    constexpr int PIECE = 1 << 20;
+    std::vector<std::pair<int, int>> pieces;   // (set, first offset)
+    for (int i = 0; i < K; ++i)
+        for (int t = 0; t <= descs[i].n; t += PIECE) pieces.emplace_back(i, t);
+    std::atomic<size_t> next{0};
+    auto rebase = [&] {
+        for (size_t j; (j = next.fetch_add(1)) < pieces.size();) {
+            const int i = pieces[j].first, t0 = pieces[j].second;
+            const int so = descs[i].site_off, n = descs[i].n, e0 = off[so];
+            const int t1 = std::min(n + 1, t0 + PIECE);
+            uint32_t *d = rel + so + i;
+            for (int t = t0; t < t1; ++t) d[t] = (uint32_t)(off[so + t] - e0);
+        }
+    };
+    const int nt = T + K > (4ll << 20)
+                       ? (int)std::min(8u, std::max(1u, std::thread::hardware_concurrency())) : 1;
+    std::vector<std::thread> th;
+    try {
+        for (int k = 1; k < nt; ++k) th.emplace_back(rebase);
+    } catch (...) {
+    }
+    rebase();
+    for (auto &x : th) x.join();
     outs.assign(K, nullptr);
     for (int i = 0; i < K; ++i) {
         ResultBox *box;
         vor_result *r = new_result(box);
-        if (!r) return VOR_E_NOMEM;
+        if (!r) {
+            for (auto &o : outs) vor_result_free(o);
+            outs.clear();
+            return VOR_E_NOMEM;
+        }
+        box->block = blk;
         const int so = descs[i].site_off, n = descs[i].n;
-        const int e0 = off[so], e1 = off[so + n];
-        box->off.resize(n + 1);
-        for (int t = 0; t <= n; ++t) box->off[t] = (uint32_t)(off[so + t] - e0);
-        box->nbr.assign(nbr + e0, nbr + e1);
-        if (vertices) box->vtx.assign(vtx + e0, vtx + e1);
+        const int e0 = off[so];
         const int d0 = doff[so], d1 = doff[so + n];
-        box->del.assign(del + 2ll * d0, del + 2ll * d1);
         r->n = (uint32_t)n;
-        r->cell_off = box->off.data();
-        r->nbr = box->nbr.data();
-        r->vtx = vertices ? box->vtx.data() : nullptr;
+        r->cell_off = rel + so + i;
+        r->nbr = nbr + e0;
+        r->vtx = vertices ? vtx + e0 : nullptr;
         r->m = (uint64_t)(d1 - d0);
-        r->del = box->del.data();
+        r->del = del + 2ll * d0;
         fill_stats(r->stats, sm.stats);
         r->device_ms = sm.ms;
         r->cells_ms = sm.cells_ms;
