@@ -3,6 +3,7 @@ the HIP library."""
 from __future__ import annotations
 
 import ctypes as C
+import gc
 import os
 from dataclasses import dataclass
 
@@ -181,7 +182,7 @@ def _make_set(x, y, box, device_ptrs=False, region=None):
                    0, rn, rx, ry), keep
 
 
-@dataclass
+@dataclass(frozen=True)
 class Stats:
     rays: int
     nodes: int
@@ -263,12 +264,25 @@ def _view(owner, addr, dtype, count):
     return np.frombuffer(buf, dtype=dt)
 
 
-def _to_result(rp, device: bool = False, owner: _Owned | None = None) -> Result:
+def _stats(raw: vor_stats, cache: dict | None = None) -> Stats:
+    """Stats of a vor_stats; `cache` shares one object among the results of a batch, which carry
+    the run's counters alike."""
+    if cache is None:
+        return Stats(*[int(getattr(raw, f)) for f, _ in vor_stats._fields_])
+    key = bytes(raw)
+    st = cache.get(key)
+    if st is None:
+        st = cache[key] = Stats(*[int(getattr(raw, f)) for f, _ in vor_stats._fields_])
+    return st
+
+
+def _to_result(rp, device: bool = False, owner: _Owned | None = None,
+               stats_cache: dict | None = None) -> Result:
     """Result of a vor_result.  With `owner` (host results), the arrays view the library's memory
     and keep it alive; without, they are copies."""
     r = rp.contents
     n = int(r.n)
-    st = Stats(*[int(getattr(r.stats, f)) for f, _ in vor_stats._fields_])
+    st = _stats(r.stats, stats_cache)
     if device:
         # arrays live in device memory: hand back their addresses, never dereference them here
         res = Result(n, np.zeros(0, np.uint32), np.zeros(0, np.int32), None,
@@ -284,8 +298,7 @@ def _to_result(rp, device: bool = False, owner: _Owned | None = None) -> Result:
                       float(r.cells_ms), float(r.exact_ms), float(r.grid_ms), float(r.emit_ms),
                       int(r.graph_replayed), float(r.adaptive_ms))
 
-    def arr(ptr, dtype, count):
-        addr = C.cast(ptr, C.c_void_p).value
+    def arr(addr, dtype, count):
         if owner is not None:
             return _view(owner, addr, dtype, count)
         dt = np.dtype(dtype)
@@ -303,10 +316,10 @@ def _to_result(rp, device: bool = False, owner: _Owned | None = None) -> Result:
                   float(r.t_admit), float(r.t_done))
 
 
-def _own_result(rp) -> Result:
+def _own_result(rp, stats_cache: dict | None = None) -> Result:
     """Result of a host vor_result whose ownership passes to Python: its arrays view the
     library's memory, freed when the last of them (and the Result) is gone."""
-    return _to_result(rp, owner=_Owned(rp))
+    return _to_result(rp, owner=_Owned(rp), stats_cache=stats_cache)
 
 
 def vor_result_free(rp) -> None:
@@ -382,12 +395,17 @@ def vor_compute_batch(ctx, sets):
     rc = lib().vor_compute_batch(ctx, arr, k, outs)
     if rc < 0 and not any(bool(o) for o in outs):
         raise VorError(rc, "vor_compute_batch")
-    res = []
-    for o in outs:
-        if o:
-            res.append(_own_result(o))
-        else:
-            res.append(None)
+    res, cache = [], {}
+    # thousands of small objects at once: the cyclic collector's passes over them (none of
+    # them is garbage yet) would cost more than the conversion itself
+    was = gc.isenabled()
+    gc.disable()
+    try:
+        for o in outs:
+            res.append(_own_result(o, cache) if o else None)
+    finally:
+        if was:
+            gc.enable()
     return rc, res
 
 
