@@ -756,12 +756,13 @@ __global__ __launch_bounds__(64) void k_cells_exact(
     const int *__restrict__ queue, const int *__restrict__ qcount, int *__restrict__ queue2,
     int *__restrict__ qcount2, int *__restrict__ wbuf, int dcap,
     unsigned long long *__restrict__ stats, const unsigned char *__restrict__ bflag,
-    int *__restrict__ status) {
+    int *__restrict__ status, int skip_upto) {
     __shared__ unsigned long long sh[SL_COUNT];
     __shared__ int larea[LCAP > 0 ? 2 * LCAP : 1];
     if (*status & (ST_DOMAIN | ST_DUP)) return;
     const int nq = *qcount;
     if ((int)blockIdx.x >= nq) return;   // no cell for this worker
+    if (nq <= skip_upto) return;         // the workgroup-per-cell pass took them
     if (threadIdx.x < SL_COUNT) sh[threadIdx.x] = 0;
     __syncthreads();
     const int lane = threadIdx.x;
@@ -818,40 +819,57 @@ __global__ __launch_bounds__(64) void k_cells_exact(
     reduce_stats(K, edges, 0, 0, sh, stats);
 }
 
-// Deep cells (more lines than the exact pass holds per worker), with the subwedges of one cell
-// spread over the waves of a workgroup (the parallel case of Appendix 2: several processing
-// units share one cell's projector).  The cell's corners form a counter-clockwise linked list
-// (line of each corner, next corner); a subedge is a corner and its successor.  Rounds: every
-// pending subedge is resolved by one wave (its 64 lanes split the candidate scans), a new
-// corner is spliced in between its two corners and both halves become pending in the next
-// round; a barrier ends the round.  Two waves never touch the same corner's successor link,
-// since each owns the subedge that starts there.  After the last round one lane walks the list
-// and writes the corners' lines with repeats removed: the same cyclic list the depth-first walk
-// yields (the set of prime subedges does not depend on the order they are resolved in).
-// The work area of a block: corner lines, successor links, two frontier lists (WIDE_CAP each).
-template <int MODE>
-__global__ __launch_bounds__(64 * WIDE_WAVES) void k_cells_wide(
+// Cells with the subwedges of one cell spread over the waves of a workgroup (the parallel case
+// of Appendix 2: several processing units share one cell's projector).  The cell's corners form
+// a counter-clockwise linked list (line of each corner, next corner); a subedge is a corner and
+// its successor.  Rounds: every pending subedge is resolved by one wave (its 64 lanes split the
+// candidate scans), a new corner is spliced in between its two corners and both halves become
+// pending in the next round; a barrier ends the round.  Two waves never touch the same corner's
+// successor link, since each owns the subedge that starts there.  After the last round one lane
+// walks the list and writes the corners' lines with repeats removed: the same cyclic list the
+// depth-first walk yields (the set of prime subedges does not depend on the order they are
+// resolved in).  A cell then takes a few rounds instead of one ray after another, which is what
+// bounds a pass over few cells.
+// CAP > 0: the deferred cells of the filtered passes (queue), lists in LDS (CAP corners each);
+// a cell with more corners goes to queue2.  CAP == 0: the deep cells (queue2), lists in the
+// block's area of wbuf (WIDE_CAP corners each: corner lines, successor links, two frontiers).
+// The deferred-cell pass runs only when it has at most WIDE_QMAX cells (a pass over few cells
+// is bound by the slowest cell); the one-wave-per-cell pass takes larger queues, where the
+// waves that idle in the early rounds would cost more than the shorter chain of rays saves.
+constexpr int WIDE_QMAX = 4096;     // deferred cells up to which the workgroup-per-cell pass runs
+constexpr int WIDE_LCAP = 256;      // corners of a deferred cell in that pass (LDS lists)
+constexpr int WIDE_LWAVES = 4;      // waves of its workgroups
+constexpr int WIDE_LBLOCKS = 2048;  // its workgroups
+constexpr int ERR_SPILL = 1 << 30;  // a deferred cell with more corners than the LDS lists hold
+
+template <int MODE, int CAP, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void k_cells_wide(
     const SetDesc *__restrict__ sets, int nsets, const int *__restrict__ set_off,
     const SideRel *__restrict__ sides,
     const float2 *__restrict__ sxy, const int *__restrict__ sid, const int *__restrict__ bstart,
     int total, int *__restrict__ ocnt, int *__restrict__ olines, int *__restrict__ dcnt,
     int *__restrict__ ovf, int *__restrict__ pool, int *__restrict__ poolcnt, long long poolcap,
     const int *__restrict__ queue, const int *__restrict__ qcount, int *__restrict__ wbuf,
+    int *__restrict__ queue2, int *__restrict__ qcount2, const unsigned char *__restrict__ bflag,
     unsigned long long *__restrict__ stats, int *__restrict__ status) {
+    constexpr int WCAP = CAP > 0 ? CAP : WIDE_CAP;
     __shared__ unsigned long long sh[SL_COUNT];
     __shared__ int fcount[2], ncorner, err, s_m, s_up, s_off;
+    __shared__ int lists[CAP > 0 ? 4 * CAP : 1];
     if (*status & (ST_DOMAIN | ST_DUP)) return;
     const int nq = *qcount;
     if ((int)blockIdx.x >= nq) return;   // no cell for this worker
+    if (CAP > 0 && nq > WIDE_QMAX) return;   // the one-wave-per-cell pass takes them
     if (threadIdx.x < SL_COUNT) sh[threadIdx.x] = 0;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    int *cline = wbuf + (size_t)blockIdx.x * 4 * WIDE_CAP;
-    int *nxt = cline + WIDE_CAP;
-    int *F[2] = {nxt + WIDE_CAP, nxt + 2 * WIDE_CAP};
+    int *cline = CAP > 0 ? lists : wbuf + (size_t)blockIdx.x * 4 * WIDE_CAP;
+    int *nxt = cline + WCAP;
+    int *F[2] = {nxt + WCAP, nxt + 2 * WCAP};
     Counters K{};
     uint32_t edges = 0;
     for (int qi = blockIdx.x; qi < nq; qi += gridDim.x) {
         const int pos = queue[qi];
+        if (CAP > 0 && bflag[pos]) continue;   // the boundary pass takes it (uniform: one pos)
         const SetDesc S = sets[find_set(set_off, nsets, pos)];
         const Cell C = make_cell(S, sxy[pos], sides);
         const int k = sid[pos];
@@ -876,12 +894,12 @@ __global__ __launch_bounds__(64 * WIDE_WAVES) void k_cells_wide(
                 F[0][wave] = wave;
             }
         }
-        __threadfence();
+        __threadfence_block();   // the lists are shared by this workgroup's waves only
         __syncthreads();
         int cur = 0;
         while (fcount[cur] > 0 && !err) {
             const int nf = fcount[cur];
-            for (int f = wave; f < nf; f += WIDE_WAVES) {
+            for (int f = wave; f < nf; f += WAVES) {
                 const int i = F[cur][f];
                 const int j = nxt[i];
                 const Line L1 = make_line(C, sxy, cline[i]), L2 = make_line(C, sxy, cline[j]);
@@ -902,8 +920,9 @@ __global__ __launch_bounds__(64 * WIDE_WAVES) void k_cells_wide(
                 int nk = 0;
                 if (lane == 0) nk = atomicAdd(&ncorner, 1);
                 nk = __shfl(nk, 0, 64);
-                if (nk >= WIDE_CAP || r < 0) {
-                    if (lane == 0) atomicOr(&err, nk >= WIDE_CAP ? ST_CAPACITY : ST_INTERNAL);
+                if (nk >= WCAP || r < 0) {
+                    if (lane == 0)
+                        atomicOr(&err, r < 0 ? ST_INTERNAL : CAP > 0 ? ERR_SPILL : ST_CAPACITY);
                     continue;
                 }
                 if (lane == 0) {
@@ -915,14 +934,17 @@ __global__ __launch_bounds__(64 * WIDE_WAVES) void k_cells_wide(
                     F[cur ^ 1][at + 1] = nk;
                 }
             }
-            __threadfence();
+            __threadfence_block();
             __syncthreads();
             if (threadIdx.x == 0) fcount[cur] = 0;
             cur ^= 1;
             __syncthreads();
         }
         if (err) {
-            if (threadIdx.x == 0) atomicOr(status, err);
+            if (threadIdx.x == 0) {
+                if (err & ~ERR_SPILL) atomicOr(status, err & ~ERR_SPILL);
+                else queue2[atomicAdd(qcount2, 1)] = pos;   // to the deep pass
+            }
             continue;   // uniform across the block (err is read after the last barrier)
         }
         // the cyclic list of distinct lines, counter-clockwise from corner 0 (into F[0])
@@ -954,7 +976,7 @@ __global__ __launch_bounds__(64 * WIDE_WAVES) void k_cells_wide(
             s_up = up;
             s_off = off;
         }
-        __threadfence();
+        __threadfence_block();
         __syncthreads();
         const int m = s_m, off = s_off;
         if (m < 0) continue;
@@ -1516,15 +1538,23 @@ static void launch_exact(const PipeArgs &a, hipStream_t st) {
     k_cells_bnd<MODE><<<BND_BLOCKS, 64, 0, st>>>(
         a.sets, a.nsets, a.set_off, a.sides, a.sxy, a.sid, a.bstart, a.total, a.ocnt, a.olines,
         a.dcnt, a.ovf, a.pool, a.poolcnt(), a.poolcap, a.queue5, a.qcount5(), a.stats, a.status_rw());
+    // the deferred cells: few of them (the usual case after the filtered passes) a workgroup
+    // each, the subwedges of a cell spread over its waves; else one wave each
+    if (!(a.exact_only || a.coop_all))
+        k_cells_wide<MODE, WIDE_LCAP, WIDE_LWAVES><<<WIDE_LBLOCKS, 64 * WIDE_LWAVES, 0, st>>>(
+            a.sets, a.nsets, a.set_off, a.sides, a.sxy, a.sid, a.bstart, a.total, a.ocnt,
+            a.olines, a.dcnt, a.ovf, a.pool, a.poolcnt(), a.poolcap, a.queue, a.qcount(), nullptr,
+            a.queue2, a.qcount2(), a.bflag, a.stats, a.status_rw());
     k_cells_exact<MODE, DCAP1><<<a.exact_blocks, 64, 0, st>>>(
         a.sets, a.nsets, a.set_off, a.sides, a.sxy, a.sid, a.bstart, a.total, a.ocnt, a.olines,
         a.dcnt, a.ovf, a.pool, a.poolcnt(), a.poolcap, a.queue, a.qcount(), a.queue2,
-        a.qcount2(), a.wbuf, DCAP1, a.stats, a.bflag, a.status_rw());
+        a.qcount2(), a.wbuf, DCAP1, a.stats, a.bflag, a.status_rw(),
+        a.exact_only || a.coop_all ? 0 : WIDE_QMAX);
     // deep cells: few workgroups, the subwedges of each cell spread over their waves
-    k_cells_wide<MODE><<<DEEP_BLOCKS, 64 * WIDE_WAVES, 0, st>>>(
+    k_cells_wide<MODE, 0, WIDE_WAVES><<<DEEP_BLOCKS, 64 * WIDE_WAVES, 0, st>>>(
         a.sets, a.nsets, a.set_off, a.sides, a.sxy, a.sid, a.bstart, a.total, a.ocnt, a.olines,
-        a.dcnt, a.ovf, a.pool, a.poolcnt(), a.poolcap, a.queue2, a.qcount2(), a.wbuf2, a.stats,
-        a.status_rw());
+        a.dcnt, a.ovf, a.pool, a.poolcnt(), a.poolcap, a.queue2, a.qcount2(), a.wbuf2, nullptr,
+        nullptr, nullptr, a.stats, a.status_rw());
 }
 
 void launch_stage(const PipeArgs &a, hipStream_t st, int stage) {
