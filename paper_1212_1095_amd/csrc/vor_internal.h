@@ -47,7 +47,8 @@ struct PipeArgs {
     int *tref;              // [gtot + 1] refined grid buckets before each bucket
     float2 *sxy;            // sorted coordinates [total]
     int *sid;               // local id of each sorted site [total]
-    int *ocnt;              // [total] lines of each cell, by site id (-1: not done)
+    int *ocnt;              // [total] lines of each cell, by site id (-1: not done); before the
+                            // cell passes, the counting sort's slot of each site
     int *olines;            // [KOUT * total] line t of the cell at sorted position pos at
                             // t * total + pos: the neighbour's sorted position or a side code
     int *ovf;               // [total] by sorted position: pool offset of a cell with more than

@@ -59,7 +59,8 @@ __global__ void k_clear(int *__restrict__ p, long long n, int *__restrict__ smal
 __global__ void k_prep(const SetDesc *__restrict__ sets, int nsets, const int *__restrict__ set_off,
                        const SideRel *__restrict__ sides, const int *__restrict__ in_x,
                        const int *__restrict__ in_y, int total, int2 *__restrict__ xyid,
-                       int *__restrict__ key, int *__restrict__ bcnt, int *__restrict__ status) {
+                       int *__restrict__ key, int *__restrict__ bcnt, int *__restrict__ rank,
+                       int *__restrict__ status) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= total) return;
     const SetDesc S = sets[find_set(set_off, nsets, i)];
@@ -84,14 +85,15 @@ __global__ void k_prep(const SetDesc *__restrict__ sets, int nsets, const int *_
     const int bx = min((int)rx / S.s, S.gx - 1), by = min((int)ry / S.s, S.gy - 1);
     const int b = S.bucket_off + by * S.gx + bx;
     key[i] = b | (onb ? KEY_BOUNDARY : 0);   // bucket ids stay below 2^30
-    atomicAdd(&bcnt[b], 1);
+    rank[i] = atomicAdd(&bcnt[b], 1);          // the site's slot among its bucket's sites
 }
 
-// Counting-sort scatter.  bcnt counts down to zero again, ready for the next call.  Sites on
-// the boundary of X are flagged by sorted position and listed for the boundary pass.
+// Counting-sort scatter: a site goes to its bucket's start plus the slot its count gave it (no
+// atomics here).  Sites on the boundary of X are flagged by sorted position and listed for the
+// boundary pass.
 __global__ void k_scatter(const SetDesc *__restrict__ sets, int nsets, const int *__restrict__ set_off,
                           int total, const int2 *__restrict__ xyid, const int *__restrict__ key,
-                          const int *__restrict__ bstart, int *__restrict__ bcnt,
+                          const int *__restrict__ bstart, const int *__restrict__ rank,
                           float2 *__restrict__ sxy, int *__restrict__ sid,
                           unsigned char *__restrict__ bflag, int *__restrict__ queue5,
                           int *__restrict__ qcount5) {
@@ -99,7 +101,7 @@ __global__ void k_scatter(const SetDesc *__restrict__ sets, int nsets, const int
     if (i >= total) return;
     const int kb = key[i];
     const int b = kb & ~KEY_BOUNDARY;
-    const int pos = bstart[b] + atomicSub(&bcnt[b], 1) - 1;
+    const int pos = bstart[b] + rank[i];
     const int2 r = xyid[i];
     sxy[pos] = make_float2((float)r.x, (float)r.y);
     sid[pos] = i - set_off[find_set(set_off, nsets, i)];
@@ -1567,11 +1569,14 @@ void launch_stage(const PipeArgs &a, hipStream_t st, int stage) {
         k_clear<<<nblk(big, 256), 256, 0, st>>>(a.bcnt, n, a.small, SMALL_INTS, a.stats,
                                                 (unsigned *)a.bflag, nf);
         // grid build (Method 11.5), then adaptive refinement of crowded buckets
+        // the slots of the counting sort are kept by input index in the per-cell line counts,
+        // which the cell passes write later
         k_prep<<<nblk(T, 256), 256, 0, st>>>(a.sets, a.nsets, a.set_off, a.sides, a.in_x,
-                                              a.in_y, T, a.xyid, a.key, a.bcnt, a.status());
+                                              a.in_y, T, a.xyid, a.key, a.bcnt, a.ocnt,
+                                              a.status());
         launch_scan(a.bcnt, a.gtot, a.bstart, a.scan_tmp, a.status(), 0, st);
         k_scatter<<<nblk(T, 256), 256, 0, st>>>(a.sets, a.nsets, a.set_off, T, a.xyid, a.key,
-                                                 a.bstart, a.bcnt, a.sxy, a.sid, a.bflag,
+                                                 a.bstart, a.ocnt, a.sxy, a.sid, a.bflag,
                                                  a.queue5, a.qcount5());
         k_tree_mark0<<<nblk(a.gtot + 1, 256), 256, 0, st>>>(a.sets, a.nsets, a.gtot, a.bstart,
                                                             a.tchild, a.bcnt, a.nodes, a.ncap,
