@@ -46,7 +46,8 @@ def log(*a):
 
 
 KERNEL_SOURCES = ("paper_1212_1095_amd/csrc/vor_cell.hpp", "paper_1212_1095_amd/csrc/vor_device.hpp",
-                  "paper_1212_1095_amd/csrc/vor_kernels.hip", "paper_1212_1095_amd/csrc/vor_internal.h")
+                  "paper_1212_1095_amd/csrc/vor_kernels.hip", "paper_1212_1095_amd/csrc/vor_internal.h",
+                  "paper_1212_1095_amd/csrc/vor_local.hpp", "paper_1212_1095_amd/csrc/vor_tree.hpp")
 
 
 def kernel_source_hash():
