@@ -449,13 +449,13 @@ def main():
     log(f"timed output vs oracle digests: {exact_cells} cells bit-exact, {exact_err or 'ok'}")
 
     # roofline of the dominant kernel: algorithmic flops per launch / mean launch duration.
-    # The filtered grid pass runs as one kernel, the adaptive (coordinate-rectangle) pass as two
-    # (list scans only, then the full scanner for the cells the first run hands on); the
-    # evaluations of the exact pass (a few hundred cells) count with the grid pass.
+    # The filtered grid pass runs as one kernel, the adaptive pass as two (the local grids,
+    # then the tree scans for the cells they hand on); the evaluations of the exact pass (a few
+    # hundred cells) count with the grid pass.
     if float(np.mean(adapt_ms)) > float(np.mean(cells_ms)):
         evals = st.adaptive_evals
         kern_s = float(np.mean(adapt_ms)) / 1000.0
-        kname = "vor::k_cells_tree<128, true> + vor::k_cells_tree<128, false>"
+        kname = "vor::k_cells_local + vor::k_cells_tree<128>"
     else:
         evals = st.evals - st.adaptive_evals
         kern_s = float(np.mean(cells_ms)) / 1000.0
