@@ -838,7 +838,7 @@ __global__ __launch_bounds__(64) void k_cells_exact(
 // The deferred-cell pass runs only when it has at most WIDE_QMAX cells (a pass over few cells
 // is bound by the slowest cell); the one-wave-per-cell pass takes larger queues, where the
 // waves that idle in the early rounds would cost more than the shorter chain of rays saves.
-constexpr int WIDE_QMAX = 4096;     // deferred cells up to which the workgroup-per-cell pass runs
+constexpr int WIDE_QMAX = 16384;    // deferred cells up to which the workgroup-per-cell pass runs
 constexpr int WIDE_LCAP = 256;      // corners of a deferred cell in that pass (LDS lists)
 constexpr int WIDE_LWAVES = 4;      // waves of its workgroups
 constexpr int WIDE_LBLOCKS = 2048;  // its workgroups

@@ -28,7 +28,7 @@ constexpr int TFRAMES = TREE_LEVELS + 1;
 constexpr int TREE_LIST = 48;     // cached candidate positions per cell (adaptive pass)
 constexpr int TREE_LIST_FILL = 20;// the cached region grows until it holds this many sites
 constexpr int TREE_PROBES = 6;    // leaves probed along the ray before a region pass
-constexpr int TREE_BUDGET = 1024; // sub-buckets + evaluations a lane spends on one cell before
+constexpr int TREE_BUDGET = 640;  // sub-buckets + evaluations a lane spends on one cell before
                                   // handing it to the one-wave-per-cell pass
 constexpr int TREE_BATCH = 4;     // candidate loads issued together (one lane walks one cell, so
                                   // the loads of a leaf or of the list overlap instead of queueing)
