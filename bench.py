@@ -151,9 +151,9 @@ def bench_batched(vor, sets, name, steps=3, flags=0, kernel_roofline=False):
     table = batch_size_table()
     with vor.Context(flags=flags) as ctx:
         ctx.size_tuning(table)
-        # warm-up and graph capture; two calls, the first one's results held meanwhile, so that
-        # the library's two cached host blocks exist (the steady state of a caller that keeps
-        # one batch's results while the next one runs)
+        # warm-up and graph capture (a shape's second call captures it); two calls, the first
+        # one's results held meanwhile, so that the library's pinned pool holds the two host
+        # blocks of a caller that keeps one batch's results while the next one runs
         held = ctx.compute_batch(args)
         ctx.compute_batch(args)
         del held
@@ -246,6 +246,7 @@ def bench_served(vor, count=200, seed=5, hi=1 << 20):
                      "source": "autotuner batch table (tuning.json)" if table else "library default"}
     with vor.Context() as ctx:
         ctx.size_tuning(table)
+        run(None)   # warm-up: the request loop's workspaces and the pinned result pool
         _, fails, cap_s, kept = run(None)
         rate = count / cap_s
         out["capacity_req_per_s"] = round(rate, 1)

@@ -172,7 +172,8 @@ int vor_compute(vor_ctx *ctx, const vor_set *set, vor_result **out);
 
 /* Blocking: k independent point sets in one launch per pipeline stage (the cells of every set
  * of the batch in each kernel's grid, so that the cells of all sets run in parallel as
- * Theorem 9.1(d) allows), the whole pipeline captured once as a HIP graph and replayed.
+ * Theorem 9.1(d) allows); a shape's first call launches kernel by kernel, and from its second
+ * call on the pipeline runs as a captured HIP graph, replayed while the shape repeats.
  * outs[i] receives set i's result (its status field carries a per-set error: a set with an
  * input error is found by running the sets one by one, and the others still succeed).  The
  * sets together hold at most 2^27 sites (VOR_E_NOMEM beyond, before any device work; split

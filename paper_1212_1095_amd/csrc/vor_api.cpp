@@ -75,27 +75,76 @@ struct HostBuf {   // pinned staging
 };
 
 
-// The host results of one run: the output arrays copied straight from HBM into one block that
-// every set's result points into.  Each result holds a reference; a block whose only holder is
-// its workspace's cache is free and the next run writes into it again.
+// Pinned host memory for results, kept for reuse: a block that its results no longer need goes
+// back to the free list (up to PINNED_CACHE bytes, or twice the largest block asked for, stay
+// cached: a caller that holds one run's results while the next runs needs two such blocks), so
+// that once the pool has grown to what the caller holds at a time, runs neither pin new memory
+// nor wait on its release.
+constexpr size_t PINNED_CACHE = 8ull << 30;
+constexpr size_t PINNED_GRAIN = 2ull << 20;
+struct PinnedPool {
+    std::mutex mu;
+    std::multimap<size_t, void *> free;   // size -> block
+    size_t cached = 0;
+    size_t biggest = 0;
+    ~PinnedPool() {
+        for (auto &kv : free) (void)hipHostFree(kv.second);
+    }
+    // A block of at least `bytes` (its size in `got`): a cached one at most half as large again,
+    // else a new one; nullptr when pinned memory runs short.
+    void *get(size_t bytes, size_t &got) {
+        const size_t want = (std::max<size_t>(bytes, 1) + PINNED_GRAIN - 1) / PINNED_GRAIN * PINNED_GRAIN;
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            biggest = std::max(biggest, want);
+            auto it = free.lower_bound(want);
+            if (it != free.end() && it->first <= want + want / 2) {
+                void *p = it->second;
+                got = it->first;
+                cached -= got;
+                free.erase(it);
+                return p;
+            }
+        }
+        void *p = nullptr;
+        if (hipHostMalloc(&p, want, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        got = want;
+        return p;
+    }
+    void put(void *p, size_t size) {
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            if (cached + size <= std::max(PINNED_CACHE, 2 * biggest)) {
+                free.emplace(size, p);
+                cached += size;
+                return;
+            }
+        }
+        (void)hipHostFree(p);
+    }
+};
+
+// Host memory that results point into: a pool block (pinned) or, when pinned memory runs
+// short, a pageable one.  Every result of the block holds a reference.
 struct OutBlock {
     void *p = nullptr;
     size_t cap = 0;
-    bool pinned = false;
+    std::shared_ptr<PinnedPool> pool;   // null: malloc'd
     ~OutBlock() {
         if (!p) return;
-        if (pinned)
-            (void)hipHostFree(p);
+        if (pool)
+            pool->put(p, cap);
         else
             std::free(p);
     }
 };
-constexpr int OUT_CACHE = 2;   // pinned blocks kept per workspace (one held, one filling)
 
 struct Workspace {
     DevBuf b[B_COUNT];
     HostBuf h_in, h_small;          // pinned staging: inputs, summary
-    std::shared_ptr<OutBlock> out_cache[OUT_CACHE];
     std::vector<SideRel> sides_h;   // side table of the sets being launched
     std::vector<char> up_cache;     // set descriptors, side table, set offsets last uploaded
     DevBuf lcx, lcy, lqx, lqy, lkeys, lcnt, lflag;   // Lloyd iterations
@@ -106,6 +155,8 @@ struct Workspace {
     hipGraphExec_t gexec[NSTAGES] = {};
     hipGraph_t graph[NSTAGES] = {};
     PipeArgs gkey{};
+    PipeArgs last{};          // the arguments of the last run launched kernel by kernel
+    bool have_last = false;
     bool have_graph = false;
     bool graph_broken = false;
     bool last_timed = false;
@@ -134,7 +185,6 @@ struct Workspace {
         drop_graph();
         for (auto &x : b) x.release();
         h_in.release();
-        for (auto &o : out_cache) o.reset();
         up_cache.clear();
     }
     void destroy() {
@@ -144,7 +194,6 @@ struct Workspace {
         for (DevBuf *x : {&lcx, &lcy, &lqx, &lqy, &lkeys, &lcnt, &lflag}) x->release();
         h_in.release();
         h_small.release();
-        for (auto &o : out_cache) o.reset();
         h_lloyd.release();
         if (ev0) (void)hipEventDestroy(ev0);
         if (ev1) (void)hipEventDestroy(ev1);
@@ -164,7 +213,7 @@ struct ResultBox {   // vor_result plus the storage it points to
     std::vector<int32_t> nbr;
     std::vector<vor_rat> vtx;
     std::vector<uint32_t> del;
-    std::shared_ptr<OutBlock> block;   // a run's shared host block (instead of the vectors)
+    std::shared_ptr<OutBlock> block;   // a run's host block (instead of the vectors)
 };
 
 vor_result *new_result(ResultBox *&box) {
@@ -209,6 +258,7 @@ struct vor_ctx {
     // per-set grid parameters by size class (vor_set_size_tuning); empty: `tune` for every set
     std::vector<vor_size_tuning> size_tune;
     Workspace ws;            // vor_compute / vor_compute_batch
+    std::shared_ptr<PinnedPool> pool = std::make_shared<PinnedPool>();   // host result memory
     std::mutex mu;           // serialises vor_compute*
     bool use_graph = true;
     long long coop_below = 4096;   // sets up to this size: one wave per cell
@@ -336,8 +386,13 @@ int launch(vor_ctx *ctx, Workspace &ws, const std::vector<HostSet> &sets, bool v
     // one graph for the whole pipeline, or one per stage with events between the stages
     const int ngraphs = a.time_stages ? NSTAGES : 1;
     bool launched = false;
-    if (use_graph && !ws.graph_broken) {
-        if (!ws.have_graph || std::memcmp(&ws.gkey, &a, sizeof(a)) != 0) {
+    // a graph pays when it is replayed: the first run of a new shape launches kernel by kernel,
+    // and the graph is captured when the same shape comes again (the request loop's batches
+    // rarely repeat one)
+    const bool same_graph = ws.have_graph && std::memcmp(&ws.gkey, &a, sizeof(a)) == 0;
+    const bool repeat = ws.have_last && std::memcmp(&ws.last, &a, sizeof(a)) == 0;
+    if (use_graph && !ws.graph_broken && (same_graph || repeat)) {
+        if (!same_graph) {
             ws.drop_graph();
             bool ok = true;
             for (int g = 0; g < ngraphs && ok; ++g) {
@@ -380,6 +435,8 @@ int launch(vor_ctx *ctx, Workspace &ws, const std::vector<HostSet> &sets, bool v
         if (a.time_stages && (e = hipEventRecord(ws.ek[NSTAGES], ws.stream)) != hipSuccess)
             return VOR_E_DEVICE;
         if ((e = hipGetLastError()) != hipSuccess) return VOR_E_DEVICE;
+        ws.last = a;
+        ws.have_last = true;
     }
     ws.used_graph = launched;
     if ((e = hipEventRecord(ws.ev1, ws.stream)) != hipSuccess) return VOR_E_DEVICE;
@@ -420,33 +477,15 @@ Summary read_summary(Workspace &ws) {
 }
 
 
-// A block of at least `bytes` for a run's host results: a free cached pinned block, else a new
-// pinned block in a free or empty cache slot, else (every cached block still held by results,
-// or pinned memory short) a pageable block of this run's own.
-std::shared_ptr<OutBlock> take_out_block(Workspace &ws, size_t bytes) {
+// A host block of at least `bytes` for results: from the pinned pool, else pageable.
+std::shared_ptr<OutBlock> take_out_block(const std::shared_ptr<PinnedPool> &pool, size_t bytes) {
     try {
-        for (auto &o : ws.out_cache)
-            if (o && o.use_count() == 1 && o->cap >= bytes) {
-                // the last holder's release happened before this read: its reads are done
-                std::atomic_thread_fence(std::memory_order_acquire);
-                return o;
-            }
-        for (auto &o : ws.out_cache) {
-            if (o && o.use_count() != 1) continue;
-            o.reset();
-            auto nb = std::make_shared<OutBlock>();
-            const size_t want = bytes + bytes / 8;
-            if (hipHostMalloc(&nb->p, want, hipHostMallocDefault) != hipSuccess) {
-                (void)hipGetLastError();
-                nb->p = nullptr;
-                break;
-            }
-            nb->cap = want;
-            nb->pinned = true;
-            o = nb;
-            return o;
-        }
         auto nb = std::make_shared<OutBlock>();
+        nb->p = pool->get(bytes, nb->cap);
+        if (nb->p) {
+            nb->pool = pool;
+            return nb;
+        }
         nb->p = std::malloc(bytes);
         if (!nb->p) return nullptr;
         nb->cap = bytes;
@@ -456,30 +495,96 @@ std::shared_ptr<OutBlock> take_out_block(Workspace &ws, size_t bytes) {
     }
 }
 
-// Copy the results of every set back to the host (after the stream is idle): the run's output
-// arrays by DMA into one host block, each set's offsets rebased to its first entry, and every
-// set's result pointing at its slices of the block.
-int collect_host(Workspace &ws, const PipeArgs &a, const std::vector<SetDesc> &descs,
-                 const Summary &sm, bool vertices, std::vector<vor_result *> &outs) {
+size_t up256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// Fills a set's result (arrays at the given host addresses) with the run's figures.
+void fill_result(vor_result *r, const Summary &sm, uint32_t n, const uint32_t *off,
+                 const int32_t *nbr, const vor_rat *vtx, uint64_t m, const uint32_t *del) {
+    r->n = n;
+    r->cell_off = off;
+    r->nbr = nbr;
+    r->vtx = vtx;
+    r->m = m;
+    r->del = del;
+    fill_stats(r->stats, sm.stats);
+    r->device_ms = sm.ms;
+    r->cells_ms = sm.cells_ms;
+    r->exact_ms = sm.exact_ms;
+    r->grid_ms = sm.stage_ms[0];
+    r->adaptive_ms = sm.stage_ms[2];
+    r->emit_ms = sm.stage_ms[4];
+    r->graph_replayed = sm.graph ? 1 : 0;
+    r->status = VOR_OK;
+}
+
+// Copy the results of every set back to the host (after the stream is idle).
+// Shared (the batch calls): the run's output arrays by DMA into one host block, each set's
+// offsets rebased to its first entry inside it, every set's result pointing at its slices.
+// Per set (the request loop, whose results are handed over and freed one by one): the offsets
+// first, then each set's slices by DMA into a block of its own.
+int collect_host(Workspace &ws, const std::shared_ptr<PinnedPool> &pool, const PipeArgs &a,
+                 const std::vector<SetDesc> &descs, const Summary &sm, bool vertices,
+                 bool per_set, std::vector<vor_result *> &outs) {
     const long long T = a.total;
     const int K = (int)descs.size();
-    auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
     const size_t b_off = 4ull * (T + 1), b_nbr = 4ull * sm.edges;
     const size_t b_vtx = vertices ? sizeof(vor_rat) * sm.edges : 0, b_del = 8ull * sm.dels;
-    const size_t o_doff = up(b_off), o_nbr = o_doff + up(b_off), o_vtx = o_nbr + up(b_nbr);
-    const size_t o_del = o_vtx + up(b_vtx), o_rel = o_del + up(b_del);
-    std::shared_ptr<OutBlock> blk = take_out_block(ws, o_rel + 4ull * (T + K));
+    const size_t o_doff = up256(b_off), o_nbr = o_doff + up256(b_off);
+    const size_t o_vtx = o_nbr + up256(per_set ? 0 : b_nbr);
+    const size_t o_del = o_vtx + up256(per_set ? 0 : b_vtx);
+    const size_t o_rel = o_del + up256(per_set ? 0 : b_del);
+    std::shared_ptr<OutBlock> blk = take_out_block(pool, per_set ? o_nbr : o_rel + 4ull * (T + K));
     if (!blk) return VOR_E_NOMEM;
     char *hp = (char *)blk->p;
     const int *off = (const int *)hp;
     const int *doff = (const int *)(hp + o_doff);
+    hipError_t e = hipMemcpyAsync((void *)off, a.cell_off, b_off, hipMemcpyDeviceToHost, ws.stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync((void *)doff, a.del_off, b_off, hipMemcpyDeviceToHost, ws.stream);
+    outs.assign(K, nullptr);
+    auto fail = [&](int rc) {
+        (void)hipStreamSynchronize(ws.stream);   // no copy into a block that goes back
+        for (auto &o : outs) vor_result_free(o);
+        outs.clear();
+        return rc;
+    };
+    if (per_set) {
+        if (e == hipSuccess) e = hipStreamSynchronize(ws.stream);
+        if (e != hipSuccess) return fail(VOR_E_DEVICE);
+        for (int i = 0; i < K && e == hipSuccess; ++i) {
+            const int so = descs[i].site_off, n = descs[i].n;
+            const int e0 = off[so], E = off[so + n] - e0;
+            const int d0 = doff[so], m = doff[so + n] - d0;
+            const size_t q_nbr = up256(4ull * (n + 1)), q_vtx = q_nbr + up256(4ull * E);
+            const size_t q_del = q_vtx + up256(vertices ? sizeof(vor_rat) * E : 0);
+            std::shared_ptr<OutBlock> own = take_out_block(pool, q_del + 8ull * m);
+            ResultBox *box;
+            vor_result *r = own ? new_result(box) : nullptr;
+            if (!r) return fail(VOR_E_NOMEM);
+            outs[i] = r;
+            box->block = own;
+            char *q = (char *)own->p;
+            uint32_t *ro = (uint32_t *)q;
+            for (int t = 0; t <= n; ++t) ro[t] = (uint32_t)(off[so + t] - e0);
+            if (E) e = hipMemcpyAsync(q + q_nbr, a.nbr + e0, 4ull * E, hipMemcpyDeviceToHost, ws.stream);
+            if (e == hipSuccess && vertices && E)
+                e = hipMemcpyAsync(q + q_vtx, (const vor_rat *)a.vtx + e0, sizeof(vor_rat) * E,
+                                   hipMemcpyDeviceToHost, ws.stream);
+            if (e == hipSuccess && m)
+                e = hipMemcpyAsync(q + q_del, a.del + 2ll * d0, 8ull * m, hipMemcpyDeviceToHost,
+                                   ws.stream);
+            fill_result(r, sm, (uint32_t)n, ro, (const int32_t *)(q + q_nbr),
+                        vertices ? (const vor_rat *)(q + q_vtx) : nullptr, (uint64_t)m,
+                        (const uint32_t *)(q + q_del));
+        }
+        if (e == hipSuccess) e = hipStreamSynchronize(ws.stream);
+        if (e != hipSuccess) return fail(VOR_E_DEVICE);
+        return VOR_OK;
+    }
     const int32_t *nbr = (const int32_t *)(hp + o_nbr);
     const vor_rat *vtx = (const vor_rat *)(hp + o_vtx);
     const uint32_t *del = (const uint32_t *)(hp + o_del);
     uint32_t *rel = (uint32_t *)(hp + o_rel);   // set i's n+1 offsets at site_off + i
-    hipError_t e = hipMemcpyAsync((void *)off, a.cell_off, b_off, hipMemcpyDeviceToHost, ws.stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync((void *)doff, a.del_off, b_off, hipMemcpyDeviceToHost, ws.stream);
     if (e == hipSuccess && b_nbr)
         e = hipMemcpyAsync((void *)nbr, a.nbr, b_nbr, hipMemcpyDeviceToHost, ws.stream);
     if (e == hipSuccess && b_vtx)
@@ -487,7 +592,7 @@ int collect_host(Workspace &ws, const PipeArgs &a, const std::vector<SetDesc> &d
     if (e == hipSuccess && b_del)
         e = hipMemcpyAsync((void *)del, a.del, b_del, hipMemcpyDeviceToHost, ws.stream);
     if (e == hipSuccess) e = hipStreamSynchronize(ws.stream);
-    if (e != hipSuccess) return VOR_E_DEVICE;
+    if (e != hipSuccess) return fail(VOR_E_DEVICE);
     // rebasing: pieces of at most 2^20 offsets, spread over a few threads for large runs
     constexpr int PIECE = 1 << 20;
     std::vector<std::pair<int, int>> pieces;   // (set, first offset)
@@ -512,35 +617,17 @@ int collect_host(Workspace &ws, const PipeArgs &a, const std::vector<SetDesc> &d
     }
     rebase();
     for (auto &x : th) x.join();
-    outs.assign(K, nullptr);
     for (int i = 0; i < K; ++i) {
         ResultBox *box;
         vor_result *r = new_result(box);
-        if (!r) {
-            for (auto &o : outs) vor_result_free(o);
-            outs.clear();
-            return VOR_E_NOMEM;
-        }
+        if (!r) return fail(VOR_E_NOMEM);
+        outs[i] = r;
         box->block = blk;
         const int so = descs[i].site_off, n = descs[i].n;
         const int e0 = off[so];
         const int d0 = doff[so], d1 = doff[so + n];
-        r->n = (uint32_t)n;
-        r->cell_off = rel + so + i;
-        r->nbr = nbr + e0;
-        r->vtx = vertices ? vtx + e0 : nullptr;
-        r->m = (uint64_t)(d1 - d0);
-        r->del = del + 2ll * d0;
-        fill_stats(r->stats, sm.stats);
-        r->device_ms = sm.ms;
-        r->cells_ms = sm.cells_ms;
-        r->exact_ms = sm.exact_ms;
-        r->grid_ms = sm.stage_ms[0];
-        r->adaptive_ms = sm.stage_ms[2];
-        r->emit_ms = sm.stage_ms[4];
-        r->graph_replayed = sm.graph ? 1 : 0;
-        r->status = VOR_OK;
-        outs[i] = r;
+        fill_result(r, sm, (uint32_t)n, rel + so + i, nbr + e0, vertices ? vtx + e0 : nullptr,
+                    (uint64_t)(d1 - d0), del + 2ll * d0);
     }
     return VOR_OK;
 }
@@ -584,7 +671,7 @@ int run_sync(vor_ctx *ctx, Workspace &ws, const std::vector<HostSet> &sets,
         outs.assign(1, r);
         return VOR_OK;
     }
-    return collect_host(ws, a, descs, sm, vertices, outs);
+    return collect_host(ws, ctx->pool, a, descs, sm, vertices, false, outs);
 }
 
 // ------------------------------------------------------------------------------ request loop
@@ -625,7 +712,8 @@ void request_loop(vor_ctx *ctx) {
                 rc = map_status(sm.status);
             }
             if (rc == VOR_OK)
-                rc = collect_host(ctx->rws[w], fl[w].a, fl[w].descs, sm, vertices, outs);
+                rc = collect_host(ctx->rws[w], ctx->pool, fl[w].a, fl[w].descs, sm, vertices,
+                                  true, outs);
             if (rc != VOR_OK && rc != VOR_E_DEVICE && fl[w].reqs.size() > 1) {
                 // an input error of one request: re-run each alone so the others succeed
                 std::lock_guard<std::mutex> lk(ctx->qmu);

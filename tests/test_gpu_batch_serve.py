@@ -69,15 +69,19 @@ def test_batch_with_a_bad_set(vor):
 
 
 def test_batch_repeated_calls_replay(vor):
-    """The second call with the same shapes replays the captured graph; results identical."""
+    """A new shape launches kernel by kernel; the same shape again is captured as a graph and
+    replayed from then on; the results of all three calls are identical."""
     sets = uneven_sets(16, seed=5, hi=2048)
     args = [(s.x, s.y, s.box) for s in sets]
     with vor.Context() as ctx:
         _, r1 = ctx.compute_batch(args)
         _, r2 = ctx.compute_batch(args)
-        for a, b in zip(r1, r2):
+        _, r3 = ctx.compute_batch(args)
+        for a, b, c in zip(r1, r2, r3):
             same(a, b)
-        assert r2[0].graph_replayed in (0, 1)
+            same(a, c)
+        assert r1[0].graph_replayed == 0
+        assert r2[0].graph_replayed == 1 and r3[0].graph_replayed == 1
 
 
 def wait_all(ctx, tickets, timeout=120.0):
