@@ -517,82 +517,55 @@ void fill_result(vor_result *r, const Summary &sm, uint32_t n, const uint32_t *o
     r->status = VOR_OK;
 }
 
-// Copy the results of every set back to the host (after the stream is idle).
-// Shared (the batch calls): the run's output arrays by DMA into one host block, each set's
-// offsets rebased to its first entry inside it, every set's result pointing at its slices.
-// Per set (the request loop, whose results are handed over and freed one by one): the offsets
-// first, then each set's slices by DMA into a block of its own.
-int collect_host(Workspace &ws, const std::shared_ptr<PinnedPool> &pool, const PipeArgs &a,
-                 const std::vector<SetDesc> &descs, const Summary &sm, bool vertices,
-                 bool per_set, std::vector<vor_result *> &outs) {
+// The host copy of a run's output arrays: enqueued on the workspace's stream right behind the
+// pipeline, so that the copy engine starts as soon as the kernels end, without a round trip
+// through the host.  The totals are not known yet, so the arrays go over at their capacity
+// (sized by the Euler bound, within a few entries of the totals); one pool block holds them and
+// the rebased offsets of every set.
+struct HostCopy {
+    std::shared_ptr<OutBlock> blk;
+    size_t o_doff = 0, o_nbr = 0, o_vtx = 0, o_del = 0, o_rel = 0;
+};
+
+int enqueue_host_copy(Workspace &ws, const std::shared_ptr<PinnedPool> &pool, const PipeArgs &a,
+                      int K, bool vertices, HostCopy &hc) {
+    const long long T = a.total;
+    const size_t b_off = 4ull * (T + 1), b_nbr = 4ull * a.nbr_cap;
+    const size_t b_vtx = vertices ? sizeof(vor_rat) * a.nbr_cap : 0, b_del = 8ull * a.del_cap;
+    hc.o_doff = up256(b_off);
+    hc.o_nbr = hc.o_doff + up256(b_off);
+    hc.o_vtx = hc.o_nbr + up256(b_nbr);
+    hc.o_del = hc.o_vtx + up256(b_vtx);
+    hc.o_rel = hc.o_del + up256(b_del);
+    hc.blk = take_out_block(pool, hc.o_rel + 4ull * (T + K));
+    if (!hc.blk) return VOR_E_NOMEM;
+    char *hp = (char *)hc.blk->p;
+    hipError_t e = hipMemcpyAsync(hp, a.cell_off, b_off, hipMemcpyDeviceToHost, ws.stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(hp + hc.o_doff, a.del_off, b_off, hipMemcpyDeviceToHost, ws.stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(hp + hc.o_nbr, a.nbr, b_nbr, hipMemcpyDeviceToHost, ws.stream);
+    if (e == hipSuccess && b_vtx)
+        e = hipMemcpyAsync(hp + hc.o_vtx, a.vtx, b_vtx, hipMemcpyDeviceToHost, ws.stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(hp + hc.o_del, a.del, b_del, hipMemcpyDeviceToHost, ws.stream);
+    return e == hipSuccess ? VOR_OK : VOR_E_DEVICE;
+}
+
+// The results of every set from a finished host copy (the stream is idle): each set's offsets
+// rebased to its first entry inside the block, every set's result pointing at its slices and
+// holding a reference to the block.
+int finish_host(const HostCopy &hc, const PipeArgs &a, const std::vector<SetDesc> &descs,
+                const Summary &sm, bool vertices, std::vector<vor_result *> &outs) {
     const long long T = a.total;
     const int K = (int)descs.size();
-    const size_t b_off = 4ull * (T + 1), b_nbr = 4ull * sm.edges;
-    const size_t b_vtx = vertices ? sizeof(vor_rat) * sm.edges : 0, b_del = 8ull * sm.dels;
-    const size_t o_doff = up256(b_off), o_nbr = o_doff + up256(b_off);
-    const size_t o_vtx = o_nbr + up256(per_set ? 0 : b_nbr);
-    const size_t o_del = o_vtx + up256(per_set ? 0 : b_vtx);
-    const size_t o_rel = o_del + up256(per_set ? 0 : b_del);
-    std::shared_ptr<OutBlock> blk = take_out_block(pool, per_set ? o_nbr : o_rel + 4ull * (T + K));
-    if (!blk) return VOR_E_NOMEM;
-    char *hp = (char *)blk->p;
+    char *hp = (char *)hc.blk->p;
     const int *off = (const int *)hp;
-    const int *doff = (const int *)(hp + o_doff);
-    hipError_t e = hipMemcpyAsync((void *)off, a.cell_off, b_off, hipMemcpyDeviceToHost, ws.stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync((void *)doff, a.del_off, b_off, hipMemcpyDeviceToHost, ws.stream);
-    outs.assign(K, nullptr);
-    auto fail = [&](int rc) {
-        (void)hipStreamSynchronize(ws.stream);   // no copy into a block that goes back
-        for (auto &o : outs) vor_result_free(o);
-        outs.clear();
-        return rc;
-    };
-    if (per_set) {
-        if (e == hipSuccess) e = hipStreamSynchronize(ws.stream);
-        if (e != hipSuccess) return fail(VOR_E_DEVICE);
-        for (int i = 0; i < K && e == hipSuccess; ++i) {
-            const int so = descs[i].site_off, n = descs[i].n;
-            const int e0 = off[so], E = off[so + n] - e0;
-            const int d0 = doff[so], m = doff[so + n] - d0;
-            const size_t q_nbr = up256(4ull * (n + 1)), q_vtx = q_nbr + up256(4ull * E);
-            const size_t q_del = q_vtx + up256(vertices ? sizeof(vor_rat) * E : 0);
-            std::shared_ptr<OutBlock> own = take_out_block(pool, q_del + 8ull * m);
-            ResultBox *box;
-            vor_result *r = own ? new_result(box) : nullptr;
-            if (!r) return fail(VOR_E_NOMEM);
-            outs[i] = r;
-            box->block = own;
-            char *q = (char *)own->p;
-            uint32_t *ro = (uint32_t *)q;
-            for (int t = 0; t <= n; ++t) ro[t] = (uint32_t)(off[so + t] - e0);
-            if (E) e = hipMemcpyAsync(q + q_nbr, a.nbr + e0, 4ull * E, hipMemcpyDeviceToHost, ws.stream);
-            if (e == hipSuccess && vertices && E)
-                e = hipMemcpyAsync(q + q_vtx, (const vor_rat *)a.vtx + e0, sizeof(vor_rat) * E,
-                                   hipMemcpyDeviceToHost, ws.stream);
-            if (e == hipSuccess && m)
-                e = hipMemcpyAsync(q + q_del, a.del + 2ll * d0, 8ull * m, hipMemcpyDeviceToHost,
-                                   ws.stream);
-            fill_result(r, sm, (uint32_t)n, ro, (const int32_t *)(q + q_nbr),
-                        vertices ? (const vor_rat *)(q + q_vtx) : nullptr, (uint64_t)m,
-                        (const uint32_t *)(q + q_del));
-        }
-        if (e == hipSuccess) e = hipStreamSynchronize(ws.stream);
-        if (e != hipSuccess) return fail(VOR_E_DEVICE);
-        return VOR_OK;
-    }
-    const int32_t *nbr = (const int32_t *)(hp + o_nbr);
-    const vor_rat *vtx = (const vor_rat *)(hp + o_vtx);
-    const uint32_t *del = (const uint32_t *)(hp + o_del);
-    uint32_t *rel = (uint32_t *)(hp + o_rel);   // set i's n+1 offsets at site_off + i
-    if (e == hipSuccess && b_nbr)
-        e = hipMemcpyAsync((void *)nbr, a.nbr, b_nbr, hipMemcpyDeviceToHost, ws.stream);
-    if (e == hipSuccess && b_vtx)
-        e = hipMemcpyAsync((void *)vtx, a.vtx, b_vtx, hipMemcpyDeviceToHost, ws.stream);
-    if (e == hipSuccess && b_del)
-        e = hipMemcpyAsync((void *)del, a.del, b_del, hipMemcpyDeviceToHost, ws.stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(ws.stream);
-    if (e != hipSuccess) return fail(VOR_E_DEVICE);
+    const int *doff = (const int *)(hp + hc.o_doff);
+    const int32_t *nbr = (const int32_t *)(hp + hc.o_nbr);
+    const vor_rat *vtx = (const vor_rat *)(hp + hc.o_vtx);
+    const uint32_t *del = (const uint32_t *)(hp + hc.o_del);
+    uint32_t *rel = (uint32_t *)(hp + hc.o_rel);   // set i's n+1 offsets at site_off + i
     // rebasing: pieces of at most 2^20 offsets, spread over a few threads for large runs
     constexpr int PIECE = 1 << 20;
     std::vector<std::pair<int, int>> pieces;   // (set, first offset)
@@ -617,12 +590,17 @@ int collect_host(Workspace &ws, const std::shared_ptr<PinnedPool> &pool, const P
     }
     rebase();
     for (auto &x : th) x.join();
+    outs.assign(K, nullptr);
     for (int i = 0; i < K; ++i) {
         ResultBox *box;
         vor_result *r = new_result(box);
-        if (!r) return fail(VOR_E_NOMEM);
+        if (!r) {
+            for (auto &o : outs) vor_result_free(o);
+            outs.clear();
+            return VOR_E_NOMEM;
+        }
         outs[i] = r;
-        box->block = blk;
+        box->block = hc.blk;
         const int so = descs[i].site_off, n = descs[i].n;
         const int e0 = off[so];
         const int d0 = doff[so], d1 = doff[so + n];
@@ -641,6 +619,9 @@ int run_sync(vor_ctx *ctx, Workspace &ws, const std::vector<HostSet> &sets,
     std::vector<SetDesc> descs;
     std::vector<int> set_off;
     int rc = launch(ctx, ws, sets, vertices, exact_only, sym, ctx->use_graph, a, descs, set_off);
+    HostCopy hc;
+    if (rc == VOR_OK && !device_result)
+        rc = enqueue_host_copy(ws, ctx->pool, a, (int)descs.size(), vertices, hc);
     if (rc != VOR_OK) {
         (void)hipStreamSynchronize(ws.stream);
         return rc;
@@ -671,7 +652,7 @@ int run_sync(vor_ctx *ctx, Workspace &ws, const std::vector<HostSet> &sets,
         outs.assign(1, r);
         return VOR_OK;
     }
-    return collect_host(ws, ctx->pool, a, descs, sm, vertices, false, outs);
+    return finish_host(hc, a, descs, sm, vertices, outs);
 }
 
 // ------------------------------------------------------------------------------ request loop
@@ -682,6 +663,7 @@ void request_loop(vor_ctx *ctx) {
         PipeArgs a;
         std::vector<SetDesc> descs;
         std::vector<int> set_off;
+        HostCopy hc;     // the outputs' host copy, enqueued behind the pipeline
         bool busy = false;
         size_t fp = 0;   // admitted footprint
     } fl[REQ_WORKSPACES];
@@ -711,9 +693,8 @@ void request_loop(vor_ctx *ctx) {
                 sm = read_summary(ctx->rws[w]);
                 rc = map_status(sm.status);
             }
-            if (rc == VOR_OK)
-                rc = collect_host(ctx->rws[w], ctx->pool, fl[w].a, fl[w].descs, sm, vertices,
-                                  true, outs);
+            if (rc == VOR_OK) rc = finish_host(fl[w].hc, fl[w].a, fl[w].descs, sm, vertices, outs);
+            fl[w].hc.blk.reset();   // the results hold the block now (or nobody does)
             if (rc != VOR_OK && rc != VOR_E_DEVICE && fl[w].reqs.size() > 1) {
                 // an input error of one request: re-run each alone so the others succeed
                 std::lock_guard<std::mutex> lk(ctx->qmu);
@@ -796,8 +777,12 @@ void request_loop(vor_ctx *ctx) {
             for (auto &r : take) fl[w].fp += r->footprint;
             int rc = launch(ctx, ctx->rws[w], sets, vertices, exact_only, false, ctx->use_graph,
                             fl[w].a, fl[w].descs, fl[w].set_off);
+            if (rc == VOR_OK)
+                rc = enqueue_host_copy(ctx->rws[w], ctx->pool, fl[w].a, (int)fl[w].descs.size(),
+                                       vertices, fl[w].hc);
             if (rc != VOR_OK) {
                 (void)hipStreamSynchronize(ctx->rws[w].stream);
+                fl[w].hc.blk.reset();   // after the stream: no copy still going into it
                 std::lock_guard<std::mutex> lk(ctx->qmu);
                 for (auto &r : take) {
                     r->status = rc;
