@@ -636,6 +636,19 @@ struct TreeScan {
     int nl;      // sites in the list (may exceed LS::K: overflow)
     bool cached;
     int work;    // sub-buckets visited + evaluations for this cell (lane-per-cell scans)
+    unsigned long long t0;   // when the lane started the cell (100 MHz clock)
+    const int *done = nullptr;   // workgroups of the pass that have finished their cells
+    int tail = 0;                // from this many on, the pass is in its tail
+
+    // In the pass's tail, a lane that has spent TREE_TICKS on its cell hands it on: the walk's
+    // steps are chains of dependent loads, so a cell near a cluster can hold its lane for
+    // milliseconds within its work budget while the rest of the GPU idles.  Before the tail the
+    // lanes share the GPU and their clocks say little.  The cell's result does not depend on
+    // which pass computes it.
+    __device__ __forceinline__ bool over_time() const {
+        return done && wall_clock64() - t0 > TREE_TICKS &&
+               __hip_atomic_load(done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= tail;
+    }
 
     // Appends the sites of N \ O to the list; false (and the list as before) on overflow.
     __device__ __forceinline__ bool gather(const Cell &C, const float2 *__restrict__ sxy, Rect N,
@@ -679,6 +692,7 @@ struct TreeScan {
         Q0 = tree_block(C, T, C.ht);
         heavy = false;
         work = 0;
+        if (LS::K > 0) t0 = wall_clock64();
         if (LS::K > 0) {
             G = tree_block(C, T, 0);
             nl = 0;
@@ -749,6 +763,10 @@ struct TreeScan {
                 }
                 pos += TREE_BATCH * P::W;
                 continue;
+            }
+            if (LS::K > 0 && over_time()) {
+                heavy = true;
+                break;
             }
             if (!wk.next(C, T, fs)) break;
             pos = wk.pos + P::lane();
@@ -918,12 +936,19 @@ struct TreeScan {
         const float lim = Tlim * CERT_UP;
         TreeWalk wk;
         wk.start(C, T, N, O, Dk);
-        int pos = 0, end = 0;
+        int pos = 0, end = 0, ev = 0;
         bool full = true;
         for (;;) {
+            // the lane-per-cell scans keep to the cell's work budget here too: a disk that
+            // holds a cluster would keep one lane busy long after the others
+            if (LS::K > 0 && work + wk.steps + ev > TREE_BUDGET) {
+                heavy = true;
+                break;
+            }
             if (pos < end) {
                 const int q = pos;
                 pos += P::W;
+                ++ev;
                 if (q == ex1 || q == ex2) continue;
                 const float2 a = sxy[q];
                 if (!full && !(in_rect(N, a.x, a.y) && !in_rect(O, a.x, a.y))) continue;
@@ -931,11 +956,16 @@ struct TreeScan {
                 exact_site<FILTER, P>(C, a, q, d, lim, xb, K);
                 continue;
             }
+            if (LS::K > 0 && over_time()) {
+                heavy = true;
+                break;
+            }
             if (!wk.next(C, T, fs)) break;
             pos = wk.pos + P::lane();
             end = wk.end;
             full = wk.full;
         }
+        work += wk.steps + ev;
     }
 
     __device__ __forceinline__ void exact(const Cell &C, const float2 *__restrict__ sxy,
@@ -1062,6 +1092,7 @@ __device__ __forceinline__ int ray(const Cell &C, Sc &sc, const float2 *__restri
         K.xinc += vmode;
         // exact decision over the certified region, FP32-plausible candidates only
         sc.exact(C, sxy, d, s, vmode ? tu_hi : s.U, ex1, ex2, xb, K);
+        if (sc.heavy) return -4;   // over the lane's work budget (tree scans)
     }
     // no line other than the two through u is crossed: u is the endpoint (a vertex)
     if (!xb.have) return vmode ? 1 : -1;

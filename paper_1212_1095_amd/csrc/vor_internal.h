@@ -86,6 +86,7 @@ struct PipeArgs {
     int *rootcnt() const { return small + 6; }   // refined grid buckets (tree roots)
     int *qcount4() const { return small + 7; }   // cells the local grids hand to the tree scans
     int *qcount3() const { return small + 8; }
+    int *tree_done() const { return small + 9; }   // workgroups of the tree scans done
     int *nlist;             // [TREE_LEVELS - 1][ncap] node ids of refinement levels 2..
     unsigned char *bflag;   // [total] by sorted position: the site lies on the boundary of X
     unsigned char *hand;    // [total] by sorted position: the filtered pass handed the cell on

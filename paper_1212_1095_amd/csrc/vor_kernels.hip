@@ -681,7 +681,7 @@ __global__ __launch_bounds__(BLOCK, 3) void k_cells_tree(
     int *__restrict__ queue, int *__restrict__ qcount, const int *__restrict__ queue4,
     const int *__restrict__ qcount4, int *__restrict__ tlist,
     unsigned long long *__restrict__ stats, const unsigned char *__restrict__ bflag,
-    const int *__restrict__ status) {
+    int *__restrict__ done, const int *__restrict__ status) {
     __shared__ int stk[SCAP][BLOCK];
     __shared__ int fr[TFRAMES][3][BLOCK];
     __shared__ unsigned long long sh[SL_COUNT];
@@ -691,6 +691,9 @@ __global__ __launch_bounds__(BLOCK, 3) void k_cells_tree(
     if ((int)(blockIdx.x * BLOCK) >= nq) return;
     if (threadIdx.x < SL_COUNT) sh[threadIdx.x] = 0;
     __syncthreads();
+    // the tail: all but an eighth of the workgroups that have cells are done
+    const int busy = min((int)gridDim.x, (nq + BLOCK - 1) / BLOCK);
+    const int tail = busy - max(1, busy / 8);
     Counters K{};
     uint32_t edges = 0, deferred = 0;
     for (int qi = blockIdx.x * BLOCK + threadIdx.x; qi < nq; qi += gridDim.x * BLOCK) {
@@ -706,6 +709,8 @@ __global__ __launch_bounds__(BLOCK, 3) void k_cells_tree(
             GlobalList<TREE_LIST>{tlist + blockIdx.x * BLOCK + threadIdx.x,
                                   (int)(gridDim.x * BLOCK)},
             Rect{}, false, Rect{}, 0, false};
+        sc.done = done;
+        sc.tail = tail;
         Sink sink{olines + pos, total, sid, k};
         const int r = run_cell<1, Solo>(C, sxy, sc, st, SCAP, sink, KOUT, K);
         if (r >= 0) {
@@ -718,7 +723,8 @@ __global__ __launch_bounds__(BLOCK, 3) void k_cells_tree(
             ++deferred;
         }
     }
-    reduce_stats(K, edges, deferred, 0, sh, stats, true);
+    reduce_stats(K, edges, deferred, 0, sh, stats, true);   // ends with a barrier
+    if (threadIdx.x == 0) atomicAdd(done, 1);
 }
 
 // Every cell into a queue, in bucket order.
@@ -1618,7 +1624,7 @@ void launch_stage(const PipeArgs &a, hipStream_t st, int stage) {
             k_cells_tree<TREE_PASS_BLOCK><<<nb, TREE_PASS_BLOCK, 0, st>>>(
                 a.sets, a.nsets, a.set_off, a.sides, a.sxy, a.sid, a.bstart, a.tchild, a.nodes, a.tref,
                 T, a.ocnt, a.olines, a.ovf, a.dcnt, a.queue, a.qcount(), a.queue4, a.qcount4(),
-                a.tlist, a.stats, a.bflag, a.status());
+                a.tlist, a.stats, a.bflag, a.tree_done(), a.status());
         }
     } else if (stage == 3) {
         if (a.exact_only) launch_exact<2>(a, st);

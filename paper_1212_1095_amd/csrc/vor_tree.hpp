@@ -30,6 +30,9 @@ constexpr int TREE_LIST_FILL = 20;// the cached region grows until it holds this
 constexpr int TREE_PROBES = 6;    // leaves probed along the ray before a region pass
 constexpr int TREE_BUDGET = 640;  // sub-buckets + evaluations a lane spends on one cell before
                                   // handing it to the one-wave-per-cell pass
+constexpr unsigned long long TREE_TICKS = 30000;   // 300 us at the 100 MHz clock: a lane's
+                                                 // time on one cell before it hands the cell on
+                                                 // in the tree scans' tail
 constexpr int TREE_BATCH = 4;     // candidate loads issued together (one lane walks one cell, so
                                   // the loads of a leaf or of the list overlap instead of queueing)
 
