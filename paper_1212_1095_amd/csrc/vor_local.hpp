@@ -25,7 +25,7 @@ constexpr float LOC_MARGIN = 2.5f;  // region margin in local spacings
 constexpr int LOC_GRID_MAX = 4096;  // workgroups at most (then each takes several chunks)
 constexpr int LOC_NF = 2 * LOC_BLOCK;   // refined nodes per level of a region's gather at most
 constexpr int LOC_GBMAX = 4096;     // grid buckets of a region at most
-constexpr int LOC_MINGROUP = 32;    // a region that overflows is split down to this many cells
+constexpr int LOC_MINGROUP = 64;    // a region that overflows is split down to this many cells
 static_assert(LOC_BCAP == 4 * LOC_BLOCK, "the bucket scan gives each thread four buckets");
 static_assert(2 * LOC_RCAP >= LOC_BCAP, "the fill counters reuse the range table");
 
