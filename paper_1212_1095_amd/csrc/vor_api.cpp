@@ -520,8 +520,8 @@ void fill_result(vor_result *r, const Summary &sm, uint32_t n, const uint32_t *o
 // The host copy of a run's output arrays: enqueued on the workspace's stream right behind the
 // pipeline, so that the copy engine starts as soon as the kernels end, without a round trip
 // through the host.  The totals are not known yet, so the arrays go over at their capacity
-// (sized by the Euler bound, within a few entries of the totals); one pool block holds them and
-// the rebased offsets of every set.
+// (sized by the Euler bound, a little above the totals: the cells at X's boundary have fewer
+// lines); one pool block holds them and the rebased offsets of every set.
 struct HostCopy {
     std::shared_ptr<OutBlock> blk;
     size_t o_doff = 0, o_nbr = 0, o_vtx = 0, o_del = 0, o_rel = 0;
