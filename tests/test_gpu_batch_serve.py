@@ -219,3 +219,58 @@ def test_size_tuning_changes_no_result(vor):
         for a, b in zip(out[0], res):
             same(a, b)
     assert_matches_oracle(out[1][3], sets[3])
+
+
+def snapshot(r):
+    """Copies of a result's arrays (which view library memory)."""
+    return (r.cell_off.copy(), r.nbr.copy(), None if r.vtx is None else r.vtx.copy(),
+            r.dele.copy())
+
+
+def unchanged(r, snap):
+    off, nbr, vtx, dele = snap
+    assert np.array_equal(r.cell_off, off) and np.array_equal(r.nbr, nbr)
+    assert np.array_equal(r.dele, dele)
+    assert (vtx is None) == (r.vtx is None)
+    if vtx is not None:
+        assert r.vtx.tobytes() == vtx.tobytes()
+
+
+def test_held_results_survive_later_calls_and_the_context(vor):
+    """Results point into pooled host blocks: a block still held by results is never handed to
+    a later run, and results outlive the context that made them."""
+    a_sets = uneven_sets(24, seed=31, hi=3000)
+    b_sets = uneven_sets(24, seed=32, hi=3000)
+    ctx = vor.Context()
+    _, ra = ctx.compute_batch([(s.x, s.y, s.box) for s in a_sets])
+    snaps = [snapshot(r) for r in ra]
+    one = ctx.compute(a_sets[0].x, a_sets[0].y, a_sets[0].box)
+    one_snap = snapshot(one)
+    for _ in range(3):   # later runs of other shapes and of the same shape, results dropped
+        ctx.compute_batch([(s.x, s.y, s.box) for s in b_sets])
+        ctx.compute_batch([(s.x, s.y, s.box) for s in a_sets])
+        ctx.compute(b_sets[1].x, b_sets[1].y, b_sets[1].box)
+    for r, sn in zip(ra, snaps):
+        unchanged(r, sn)
+    unchanged(one, one_snap)
+    ctx.close()
+    for r, sn in zip(ra, snaps):   # after the context is gone
+        unchanged(r, sn)
+    for s, r in zip(a_sets[:4], ra[:4]):
+        assert_matches_oracle(r, s)
+    del ra, one
+
+
+def test_held_request_results_survive_later_requests(vor):
+    """The request loop's results stay intact while later batches run."""
+    sets = [sitegen.uniform(n, 1 << 20, 40 + i) for i, n in enumerate((500, 2000, 800, 5000))]
+    with vor.Context() as ctx:
+        first = wait_all(ctx, [ctx.submit(s.x, s.y, s.box) for s in sets])
+        held = [first[t][1] for t in sorted(first)]
+        snaps = [snapshot(r) for r in held]
+        for _ in range(3):
+            wait_all(ctx, [ctx.submit(s.x, s.y, s.box) for s in reversed(sets)])
+        for r, sn in zip(held, snaps):
+            unchanged(r, sn)
+        for s, r in zip(sets, held):
+            assert_matches_oracle(r, s)
