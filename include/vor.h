@@ -182,10 +182,10 @@ int vor_compute_batch(vor_ctx *ctx, const vor_set *sets, uint32_t k, vor_result 
 
 /* Request loop (the parallel setting of Theorem 9.1(d) applied to independent requests):
  * copy the set into library memory and enqueue it; returns immediately with a ticket.  A host
- * thread admits queued requests in submission order into one of two device workspaces (each
+ * thread admits queued requests in submission order into one of four device workspaces (each
  * admitted group runs as one batched pipeline, as vor_compute_batch) while their HBM
  * footprints (vor_footprint) and those of the batches already on the GPU fit the context's
- * budget; two admitted groups overlap on the device.  Thread-safe.  VOR_E_INVAL for a bad set
+ * budget; up to four admitted groups overlap on the device.  Thread-safe.  VOR_E_INVAL for a bad set
  * or device input (VOR_SET_DEVICE). */
 int vor_submit(vor_ctx *ctx, const vor_set *set, uint64_t *ticket);
 

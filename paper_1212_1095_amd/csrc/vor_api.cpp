@@ -248,7 +248,7 @@ struct Request {
 
 // Batches of the request loop on the GPU at once (one workspace and stream each); three or four
 // gave no better latency on the mixed request stream.
-constexpr int REQ_WORKSPACES = 2;
+constexpr int REQ_WORKSPACES = 4;
 struct vor_ctx {
     int device = 0;
     vor_opts opts{};
