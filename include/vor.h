@@ -219,6 +219,14 @@ void vor_result_free(vor_result *r);
  * (Section 6 representation and Section 7 Delaunay list, as vor_compute returns them.) */
 int vor_result_to_host(vor_ctx *ctx, const vor_result *dev, vor_result **out);
 
+/* Where k results keep their host arrays, in one call: for bindings that wrap many results at
+ * once (a batch's results share one library block).  Row i of `table` (8 words) describes
+ * results[i]: n, m, the addresses of cell_off, nbr, vtx (0 when NULL) and del, then the address
+ * and byte size of the library block that holds those arrays (0 and 0 when they are not in one
+ * such block, as for device results or a result with an error status).  A NULL results[i]
+ * gives a row of zeros.  Nothing is modified or freed.  VOR_E_INVAL for a NULL argument. */
+int vor_result_layout(const vor_result *const *results, uint32_t k, uint64_t *table);
+
 /* Static string for a status code (never NULL). */
 const char *vor_strerror(int status);
 

@@ -97,6 +97,7 @@ def lib():
         L.vor_footprint.argtypes = [C.c_void_p, P(vor_set), P(C.c_uint64)]
         L.vor_result_free.argtypes = [P(vor_result)]
         L.vor_result_to_host.argtypes = [C.c_void_p, P(vor_result), P(P(vor_result))]
+        L.vor_result_layout.argtypes = [P(P(vor_result)), C.c_uint32, P(C.c_uint64)]
         L.vor_result_free.restype = None
         L.vor_strerror.argtypes = [C.c_int]
         L.vor_strerror.restype = C.c_char_p
@@ -316,6 +317,64 @@ def _to_result(rp, device: bool = False, owner: _Owned | None = None,
                   float(r.t_admit), float(r.t_done))
 
 
+class _OwnedMany:
+    """Holds the library results that share one host block: vor_result_free runs for each of
+    them once no array that views the block is referenced."""
+    __slots__ = ("rps",)
+
+    def __init__(self):
+        self.rps = []
+
+    def __del__(self):
+        try:
+            for rp in self.rps:
+                lib().vor_result_free(rp)
+        except Exception:
+            pass
+
+
+def _own_batch(outs, k: int) -> list:
+    """Results of a batch call whose ownership passes to Python.  The results of one run share
+    one library block: one buffer per block, each result's arrays are views at their offsets in
+    it (no ctypes structure read per result), and the block's results are freed together once
+    none of those arrays is referenced.  Results outside a block (error status) go one by one."""
+    tab = np.zeros((k, 8), np.uint64)
+    _check(lib().vor_result_layout(outs, k, tab.ctypes.data_as(C.POINTER(C.c_uint64))),
+           "vor_result_layout")
+    rows = tab.tolist()
+    res = [None] * k
+    cache, groups = {}, {}
+    for i in range(k):
+        o = outs[i]
+        if not o:
+            continue
+        n, m, a_off, a_nbr, a_vtx, a_del, base, size = rows[i]
+        if not base:
+            res[i] = _own_result(o, cache)
+            continue
+        g = groups.get(base)
+        if g is None:
+            owner = _OwnedMany()
+            buf = (C.c_char * size).from_address(base)
+            buf._owner = owner
+            r0 = o.contents   # every result of one run carries the run's counters and times
+            figs = (float(r0.device_ms), int(r0.status), float(r0.cells_ms), float(r0.exact_ms),
+                    float(r0.grid_ms), float(r0.emit_ms), int(r0.graph_replayed),
+                    float(r0.adaptive_ms), float(r0.t_submit), float(r0.t_admit),
+                    float(r0.t_done))
+            g = groups[base] = (owner, buf, _stats(r0.stats, cache), figs)
+        owner, buf, st, figs = g
+        owner.rps.append(o)
+        off = np.frombuffer(buf, np.uint32, n + 1, a_off - base)
+        E = int(off[-1])
+        nbr = np.frombuffer(buf, np.int32, E, a_nbr - base) if E else np.zeros(0, np.int32)
+        vtx = np.frombuffer(buf, _RAT, E, a_vtx - base) if (a_vtx and E) else None
+        dele = (np.frombuffer(buf, np.uint32, 2 * m, a_del - base).reshape(m, 2) if m
+                else np.zeros((0, 2), np.uint32))
+        res[i] = Result(n, off, nbr, vtx, dele, st, *figs)
+    return res
+
+
 def _own_result(rp, stats_cache: dict | None = None) -> Result:
     """Result of a host vor_result whose ownership passes to Python: its arrays view the
     library's memory, freed when the last of them (and the Result) is gone."""
@@ -388,21 +447,31 @@ def vor_compute_batch(ctx, sets):
     keep = []
     for i, t in enumerate(sets):
         x, y, box = t[:3]
-        s, kp = _make_set(x, y, box, region=t[3] if len(t) > 3 else None)
-        arr[i] = s
-        keep.append(kp)
+        if len(t) > 3 and t[3] is not None:
+            s, kp = _make_set(x, y, box, region=t[3])
+            arr[i] = s
+            keep.append(kp)
+            continue
+        # the plain case field by field (no intermediate structure)
+        x = np.ascontiguousarray(x, dtype=np.int32)
+        y = np.ascontiguousarray(y, dtype=np.int32)
+        e = arr[i]
+        e.n = x.shape[0]
+        e.x = x.ctypes.data
+        e.y = y.ctypes.data
+        bx = e.box
+        bx.x0, bx.y0, bx.x1, bx.y1 = (int(v) for v in box)
+        keep.append((x, y))
     outs = (C.POINTER(vor_result) * k)()
     rc = lib().vor_compute_batch(ctx, arr, k, outs)
     if rc < 0 and not any(bool(o) for o in outs):
         raise VorError(rc, "vor_compute_batch")
-    res, cache = [], {}
     # thousands of small objects at once: the cyclic collector's passes over them (none of
     # them is garbage yet) would cost more than the conversion itself
     was = gc.isenabled()
     gc.disable()
     try:
-        for o in outs:
-            res.append(_own_result(o, cache) if o else None)
+        res = _own_batch(outs, k)
     finally:
         if was:
             gc.enable()

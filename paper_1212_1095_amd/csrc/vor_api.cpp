@@ -1136,6 +1136,29 @@ void vor_result_free(vor_result *r) {
     delete reinterpret_cast<ResultBox *>(r);
 }
 
+int vor_result_layout(const vor_result *const *results, uint32_t k, uint64_t *table) {
+    if (!results || !table) return VOR_E_INVAL;
+    for (uint32_t i = 0; i < k; ++i) {
+        uint64_t *t = table + 8ull * i;
+        std::memset(t, 0, 8 * sizeof(uint64_t));
+        const vor_result *r = results[i];
+        if (!r) continue;
+        t[0] = r->n;
+        t[1] = r->m;
+        t[2] = (uint64_t)(uintptr_t)r->cell_off;
+        t[3] = (uint64_t)(uintptr_t)r->nbr;
+        t[4] = (uint64_t)(uintptr_t)r->vtx;
+        t[5] = (uint64_t)(uintptr_t)r->del;
+        // vor_result is the first member of ResultBox
+        const ResultBox *box = reinterpret_cast<const ResultBox *>(r);
+        if (box->block && r->status == VOR_OK) {
+            t[6] = (uint64_t)(uintptr_t)box->block->p;
+            t[7] = box->block->cap;
+        }
+    }
+    return VOR_OK;
+}
+
 int vor_result_to_host(vor_ctx *ctx, const vor_result *dev, vor_result **out) {
     if (!ctx || !dev || !out) return VOR_E_INVAL;
     *out = nullptr;

@@ -84,3 +84,15 @@ def test_autotune_size_table(tmp_path):
         rho, h, ht, path = (e["sites_per_bucket"], e["block_halfwidth"], e["leaf_halfwidth"],
                             e["scan_path"])
         assert (rho, h, ht, path) in autotune.DEFAULT_GRID, "shipped entry outside the sweep grid"
+
+
+def test_result_layout_of_null_results_without_gpu():
+    """vor_result_layout: a NULL result gives a row of zeros; a NULL table is refused."""
+    import numpy as np
+    import paper_1212_1095_amd as vor
+    from paper_1212_1095_amd import _binding as b
+    outs = (ctypes.POINTER(b.vor_result) * 3)()
+    tab = np.full((3, 8), 7, np.uint64)
+    rc = b.lib().vor_result_layout(outs, 3, tab.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)))
+    assert rc == vor.VOR_OK and not tab.any()
+    assert b.lib().vor_result_layout(outs, 3, None) == vor.VOR_E_INVAL
