@@ -59,3 +59,17 @@ def test_scan_gate_is_set_except_for_the_bucket_scan():
     assert len(calls) == 4
     ungated = [c for c in calls if re.search(r",\s*0,\s*st\s*$", c)]
     assert len(ungated) == 1 and "a.bstart" in ungated[0], ungated
+
+
+def test_subwedge_workgroups_have_a_wave_per_corner_ray():
+    """The subwedge passes shoot the projector's three corner rays on waves 0, 1 and 2 of a
+    workgroup in their first round; a workgroup with fewer waves would leave a corner unwritten
+    and follow a garbage successor link in the later rounds."""
+    src = open(SRC).read()
+    assert "if (wave < 3)" in src
+    for name in ("WIDE_WAVES", "WIDE_LWAVES"):
+        m = re.search(r"constexpr int %s = (\d+);" % name, src) or re.search(
+            r"constexpr int %s = (\d+);" % name,
+            open(os.path.join(ROOT, "paper_1212_1095_amd", "csrc", "vor_internal.h")).read())
+        assert m, name
+        assert int(m.group(1)) >= 3, name
