@@ -850,8 +850,11 @@ constexpr int WIDE_LWAVES = 4;      // waves of its workgroups
 constexpr int WIDE_LBLOCKS = 2048;  // its workgroups
 constexpr int ERR_SPILL = 1 << 30;  // a deferred cell with more corners than the LDS lists hold
 
+// Four waves per SIMD: the register budget this asks for (128) costs the deferred-cell pass no
+// spill (the deep pass a few), and a pass over thousands of deferred cells keeps a third more
+// of them in flight than at three.
 template <int MODE, int CAP, int WAVES>
-__global__ __launch_bounds__(64 * WAVES) void k_cells_wide(
+__global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_cells_wide(
     const SetDesc *__restrict__ sets, int nsets, const int *__restrict__ set_off,
     const SideRel *__restrict__ sides,
     const float2 *__restrict__ sxy, const int *__restrict__ sid, const int *__restrict__ bstart,
